@@ -1,0 +1,192 @@
+"""FP64 CPU oracle for randomized Cholesky QR -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke entry and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the HIP product path and never
+imports it.  Every routine follows a passage of Balabanov, "Randomized
+Cholesky QR factorizations":
+
+* ``sketch``            -- Algorithm 2 step 1, P = Theta X (Section 2 embeddings)
+* ``householder_qr``    -- Algorithm 2 step 2, Householder as in Section 6.1
+* ``trsm_rows``         -- Algorithm 2 step 3, row-wise forward substitution
+* ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
+* ``rcholqr``           -- Algorithm 2 (passes=1) / Algorithm 3 (passes=2)
+* ``qr_backward``       -- reverse-mode derivative of the positive-diagonal
+                           thin QR (not in the paper; standard identity)
+
+Parity pins for each routine are in tests/test_oracle_pins.py.  Arrays are
+numpy float64 in Fortran (column-major) order, like the C-ABI of the product.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+GAUSSIAN, RADEMACHER, COUNTSKETCH, IDENTITY = 0, 1, 2, 99
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or (
+                os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        L = ctypes.CDLL(path)
+        i64, u64, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+        dp = ctypes.POINTER(ctypes.c_double)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_ln.argtypes = [ctypes.c_double]
+        L.orc_ln.restype = ctypes.c_double
+        L.orc_sincos2pi_dyadic.argtypes = [u64, dp, dp]
+        L.orc_theta_block.argtypes = [i32, i64, i64, u64, i64, i64, i64, i64, dp]
+        L.orc_countsketch_hash.argtypes = [i64, u64, i64,
+                                           ctypes.POINTER(i64), dp]
+        L.orc_sketch_scale.argtypes = [i32, i64]
+        L.orc_sketch_scale.restype = ctypes.c_double
+        L.orc_sketch.argtypes = [i32, i64, i64, i64, u64, dp, i64, dp, i64]
+        L.orc_householder_qr.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
+        L.orc_householder_qr.restype = i32
+        L.orc_trsm_rows.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
+        L.orc_gram.argtypes = [i64, i64, dp, i64, dp, i64]
+        L.orc_cholesky_upper.argtypes = [i64, dp, i64, dp, i64]
+        L.orc_cholesky_upper.restype = i32
+        L.orc_triu_product.argtypes = [i64, dp, i64, dp, i64, dp, i64]
+        L.orc_rcholqr.argtypes = [i32, i32, i64, i64, i64, u64, dp, i64, dp,
+                                  i64, dp, i64, dp, i64, dp, dp]
+        L.orc_rcholqr.restype = i32
+        L.orc_qr_backward.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, dp,
+                                      i64, dp, i64]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.asarray(a, dtype=np.float64)
+    return np.asfortranarray(a)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def philox4x32_10(counter, key):
+    """One Philox4x32-10 block (Salmon et al. SC'11) -> 4 uint32 words."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xffffffff for x in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(o[i]) for i in range(4)]
+
+
+def ln(x: float) -> float:
+    return lib().orc_ln(float(x))
+
+
+def sincos2pi_dyadic(b: int):
+    """(sin, cos) of 2*pi*b*2^-53 for integer b in [0, 2^53)."""
+    s, c = ctypes.c_double(), ctypes.c_double()
+    lib().orc_sincos2pi_dyadic(int(b), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def theta_block(kind, k, m, seed, i0, ni, j0, nj):
+    """Raw Theta(i0:i0+ni, j0:j0+nj): z for Gaussian, +-1 for Rademacher,
+    s(j) at row h(j) for CountSketch (no 1/sqrt(k) scaling)."""
+    out = np.zeros((ni, nj), dtype=np.float64, order="F")
+    lib().orc_theta_block(kind, k, m, seed, i0, ni, j0, nj, _ptr(out))
+    return out
+
+
+def countsketch_hash(k, seed, j):
+    h, s = ctypes.c_int64(), ctypes.c_double()
+    lib().orc_countsketch_hash(k, seed, j, ctypes.byref(h), ctypes.byref(s))
+    return h.value, s.value
+
+
+def sketch_scale(kind, k):
+    return lib().orc_sketch_scale(kind, k)
+
+
+def sketch(kind, X, k, seed):
+    X = _f64(X)
+    m, n = X.shape
+    P = np.zeros((k, n), dtype=np.float64, order="F")
+    lib().orc_sketch(kind, m, n, k, seed, _ptr(X), max(m, 1), _ptr(P), k)
+    return P
+
+
+def householder_qr(P, want_s=True):
+    P = _f64(P)
+    k, n = P.shape
+    R = np.zeros((n, n), order="F")
+    S = np.zeros((k, n), order="F") if want_s else None
+    st = lib().orc_householder_qr(k, n, _ptr(P), k, _ptr(R), n, _ptr(S), k)
+    return R, S, st
+
+
+def trsm_rows(X, R):
+    X, R = _f64(X), _f64(R)
+    m, n = X.shape
+    Q = np.zeros((m, n), order="F")
+    lib().orc_trsm_rows(m, n, _ptr(X), max(m, 1), _ptr(R), n, _ptr(Q), max(m, 1))
+    return Q
+
+
+def gram(Q):
+    Q = _f64(Q)
+    m, n = Q.shape
+    G = np.zeros((n, n), order="F")
+    lib().orc_gram(m, n, _ptr(Q), max(m, 1), _ptr(G), n)
+    return G
+
+
+def cholesky_upper(G):
+    G = _f64(G)
+    n = G.shape[0]
+    Rp = np.zeros((n, n), order="F")
+    st = lib().orc_cholesky_upper(n, _ptr(G), n, _ptr(Rp), n)
+    return Rp, st
+
+
+def triu_product(A, B):
+    A, B = _f64(A), _f64(B)
+    n = A.shape[0]
+    C = np.zeros((n, n), order="F")
+    lib().orc_triu_product(n, _ptr(A), n, _ptr(B), n, _ptr(C), n)
+    return C
+
+
+def rcholqr(X, k, seed, kind=GAUSSIAN, passes=2, want_s=False):
+    """Algorithm 2 (passes=1) or Algorithm 3 (passes=2).
+
+    Returns dict(Q, R, Rs, Rp, S, status).  FP32 inputs are promoted to
+    FP64 exactly; the oracle always computes in FP64."""
+    X = _f64(X)
+    m, n = X.shape
+    Q = np.zeros((m, n), order="F")
+    R = np.zeros((n, n), order="F")
+    Rs = np.zeros((n, n), order="F")
+    Rp = np.zeros((n, n), order="F")
+    S = np.zeros((k, n), order="F") if want_s else None
+    st = lib().orc_rcholqr(kind, passes, m, n, k, seed, _ptr(X), max(m, 1),
+                           _ptr(Q), max(m, 1), _ptr(R), n, _ptr(S), k,
+                           _ptr(Rs), _ptr(Rp))
+    return dict(Q=Q, R=R, Rs=Rs, Rp=Rp if passes == 2 else None, S=S,
+                status=int(st))
+
+
+def qr_backward(Q, R, dQ, dR):
+    """dX for X = Q R (positive-diagonal thin QR) given dQ, dR."""
+    Q, R, dQ, dR = _f64(Q), _f64(R), _f64(dQ), _f64(dR)
+    m, n = Q.shape
+    dX = np.zeros((m, n), order="F")
+    lib().orc_qr_backward(m, n, _ptr(Q), max(m, 1), _ptr(R), n, _ptr(dQ),
+                          max(m, 1), _ptr(dR), n, _ptr(dX), max(m, 1))
+    return dX

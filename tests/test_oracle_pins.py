@@ -1,0 +1,440 @@
+"""Pins for the FP64 CPU oracle: each routine is checked against something
+other than itself -- an independent library implementation, LAPACK, mpmath,
+exact distributions, closed forms, or the bounds of Theorem 5.2.
+
+Section/equation references are to Balabanov, "Randomized Cholesky QR
+factorizations".
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+import synth
+
+U64 = 2.0 ** -53
+G, RD, CS, ID = 0, 1, 2, 99
+
+
+# ----------------------------------------------------------------- Philox
+PIN_SRC = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+struct Exposed : rocrand_device::philox4x32_10_engine {
+  using rocrand_device::philox4x32_10_engine::ten_rounds;
+};
+int main() {
+  Exposed e;
+  unsigned c[4], k[2];
+  while (scanf("%x %x %x %x %x %x", &c[0], &c[1], &c[2], &c[3], &k[0], &k[1]) == 6) {
+    uint4 r = e.ten_rounds(uint4{c[0], c[1], c[2], c[3]}, uint2{k[0], k[1]});
+    printf("%08x %08x %08x %08x\n", r.x, r.y, r.z, r.w);
+  }
+  return 0;
+}
+"""
+
+
+def test_philox_matches_independent_library(orc, tmp_path):
+    """Philox4x32-10 (Salmon et al. SC'11) against rocRAND's separately
+    written header implementation, compiled as a host program."""
+    hdr = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    if not os.path.exists(hdr) or shutil.which("g++") is None:
+        pytest.skip("rocRAND header or g++ not available")
+    src = tmp_path / "pin.cpp"
+    src.write_text(PIN_SRC)
+    exe = tmp_path / "pin"
+    subprocess.run(["g++", "-O1", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+                    str(src), "-o", str(exe)], check=True)
+    rng = np.random.default_rng(7)
+    cases = [[0] * 6, [0xffffffff] * 6]
+    cases += rng.integers(0, 2 ** 32, size=(3000, 6), dtype=np.uint64).tolist()
+    # structured counters as used by the sketch: (row lo, row hi, block, tag)
+    for j in [0, 1, 2 ** 32 - 1, 2 ** 32, 10 ** 6 - 1]:
+        for blk in [0, 1, 299]:
+            cases.append([j & 0xffffffff, j >> 32, blk, 0x47415553, 1, 0])
+    inp = "\n".join(" ".join("%x" % v for v in c) for c in cases) + "\n"
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        ref = [int(w, 16) for w in line.split()]
+        assert orc.philox4x32_10(c[:4], c[4:]) == ref, c
+
+
+def test_philox_bits_uniform(orc):
+    """Rademacher entries are single Philox bits: chi-square over 2^16
+    counters of the four-bit nibbles, and bit balance."""
+    th = orc.theta_block(RD, 128, 4096, 12345, 0, 128, 0, 4096)
+    bits = (th < 0).astype(np.int64)            # bit 1 -> -1
+    assert abs(bits.mean() - 0.5) < 4 * 0.5 / math.sqrt(bits.size)
+    nib = bits.reshape(-1, 4) @ np.array([1, 2, 4, 8])
+    counts = np.bincount(nib, minlength=16)
+    chi2 = scipy.stats.chisquare(counts).pvalue
+    assert chi2 > 1e-4
+
+
+# -------------------------------------------------------- Gaussian transform
+def test_ln_matches_mpmath(orc):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.prec = 120
+    rng = np.random.default_rng(1)
+    xs = list(rng.random(3000)) + [U64, 2 * U64, 1.0, 0.5, 0.70710678118654757,
+                                  0.7071067811865475, 1.4142135623730951 / 2,
+                                  np.nextafter(1.0, 0), 5e-324, 1e-310, 3.0, 1e300]
+    xs += list(np.exp(-rng.random(2000) * 36.0))
+    worst = 0.0
+    for x in xs:
+        x = float(x)
+        if x <= 0:
+            continue
+        got = orc.ln(x)
+        ref = mp.log(mp.mpf(x))
+        ulp = math.ulp(float(ref)) if float(ref) != 0 else 5e-324
+        err = abs(mp.mpf(got) - ref) / ulp
+        worst = max(worst, float(err))
+    assert worst <= 2.0, worst
+
+
+def test_sincos2pi_matches_mpmath(orc):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.prec = 120
+    rng = np.random.default_rng(2)
+    bs = [0, 1, 2 ** 50, 2 ** 51, 2 ** 52, 3 * 2 ** 51, 2 ** 53 - 1, 2 ** 51 - 1,
+          2 ** 50 - 1, 2 ** 50 + 1]
+    bs += [int(v) for v in rng.integers(0, 2 ** 53, size=3000, dtype=np.int64)]
+    for b in bs:
+        s, c = orc.sincos2pi_dyadic(b)
+        ang = 2 * mp.pi * mp.mpf(b) / mp.mpf(2) ** 53
+        assert abs(mp.mpf(s) - mp.sin(ang)) <= 4 * U64, b
+        assert abs(mp.mpf(c) - mp.cos(ang)) <= 4 * U64, b
+
+
+def test_gaussian_entries_are_standard_normal(orc):
+    """Box-Muller output (Section 2: i.i.d. Gaussian entries) against the
+    exact N(0,1) law: Kolmogorov-Smirnov and the first four moments."""
+    z = orc.theta_block(G, 201, 6000, 99, 0, 201, 0, 6000).ravel()
+    assert z.size == 201 * 6000
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-4
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1) < 5 * math.sqrt(2 / n)
+    assert abs(scipy.stats.skew(z)) < 5 * math.sqrt(6 / n)
+    assert abs(scipy.stats.kurtosis(z)) < 5 * math.sqrt(24 / n)
+    # neighbouring rows (the cos/sin pair of one draw) are uncorrelated
+    t = orc.theta_block(G, 2, 200000, 5, 0, 2, 0, 200000)
+    assert abs(np.corrcoef(t[0], t[1])[0, 1]) < 5 / math.sqrt(200000)
+
+
+def test_gaussian_odd_k_uses_cos_of_last_pair(orc):
+    a = orc.theta_block(G, 7, 50, 3, 0, 7, 0, 50)
+    b = orc.theta_block(G, 8, 50, 3, 0, 8, 0, 50)
+    assert np.array_equal(a, b[:7])  # rows depend on (j, row), never on k
+
+
+def test_countsketch_hash_and_isometry(orc):
+    k = 37
+    h = np.array([orc.countsketch_hash(k, 11, j)[0] for j in range(40000)])
+    s = np.array([orc.countsketch_hash(k, 11, j)[1] for j in range(40000)])
+    assert h.min() >= 0 and h.max() < k
+    assert scipy.stats.chisquare(np.bincount(h, minlength=k)).pvalue > 1e-4
+    assert abs(s.mean()) < 5 / math.sqrt(s.size)
+    th = orc.theta_block(CS, k, 300, 4, 0, k, 0, 300)
+    assert np.all(np.count_nonzero(th, axis=0) == 1)
+    # E ||Theta x||^2 = ||x||^2 over seeds
+    x = np.random.default_rng(0).standard_normal((300, 1))
+    vals = [np.sum((orc.theta_block(CS, k, 300, sd, 0, k, 0, 300) @ x) ** 2)
+            for sd in range(400)]
+    assert abs(np.mean(vals) / np.sum(x ** 2) - 1) < 0.05
+
+
+def test_dense_embeddings_are_isometric_in_mean(orc):
+    """E ||Theta x||^2 = ||x||^2 for the rescaled Gaussian and Rademacher
+    embeddings of Section 2."""
+    x = np.random.default_rng(3).standard_normal((500, 1))
+    for kind in (G, RD):
+        vals = []
+        for sd in range(60):
+            th = orc.theta_block(kind, 64, 500, sd, 0, 64, 0, 500)
+            vals.append(np.sum((orc.sketch_scale(kind, 64) * th @ x) ** 2))
+        assert abs(np.mean(vals) / np.sum(x ** 2) - 1) < 0.06
+
+
+# ---------------------------------------------------------- sketch P = Theta X
+@pytest.mark.parametrize("kind,k", [(G, 31), (G, 32), (RD, 130), (CS, 17)])
+def test_sketch_equals_materialised_product(orc, kind, k):
+    m, n = 700, 9
+    X = np.asfortranarray(np.random.default_rng(4).standard_normal((m, n)))
+    P = orc.sketch(kind, X, k, 77)
+    th = orc.theta_block(kind, k, m, 77, 0, k, 0, m)
+    ref = orc.sketch_scale(kind, k) * (th @ X)
+    bound = 2 * m * U64 * orc.sketch_scale(kind, k) * (np.abs(th) @ np.abs(X))
+    assert np.all(np.abs(P - ref) <= bound + 1e-300)
+
+
+def test_sketch_exact_dot_mpmath(orc):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.prec = 200
+    m, n, k = 300, 3, 6
+    X = np.asfortranarray(np.random.default_rng(5).standard_normal((m, n)))
+    P = orc.sketch(G, X, k, 8)
+    th = orc.theta_block(G, k, m, 8, 0, k, 0, m)
+    sc = mp.mpf(1) / mp.sqrt(k)
+    for i in range(k):
+        for c in range(n):
+            exact = sc * mp.fsum(mp.mpf(th[i, j]) * mp.mpf(X[j, c]) for j in range(m))
+            scale = float(np.abs(th[i]) @ np.abs(X[:, c])) / math.sqrt(k)
+            assert abs(mp.mpf(P[i, c]) - exact) <= 2 * m * U64 * scale
+
+
+def test_identity_sketch_is_copy(orc):
+    X = np.asfortranarray(np.random.default_rng(6).standard_normal((40, 5)))
+    assert np.array_equal(orc.sketch(ID, X, 40, 0), X)
+
+
+# ------------------------------------------------------------ small FP64 QR
+def _lapack_qr_posdiag(A):
+    Qn, Rn = np.linalg.qr(A)
+    d = np.sign(np.diag(Rn))
+    d[d == 0] = 1
+    return Qn * d, d[:, None] * Rn
+
+
+@pytest.mark.parametrize("k,n", [(1, 1), (5, 5), (30, 10), (150, 50), (97, 33)])
+def test_householder_matches_lapack(orc, k, n):
+    P = np.asfortranarray(np.random.default_rng(k * 100 + n).standard_normal((k, n)))
+    R, S, st = orc.householder_qr(P)
+    assert st == 0
+    Sr, Rr = _lapack_qr_posdiag(P)
+    assert np.all(np.diag(R) > 0)
+    assert np.array_equal(np.tril(R, -1), np.zeros_like(R))
+    cond = np.linalg.cond(P)
+    assert np.linalg.norm(R - Rr) <= 50 * n * U64 * cond * np.linalg.norm(Rr)
+    assert np.linalg.norm(S - Sr) <= 50 * n * U64 * cond * math.sqrt(n)
+    # Assumption (eq. ass2): orthonormal S and small P - S R
+    assert np.linalg.norm(S.T @ S - np.eye(n)) <= 10 * k * n * U64
+    assert np.linalg.norm(P - S @ R) <= 10 * k * n * U64 * np.linalg.norm(P)
+
+
+def test_householder_zero_column_flags_rank(orc):
+    P = np.asfortranarray(np.random.default_rng(9).standard_normal((20, 4)))
+    P[:, 2] = 0.0
+    _, _, st = orc.householder_qr(P)
+    assert st == 1
+
+
+# ---------------------------------------------------- forward substitution
+def test_row_substitution_matches_lapack_and_is_backward_stable(orc):
+    rng = np.random.default_rng(10)
+    m, n = 500, 40
+    X = np.asfortranarray(rng.standard_normal((m, n)))
+    _, R = _lapack_qr_posdiag(rng.standard_normal((n + 20, n)) @ np.diag(
+        np.logspace(0, -6, n)))
+    R = np.asfortranarray(R)
+    Q = orc.trsm_rows(X, R)
+    ref = scipy.linalg.solve_triangular(R, X.T, trans="T", lower=False).T
+    cond = np.linalg.cond(R)
+    assert np.linalg.norm(Q - ref) <= 10 * n * U64 * cond * np.linalg.norm(ref)
+    # Higham Thm 8.5 as used in Section 5.1: |x_i - q_i R| <= 1.1 u n |q_i||R|
+    lhs = np.abs(X - Q @ R)
+    rhs = 1.1 * U64 * n * (np.abs(Q) @ np.abs(R))
+    assert np.all(lhs <= rhs + 1e-300)
+
+
+# --------------------------------------------------------- Cholesky, R product
+def test_cholesky_matches_lapack(orc):
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((200, 30))
+    Gm = np.asfortranarray(A.T @ A)
+    Rp, st = orc.cholesky_upper(Gm)
+    assert st == 0
+    Lr = np.linalg.cholesky(Gm)
+    assert np.linalg.norm(Rp - Lr.T) <= 1e-13 * np.linalg.norm(Lr)
+    assert np.array_equal(np.tril(Rp, -1), np.zeros_like(Rp))
+
+
+def test_cholesky_breakdown_reports_column(orc):
+    Gm = np.eye(5)
+    Gm[3, 3] = -1.0
+    _, st = orc.cholesky_upper(np.asfortranarray(Gm))
+    assert st == 1003
+
+
+def test_triu_product_matches_matmul(orc):
+    rng = np.random.default_rng(12)
+    A = np.triu(rng.standard_normal((17, 17)))
+    B = np.triu(rng.standard_normal((17, 17)))
+    C = orc.triu_product(A, B)
+    assert np.allclose(C, A @ B, rtol=0, atol=1e-13)
+    assert np.array_equal(np.tril(C, -1), np.zeros_like(C))
+
+
+def test_gram_matches_matmul(orc):
+    Q = np.asfortranarray(np.random.default_rng(13).standard_normal((3000, 12)))
+    Gm = orc.gram(Q)
+    assert np.allclose(Gm, Q.T @ Q, rtol=0, atol=3000 * U64 * 12 * 4)
+    assert np.array_equal(Gm, Gm.T)
+
+
+# ------------------------------------------------ whole algorithm: special cases
+@pytest.mark.parametrize("kind", [G, RD, CS])
+def test_two_pass_equals_lapack_thin_qr(orc, kind):
+    """Algorithm 3 in exact arithmetic returns the unique positive-diagonal
+    thin QR, whatever Theta is: compare with LAPACK at kappa = 1e3."""
+    m, n = 3000, 20
+    X = synth.make_x(m, n, 1e-3, seed=1)
+    out = orc.rcholqr(X, 3 * n, 5, kind, passes=2)
+    assert out["status"] == 0
+    Qr, Rr = _lapack_qr_posdiag(X)
+    assert np.linalg.norm(out["R"] - Rr) <= 1e-12 * np.linalg.norm(Rr)
+    assert np.linalg.norm(out["Q"] - Qr) <= 1e-12 * np.linalg.norm(Qr)
+
+
+def test_identity_sketch_reduces_to_householder(orc):
+    """Theta = I (k = m): Algorithm 2 is Householder QR of X then Q = X R^-1."""
+    m, n = 400, 12
+    X = synth.make_x(m, n, 1e-4, seed=2)
+    out = orc.rcholqr(X, m, 0, ID, passes=1)
+    assert out["status"] == 0
+    Qr, Rr = _lapack_qr_posdiag(X)
+    assert np.linalg.norm(out["R"] - Rr) <= 1e-13 * np.linalg.norm(Rr)
+    assert np.linalg.norm(out["Q"] - Qr) <= 1e-10
+    assert np.linalg.norm(out["Q"].T @ out["Q"] - np.eye(n), 2) <= 1e-10
+
+
+def test_single_column_closed_forms(orc):
+    rng = np.random.default_rng(14)
+    x = np.asfortranarray(rng.standard_normal((1000, 1)) * 3.0)
+    two = orc.rcholqr(x, 3, 6, G, passes=2)
+    assert abs(two["R"][0, 0] - np.linalg.norm(x)) <= 1e-13 * np.linalg.norm(x)
+    assert np.allclose(two["Q"], x / np.linalg.norm(x), rtol=0, atol=1e-15)
+    one = orc.rcholqr(x, 3, 6, G, passes=1)
+    th = orc.theta_block(G, 3, 1000, 6, 0, 3, 0, 1000) / math.sqrt(3)
+    r = np.linalg.norm(th @ x)
+    assert abs(one["R"][0, 0] - r) <= 1e-13 * r
+    assert np.allclose(one["Q"], x / r, rtol=1e-14, atol=0)
+
+
+def test_orthonormal_input_gives_identity_r(orc):
+    X = synth.make_x(2000, 16, 1.0, seed=3)     # sigma all ones: Q = X, R = I
+    out = orc.rcholqr(X, 48, 1, G, passes=2)
+    assert np.linalg.norm(out["R"] - np.eye(16)) <= 1e-13
+    assert np.linalg.norm(out["Q"] - X) <= 1e-13
+
+
+def test_diagonal_input(orc):
+    d = np.array([3.0, -2.0, 0.5, 7.0])
+    X = np.zeros((50, 4), order="F")
+    X[:4, :4] = np.diag(d)
+    out = orc.rcholqr(X, 12, 2, RD, passes=2)
+    E = np.zeros((50, 4))
+    E[:4, :4] = np.diag(np.sign(d))
+    assert np.allclose(out["Q"], E, atol=1e-14)
+    assert np.allclose(out["R"], np.diag(np.abs(d)), atol=1e-13)
+
+
+def test_singular_values_of_r_are_sigma(orc):
+    """X = U diag(sigma) V^T: R has the same singular values (Weyl)."""
+    X = synth.make_x(5000, 30, 1e-6, seed=4)
+    out = orc.rcholqr(X, 90, 3, G, passes=2)
+    sv = np.linalg.svd(out["R"], compute_uv=False)
+    assert np.all(np.abs(sv - synth.spectrum(30, 1e-6)) <= 1e-13)
+
+
+# ------------------------------------------------- Theorem 5.2 invariants
+def test_theorem_5_2_bounds_config_a(orc):
+    """m=10000, n=50, k=150, sigma down to 1e-8, Gaussian, one pass."""
+    m, n, k = 10000, 50, 150
+    X = synth.make_x(m, n, 1e-8, seed=0)
+    out = orc.rcholqr(X, k, 1, G, passes=1, want_s=True)
+    assert out["status"] == 0
+    Q, R, S = out["Q"], out["R"], out["S"]
+    # eq. main1: ||X_j - (QR)_j|| <= 2.1 u n ||X_j||
+    col = np.linalg.norm(X - Q @ R, axis=0) / np.linalg.norm(X, axis=0)
+    assert col.max() <= 2.1 * U64 * n
+    # eq. main3: ||S - Theta Q||_F <= 6.1 u n^1.5 kappa
+    th = orc.theta_block(G, k, m, 1, 0, k, 0, m) / math.sqrt(k)
+    kappa = np.linalg.cond(X / np.linalg.norm(X, axis=0))
+    assert np.linalg.norm(S - th @ Q) <= 6.1 * U64 * n ** 1.5 * kappa
+    # sketched orthonormality of Q (eq. sketchedcond, up to eq. main3)
+    SQ = th @ Q
+    assert np.linalg.norm(SQ.T @ SQ - np.eye(n), 2) <= 2 * 6.1 * U64 * n ** 1.5 * kappa
+    # Corollary 2.2: cond(Q) = cond(Theta U) for an orthonormal basis U;
+    # for k = 3n it concentrates near (1+sqrt(1/3))/(1-sqrt(1/3)) ~ 3.7
+    assert np.linalg.cond(Q) <= 20
+
+
+@pytest.mark.parametrize("kind", [G, RD, CS])
+def test_two_pass_orthogonality_at_kappa_1e12(orc, kind):
+    m, n = 20000, 40
+    X = synth.make_x(m, n, 1e-12, seed=5)
+    out = orc.rcholqr(X, 3 * n, 9, kind, passes=2)
+    assert out["status"] == 0
+    Q, R = out["Q"], out["R"]
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 1e-12
+    col = np.linalg.norm(X - Q @ R, axis=0) / np.linalg.norm(X, axis=0)
+    assert col.max() <= 1e-13
+
+
+def test_status_codes(orc):
+    X = synth.make_x(500, 6, 1e-2, seed=6)
+    Xz = X.copy()
+    Xz[:, 3] = 0.0
+    assert orc.rcholqr(Xz, 18, 1, G, passes=2)["status"] == 1
+    Xn = X.copy()
+    Xn[7, 2] = np.nan
+    assert orc.rcholqr(Xn, 18, 1, G, passes=2)["status"] == 2
+
+
+# ---------------------------------------------------------------- adjoint
+def _loss(orc, X, dQ, dR, seed):
+    o = orc.rcholqr(X, 3 * X.shape[1], seed, G, passes=2)
+    return float(np.sum(o["Q"] * dQ) + np.sum(o["R"] * dR)), o
+
+
+def test_adjoint_matches_finite_differences(orc):
+    m, n = 2000, 16
+    X = synth.make_x(m, n, 1e-2, seed=7)
+    dQ, dR = synth.make_cotangents(m, n, seed=7)
+    _, o = _loss(orc, X, dQ, dR, 1)
+    dX = orc.qr_backward(o["Q"], o["R"], dQ, dR)
+    E = np.asfortranarray(np.random.default_rng(8).standard_normal((m, n)))
+    h = 1e-5 * np.linalg.norm(X) / np.linalg.norm(E)
+    lp, _ = _loss(orc, X + h * E, dQ, dR, 1)
+    lm, _ = _loss(orc, X - h * E, dQ, dR, 1)
+    fd = (lp - lm) / (2 * h)
+    an = float(np.sum(dX * E))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_adjoint_matches_autograd_of_lapack_qr(orc):
+    torch = pytest.importorskip("torch")
+    m, n = 300, 10
+    X = synth.make_x(m, n, 1e-3, seed=8)
+    dQ, dR = synth.make_cotangents(m, n, seed=9)
+    Xt = torch.tensor(np.ascontiguousarray(X), dtype=torch.float64, requires_grad=True)
+    Qt, Rt = torch.linalg.qr(Xt)
+    d = torch.sign(torch.diagonal(Rt)).detach()
+    Qt, Rt = Qt * d, d[:, None] * Rt
+    loss = (Qt * torch.tensor(dQ)).sum() + (Rt * torch.tensor(dR)).sum()
+    loss.backward()
+    o = orc.rcholqr(X, 3 * n, 2, G, passes=2)
+    dX = orc.qr_backward(o["Q"], o["R"], dQ, dR)
+    ref = Xt.grad.numpy()
+    assert np.linalg.norm(dX - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_adjoint_single_column_closed_form(orc):
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal((200, 1))
+    r = np.linalg.norm(x)
+    q = x / r
+    qb = rng.standard_normal((200, 1))
+    rb = np.array([[1.7]])
+    dX = orc.qr_backward(q, np.array([[r]]), qb, rb)
+    ref = (qb - q * (q.T @ qb)) / r + q * rb[0, 0]
+    assert np.allclose(dX, ref, rtol=0, atol=1e-14)
