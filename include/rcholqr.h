@@ -1,0 +1,145 @@
+/*
+ * rcholqr.h -- C ABI of librcholqr.so, the MI355X (gfx950) randomized
+ * Cholesky QR library.
+ *
+ * The method is Balabanov, "Randomized Cholesky QR factorizations":
+ *   Algorithm 2 (RCholeskyQR, passes = 1):
+ *       P = Theta X;  [S, R] = QR(P);  Q = X R^{-1}
+ *   Algorithm 3 (RCholeskyQR2, passes = 2):
+ *       Algorithm 2, then A = Q^T Q;  R' = chol(A);  R <- R' R;  Q <- Q R'^{-1}
+ * for a tall-and-skinny X (m x n, n << m, Section 1), with Theta a k x m
+ * oblivious subspace embedding (Section 2) that is never stored: its
+ * entries are regenerated on the fly from a counter-based generator
+ * (Philox4x32-10) keyed by the seed, as Section 2 and Algorithm 2 allow
+ * ("provided as a function handle", "seeded random number generator").
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are column-major (Fortran) with a leading dimension >= rows.
+ *   - Unless stated otherwise, pointers are DEVICE pointers on the current
+ *     HIP device; the caller owns all memory.  The library never allocates
+ *     or frees device memory inside these calls: all scratch space is the
+ *     caller's workspace buffer, sized by rcholqr_workspace_bytes().
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls only enqueue work; they do not synchronise.  Numerical outcomes
+ *     are written to a status word inside the workspace and read with
+ *     rcholqr_status() after the stream has been synchronised.
+ *   - R factors have a positive diagonal (R_s after a sign fix of the
+ *     Householder R, R' from Cholesky), so the 2-pass (Q, R) is the unique
+ *     thin QR of a full-rank X.
+ *   - Return value: 0 on success; -i if argument i (1-based) is invalid
+ *     (LAPACK style); RCHOLQR_ERR_HIP if a launch failed.
+ *   - Results are bitwise reproducible run to run (no floating-point
+ *     atomics; every reduction has a fixed order).
+ */
+#ifndef RCHOLQR_H
+#define RCHOLQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sketching embeddings (Section 2): rescaled Gaussian (entries z/sqrt(k),
+ * z ~ N(0,1) by Box-Muller), Rademacher (+-1/sqrt(k)), CountSketch (one
+ * +-1 per column of Theta at a hashed row, no scaling). */
+enum rcholqr_sketch_kind {
+  RCHOLQR_GAUSSIAN = 0,
+  RCHOLQR_RADEMACHER = 1,
+  RCHOLQR_COUNTSKETCH = 2
+};
+
+/* Working precision of the dominant (tall) operations.
+ *   F64:   X, Q FP64; sketch on FP64 matrix cores.
+ *   F32:   X, Q FP32; sketch accumulated in FP64, solves and Gram in FP32.
+ *   MIXED: X, Q FP32; Rademacher sketch on FP16 matrix cores (X split into
+ *          FP16 hi + lo with per-tile power-of-two column scaling, +-1
+ *          exact, FP32 accumulation flushed to FP64), solves and Gram in
+ *          FP32.  Requires RCHOLQR_RADEMACHER.
+ * In every precision the small k x n QR, the Cholesky factorisation and
+ * the R' R_s product run in FP64 on the GPU (Section 5: minor operations
+ * in higher precision). */
+enum rcholqr_precision {
+  RCHOLQR_F64 = 0,
+  RCHOLQR_F32 = 1,
+  RCHOLQR_MIXED = 2
+};
+
+/* Numerical status codes written to the workspace status word. */
+#define RCHOLQR_OK 0
+#define RCHOLQR_SKETCH_RANK 1    /* zero diagonal in the sketch R (X rank deficient or Theta failed to embed) */
+#define RCHOLQR_NONFINITE 2      /* non-finite value in X (seen through the sketch) */
+#define RCHOLQR_CHOL_BREAKDOWN 1000 /* + j: non-positive pivot at column j (0-based) of chol(Q^T Q) */
+
+#define RCHOLQR_ERR_HIP (-1000)
+
+/* Bytes of device workspace rcholqr_factor needs for this problem
+ * (0 if the arguments are invalid). */
+size_t rcholqr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
+                               int passes, int precision);
+
+/* Factor X = Q R by Algorithm 2 (passes = 1) or Algorithm 3 (passes = 2).
+ *
+ *  X      [in]  m x n, ldx >= m; FP64 if precision == F64, else FP32.
+ *               Read only.
+ *  m, n   1 <= n <= 256, n <= m.
+ *  k      sketch rows, n <= k <= 1024 (the configurations use k = 3n).
+ *  seed   Philox key; Theta is a deterministic function of (kind, k, seed).
+ *  Q      [out] m x n, ldq >= m, same dtype as X.  Must not overlap X.
+ *               passes = 1: Q is well conditioned and Theta Q ~ S is
+ *               orthonormal (not Q^T Q = I).  passes = 2: Q^T Q ~ I.
+ *  R      [out] n x n FP64, ldr >= n; upper triangle written, strict lower
+ *               triangle set to zero.  passes = 2: R = R' R_s.
+ *  S      [out, optional] k x n FP64, lds >= k: the orthonormal factor of
+ *               the sketch P = S R_s (Algorithm 2 output); NULL to skip.
+ *  Rs, Rp [out, optional] n x n FP64 (ld = n): the sketch R_s and the
+ *               Cholesky factor R' (passes = 2), as saved for the adjoint;
+ *               NULL to skip.
+ *  ws     [in/out] workspace of at least rcholqr_workspace_bytes() bytes,
+ *               256-byte aligned.  Holds the status word.
+ * Outputs are unspecified when the status word is nonzero. */
+int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+                   uint64_t seed, int sketch_kind, int passes, int precision,
+                   void* Q, int64_t ldq, double* R, int64_t ldr, double* S,
+                   int64_t lds, double* Rs, double* Rp, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Read the status word of a workspace used by a completed call
+ * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.
+ * Returns 0 or RCHOLQR_ERR_HIP. */
+int rcholqr_status(const void* ws, int* info);
+
+/* Stage entry point: the sketch alone, P = Theta X (k x n FP64, ldp >= k),
+ * scaled by 1/sqrt(k) for the dense embeddings (Algorithm 2 step 1).
+ * Same argument rules as rcholqr_factor; ws sized for the same problem. */
+int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+                   uint64_t seed, int sketch_kind, int precision, double* P,
+                   int64_t ldp, void* ws, size_t ws_bytes, void* stream);
+
+/* Test-only export of raw Theta entries (before 1/sqrt(k) scaling):
+ * out[ii + jj*ni] = Theta(i0+ii, j0+jj) for 0 <= ii < ni, 0 <= jj < nj, as
+ * FP64 (Gaussian z, +-1, or the CountSketch column: s(j) at row h(j),
+ * zero elsewhere).  Lets tests compare Theta with the oracle bit for bit.
+ * Requires 0 <= i0, i0+ni <= k, 0 <= j0, ni*nj <= 2^26. */
+int rcholqr_debug_theta(int sketch_kind, int64_t k, uint64_t seed, int64_t i0,
+                        int64_t ni, int64_t j0, int64_t nj, double* out,
+                        void* stream);
+
+/* Test-only: Q = X R^{-1} by the library's tall triangular solve for an
+ * upper triangular FP64 R (n x n, ld = ldr, positive diagonal), in the
+ * working precision of `precision` (F64: FP64 X/Q; F32/MIXED: FP32).
+ * Q may equal X (in place).  ws sized by rcholqr_workspace_bytes(m, n, n,
+ * RCHOLQR_GAUSSIAN, 2, precision). */
+int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx,
+                 const double* R, int64_t ldr, int precision, void* Q,
+                 int64_t ldq, void* ws, size_t ws_bytes, void* stream);
+
+/* Human-readable text for a return code or status value. */
+const char* rcholqr_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCHOLQR_H */

@@ -1,0 +1,22 @@
+"""MI355X-native randomized Cholesky QR (Balabanov, arXiv 2210.09953).
+
+Thin ctypes binding over librcholqr.so (include/rcholqr.h).  Every step of
+the factorisation runs in the library's HIP kernels; this module only
+allocates tensors with PyTorch, passes raw device pointers and the current
+HIP stream, and checks return codes.  If the library is not built the calls
+raise: there is no fallback implementation.
+
+Matrices are column-major: an (m, n) tensor with stride (1, ld), ld >= m.
+"""
+import ctypes
+import os
+
+from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, F64, F32, MIXED,
+                      LibraryMissing, RCholQRError, lib, lib_path,
+                      workspace_bytes, factor, sketch, debug_theta, trsm,
+                      status, error_string, fortran, empty_fortran)
+
+__all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
+           "LibraryMissing", "RCholQRError", "lib", "lib_path",
+           "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
+           "status", "error_string", "fortran", "empty_fortran"]

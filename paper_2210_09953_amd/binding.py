@@ -1,0 +1,190 @@
+"""ctypes marshalling for librcholqr.so.  No arithmetic of the method here."""
+import ctypes
+import os
+
+import torch
+
+GAUSSIAN, RADEMACHER, COUNTSKETCH = 0, 1, 2
+F64, F32, MIXED = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class RCholQRError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: code {code} ({error_string(code)})")
+        self.code = code
+
+
+def lib_path():
+    return os.path.join(_HERE, "librcholqr.so")
+
+
+def lib():
+    """Load librcholqr.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise LibraryMissing(
+            f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(path)
+    i64, u64, i32, sz = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+    vp, dp = ctypes.c_void_p, ctypes.c_void_p
+    L.rcholqr_workspace_bytes.argtypes = [i64, i64, i64, i32, i32, i32]
+    L.rcholqr_workspace_bytes.restype = sz
+    L.rcholqr_factor.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, i32, vp, i64, dp,
+                                 i64, dp, i64, dp, dp, vp, sz, vp]
+    L.rcholqr_factor.restype = i32
+    L.rcholqr_status.argtypes = [vp, ctypes.POINTER(i32)]
+    L.rcholqr_status.restype = i32
+    L.rcholqr_sketch.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, dp, i64, vp, sz, vp]
+    L.rcholqr_sketch.restype = i32
+    L.rcholqr_debug_theta.argtypes = [i32, i64, u64, i64, i64, i64, i64, dp, vp]
+    L.rcholqr_debug_theta.restype = i32
+    L.rcholqr_trsm.argtypes = [vp, i64, i64, i64, dp, i64, i32, vp, i64, vp, sz, vp]
+    L.rcholqr_trsm.restype = i32
+    L.rcholqr_error_string.argtypes = [i32]
+    L.rcholqr_error_string.restype = ctypes.c_char_p
+    _LIB = L
+    return L
+
+
+def error_string(code):
+    try:
+        return lib().rcholqr_error_string(int(code)).decode()
+    except LibraryMissing:
+        return "library not built"
+
+
+def _check(code, what):
+    if code != 0:
+        raise RCholQRError(code, what)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def empty_fortran(m, n, dtype, device="cuda"):
+    return torch.empty_strided((m, n), (1, max(m, 1)), dtype=dtype, device=device)
+
+
+def fortran(t):
+    """Column-major view or copy of a 2-D tensor (stride (1, ld), ld >= m)."""
+    m, n = t.shape
+    if t.stride(0) == 1 and (n <= 1 or t.stride(1) >= m):
+        return t
+    out = empty_fortran(m, n, t.dtype, t.device)
+    out.copy_(t)
+    return out
+
+
+def _ld(t):
+    return max(t.stride(1), t.shape[0], 1) if t.shape[1] > 1 else max(t.shape[0], 1)
+
+
+def _dtype_for(precision):
+    return torch.float64 if precision == F64 else torch.float32
+
+
+def workspace_bytes(m, n, k, kind, passes, precision):
+    return int(lib().rcholqr_workspace_bytes(m, n, k, kind, passes, precision))
+
+
+def _workspace(m, n, k, kind, passes, precision, ws, device):
+    need = workspace_bytes(m, n, k, kind, passes, precision)
+    if need == 0:
+        raise RCholQRError(-1, "invalid problem size")
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    if ws.numel() < need:
+        raise RCholQRError(-19, "workspace too small")
+    return ws
+
+
+def factor(X, k, seed, kind=GAUSSIAN, passes=2, precision=None, want_s=False,
+           want_factors=False, ws=None, Q=None, R=None):
+    """Randomized Cholesky QR of a tall X on the GPU (Algorithms 2 and 3).
+
+    Returns (Q, R) or, with want_s / want_factors, (Q, R, extras) where
+    extras holds S (k x n), Rs and Rp (the sketch R and the Cholesky factor)
+    and the workspace `ws` (its status word is read by status(ws))."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X = fortran(X)
+    m, n = X.shape
+    dt = _dtype_for(precision)
+    if X.dtype != dt:
+        raise TypeError(f"X must be {dt} for precision {precision}")
+    dev = X.device
+    ws = _workspace(m, n, k, kind, passes, precision, ws, dev)
+    if Q is None:
+        Q = empty_fortran(m, n, dt, dev)
+    if R is None:
+        R = empty_fortran(n, n, torch.float64, dev)
+    S = empty_fortran(k, n, torch.float64, dev) if want_s else None
+    Rs = empty_fortran(n, n, torch.float64, dev) if want_factors else None
+    Rp = empty_fortran(n, n, torch.float64, dev) if (want_factors and passes == 2) else None
+    code = lib().rcholqr_factor(_ptr(X), m, n, _ld(X), k, int(seed), kind, passes, precision,
+                                _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(S), k, _ptr(Rs),
+                                _ptr(Rp), _ptr(ws), ws.numel(), _stream())
+    _check(code, "rcholqr_factor")
+    if want_s or want_factors:
+        return Q, R, dict(S=S, Rs=Rs, Rp=Rp, ws=ws)
+    return Q, R
+
+
+def status(ws):
+    """Status word of a workspace after its call finished (synchronises)."""
+    info = ctypes.c_int(0)
+    _check(lib().rcholqr_status(_ptr(ws), ctypes.byref(info)), "rcholqr_status")
+    return int(info.value)
+
+
+def sketch(X, k, seed, kind=GAUSSIAN, precision=None, ws=None):
+    """P = Theta X (k x n FP64, dense kinds scaled by 1/sqrt(k))."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X = fortran(X)
+    m, n = X.shape
+    ws = _workspace(m, n, k, kind, 1, precision, ws, X.device)
+    P = empty_fortran(k, n, torch.float64, X.device)
+    code = lib().rcholqr_sketch(_ptr(X), m, n, _ld(X), k, int(seed), kind, precision, _ptr(P),
+                                k, _ptr(ws), ws.numel(), _stream())
+    _check(code, "rcholqr_sketch")
+    return P
+
+
+def debug_theta(kind, k, seed, i0, ni, j0, nj, device="cuda"):
+    """Raw Theta(i0:i0+ni, j0:j0+nj) as FP64 (test export)."""
+    out = empty_fortran(ni, nj, torch.float64, device)
+    code = lib().rcholqr_debug_theta(kind, k, int(seed), i0, ni, j0, nj, _ptr(out), _stream())
+    _check(code, "rcholqr_debug_theta")
+    return out
+
+
+def trsm(X, R, precision=None, Q=None, ws=None):
+    """Q = X R^{-1} by the library's tall triangular solve (R FP64 upper)."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X = fortran(X)
+    R = fortran(R)
+    m, n = X.shape
+    ws = _workspace(m, n, n, GAUSSIAN, 2, precision, ws, X.device)
+    if Q is None:
+        Q = empty_fortran(m, n, X.dtype, X.device)
+    code = lib().rcholqr_trsm(_ptr(X), m, n, _ld(X), _ptr(R), _ld(R), precision, _ptr(Q),
+                              _ld(Q), _ptr(ws), ws.numel(), _stream())
+    _check(code, "rcholqr_trsm")
+    return Q

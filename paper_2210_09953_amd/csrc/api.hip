@@ -1,0 +1,241 @@
+// api.hip -- the C ABI declared in include/rcholqr.h: argument checks,
+// workspace layout, and the launch sequence of Algorithms 2 and 3.
+//
+// Launch sequence of rcholqr_factor (all on the caller's stream, no host
+// synchronisation, no allocation):
+//   sketch partials -> fixed-order reduction (x 1/sqrt(k))       P = Theta X
+//   blocked Householder on P, sign fix, status word               R_s (, S)
+//   panel packing of R_s, tall solve                              Q1 = X R_s^{-1}
+//   passes = 2: Gram partials of Q1 -> reduction -> Cholesky (status)
+//               -> R = R' R_s -> panel packing of R' -> solve in place
+//                                                                 Q = Q1 R'^{-1}
+#include <math.h>
+#include <string.h>
+
+#include "../../include/rcholqr.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace rcq;
+
+namespace {
+
+struct Layout {
+  SketchPlan sp;
+  GramPlan gp;
+  size_t status, part, keys, P, v0, beta, T, Rs, pan, gpart, G, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+bool valid_dims(int64_t m, int64_t n, int64_t k) {
+  return n >= 1 && n <= kMaxN && m >= n && k >= n && k <= kMaxK;
+}
+
+Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int prec) {
+  Layout L{};
+  SketchPlan& sp = L.sp;
+  sp.npad = static_cast<int>(round_up(n, 16));
+  if (kind == kCountSketch) {
+    const int panels = static_cast<int>(ceil_div(n, 8));
+    const int64_t ntile = ceil_div(m, 256);
+    int64_t ns = ceil_div(1024, panels);
+    if (ns > ntile) ns = ntile;
+    if (ns < 1) ns = 1;
+    sp.rows_per_split = round_up(ceil_div(m, ns), 256);
+    sp.nsplit = static_cast<int>(ceil_div(m, sp.rows_per_split));
+    sp.ktiles = 0;
+    sp.kpad = static_cast<int>(round_up(k, 16));
+  } else {
+    sp.ktiles = static_cast<int>(ceil_div(k, 64));
+    sp.kpad = 64 * sp.ktiles;
+    int64_t ns = ceil_div(1024, sp.ktiles);
+    const int64_t maxs = ceil_div(m, 16);
+    if (ns > maxs) ns = maxs;
+    ns = round_up(ns < 8 ? 8 : ns, 8);
+    sp.rows_per_split = round_up(ceil_div(m, ns), 16);
+    sp.nsplit = static_cast<int>(ns);
+  }
+  GramPlan& gp = L.gp;
+  gp.nbb = static_cast<int>(ceil_div(n, 64));
+  gp.npg = 64 * gp.nbb;
+  int64_t gs = ceil_div(m, 16);
+  if (gs > 256) gs = 256;
+  gp.rows_per_split = round_up(ceil_div(m, gs), 16);
+  gp.nsplit = static_cast<int>(ceil_div(m, gp.rows_per_split));
+
+  const size_t esz = (prec == kPrecF64) ? sizeof(double) : sizeof(float);
+  size_t off = 0;
+  L.status = off; off += 256;
+  L.part = off; off += align256(static_cast<size_t>(sp.nsplit) * sp.kpad * sp.npad * sizeof(double));
+  L.keys = off;
+  if (kind == kCountSketch) off += align256(static_cast<size_t>(round_up(m, 256)) * sizeof(uint32_t));
+  L.P = off; off += align256(static_cast<size_t>(k) * n * sizeof(double));
+  L.v0 = off; off += align256(static_cast<size_t>(n) * sizeof(double));
+  L.beta = off; off += align256(static_cast<size_t>(n) * sizeof(double));
+  L.T = off; off += align256(static_cast<size_t>(ceil_div(n, kHhPanel)) * kHhPanel * kHhPanel * sizeof(double));
+  L.Rs = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
+  L.pan = off; off += align256(static_cast<size_t>(panel_elems(static_cast<int>(n))) * esz);
+  L.gpart = off;
+  if (passes == 2) off += align256(static_cast<size_t>(gp.nsplit) * gp.npg * gp.npg * sizeof(double));
+  L.G = off; off += align256(static_cast<size_t>(gp.npg) * gp.npg * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+#define RCQ_TRY(expr)                              \
+  do {                                             \
+    if ((expr) != hipSuccess) return RCHOLQR_ERR_HIP; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+size_t rcholqr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind, int passes,
+                               int precision) {
+  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 2 || passes < 1 || passes > 2 ||
+      precision < 0 || precision > 2)
+    return 0;
+  return make_layout(m, n, k, sketch_kind, passes, precision).total;
+}
+
+int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
+                   int sketch_kind, int passes, int precision, void* Q, int64_t ldq, double* R,
+                   int64_t ldr, double* S, int64_t lds, double* Rs, double* Rp, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (k < n || k > kMaxK) return -5;
+  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (passes < 1 || passes > 2) return -8;
+  if (precision < 0 || precision > 2) return -9;
+  if (precision == kPrecMixed) return -9;
+  if (!Q) return -10;
+  if (ldq < m) return -11;
+  if (!R) return -12;
+  if (ldr < n) return -13;
+  if (S && lds < k) return -15;
+  if (!ws) return -18;
+  const Layout L = make_layout(m, n, k, sketch_kind, passes, precision);
+  if (ws_bytes < L.total) return -19;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f32 = precision != kPrecF64;
+  const int ni = static_cast<int>(n), ki = static_cast<int>(k);
+  int* status = at<int>(ws, L.status);
+  double* P = at<double>(ws, L.P);
+  double* Rsw = at<double>(ws, L.Rs);
+  void* pan = at<void>(ws, L.pan);
+
+  if (precision == kPrecMixed)
+    RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
+                                at<double>(ws, L.part), P, k, st));
+  else
+    RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
+                          at<uint32_t>(ws, L.keys), P, k, st));
+  RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
+                             at<double>(ws, L.T), S, lds, Rsw, passes == 1 ? R : nullptr, ldr,
+                             status, st));
+  if (Rs) RCQ_TRY(launch_copy_upper(Rsw, n, Rs, n, ni, st));
+  RCQ_TRY(launch_make_panels(Rsw, n, ni, f32, pan, st));
+  RCQ_TRY(launch_trsm(X, f32, m, ni, ldx, pan, Q, ldq, st));
+  if (passes == 1) return 0;
+
+  double* G = at<double>(ws, L.G);
+  RCQ_TRY(launch_gram(Q, f32, m, ni, ldq, L.gp, at<double>(ws, L.gpart), st));
+  RCQ_TRY(launch_gram_reduce(at<double>(ws, L.gpart), L.gp, ni, G, st));
+  RCQ_TRY(launch_cholesky(G, ni, L.gp.npg, status, st));
+  RCQ_TRY(launch_triu_product(G, L.gp.npg, Rsw, n, R, ldr, ni, st));
+  if (Rp) RCQ_TRY(launch_copy_upper(G, L.gp.npg, Rp, n, ni, st));
+  RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, f32, pan, st));
+  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  return 0;
+}
+
+int rcholqr_status(const void* ws, int* info) {
+  if (!ws || !info) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
+  if (hipMemcpy(info, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return RCHOLQR_ERR_HIP;
+  return 0;
+}
+
+int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
+                   int sketch_kind, int precision, double* P, int64_t ldp, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (k < n || k > kMaxK) return -5;
+  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (precision < 0 || precision > 2) return -8;
+  if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
+  if (!P) return -9;
+  if (ldp < k) return -10;
+  if (!ws) return -11;
+  const Layout L = make_layout(m, n, k, sketch_kind, 1, precision);
+  if (ws_bytes < L.total) return -12;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (precision == kPrecMixed)
+    RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, static_cast<int>(n), ldx,
+                                static_cast<int>(k), seed, L.sp, at<double>(ws, L.part), P, ldp, st));
+  else
+    RCQ_TRY(launch_sketch(X, precision != kPrecF64, m, static_cast<int>(n), ldx, static_cast<int>(k),
+                          sketch_kind, seed, L.sp, at<double>(ws, L.part), at<uint32_t>(ws, L.keys),
+                          P, ldp, st));
+  return 0;
+}
+
+int rcholqr_debug_theta(int sketch_kind, int64_t k, uint64_t seed, int64_t i0, int64_t ni,
+                        int64_t j0, int64_t nj, double* out, void* stream) {
+  if (sketch_kind < 0 || sketch_kind > 2) return -1;
+  if (k < 1 || k > kMaxK) return -2;
+  if (i0 < 0 || ni < 0 || i0 + ni > k) return -4;
+  if (j0 < 0 || nj < 0) return -7;
+  if (ni * nj > (int64_t(1) << 26)) return -6;
+  if (!out && ni * nj > 0) return -8;
+  RCQ_TRY(launch_theta_debug(sketch_kind, static_cast<int>(k), seed, i0, ni, j0, nj, out,
+                             static_cast<hipStream_t>(stream)));
+  return 0;
+}
+
+int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx, const double* R, int64_t ldr,
+                 int precision, void* Q, int64_t ldq, void* ws, size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (!R) return -5;
+  if (ldr < n) return -6;
+  if (precision < 0 || precision > 2) return -7;
+  if (!Q) return -8;
+  if (ldq < m) return -9;
+  if (!ws) return -10;
+  const Layout L = make_layout(m, n, n, kGaussian, 2, precision);
+  if (ws_bytes < L.total) return -11;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f32 = precision != kPrecF64;
+  void* pan = at<void>(ws, L.pan);
+  RCQ_TRY(launch_make_panels(R, ldr, static_cast<int>(n), f32, pan, st));
+  RCQ_TRY(launch_trsm(X, f32, m, static_cast<int>(n), ldx, pan, Q, ldq, st));
+  return 0;
+}
+
+const char* rcholqr_error_string(int code) {
+  if (code == 0) return "success";
+  if (code == RCHOLQR_ERR_HIP) return "HIP launch or runtime error";
+  if (code < 0) return "invalid argument (the -code-th argument, 1-based)";
+  if (code == RCHOLQR_SKETCH_RANK) return "zero diagonal in the sketch R (rank-deficient X or failed embedding)";
+  if (code == RCHOLQR_NONFINITE) return "non-finite value in X";
+  if (code >= RCHOLQR_CHOL_BREAKDOWN) return "Cholesky breakdown of Q^T Q (status - 1000 = column)";
+  return "unknown code";
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// common.h -- shared device helpers for the gfx950 kernels (wave64, MFMA).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+// 16x16x4 matrix-core products.  Operand layouts (lane l, l16 = l % 16,
+// lg = l / 16):  A(16x4): A[l16][lg];  B(4x16): B[lg][l16];
+// D(16x16): element v holds D[drow(lg, v)][l16], where the row index is
+// lg + 4 v for the FP64 product and 4 lg + v for the FP32 one (measured on
+// gfx950 with a one-hot probe).
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ constexpr int drow(int lg, int v) {
+  return sizeof(T) == 8 ? lg + 4 * v : 4 * lg + v;
+}
+// A-operand row that makes D element v of lane group lg hold row 4 lg + v.
+template <typename T>
+__device__ __forceinline__ constexpr int arow_for_blocked_d(int l16) {
+  return sizeof(T) == 8 ? 4 * (l16 & 3) + (l16 >> 2) : l16;
+}
+
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> {
+  typedef d4 type;
+};
+template <>
+struct Acc4<float> {
+  typedef f4 type;
+};
+
+// Sum over the 64 lanes of a wave (fixed butterfly order: deterministic).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over a block; every thread gets the result.  `red` must hold at least
+// blockDim.x / 64 values.  Contains two barriers.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  T s = T(0);
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// Orders LDS traffic among the lanes of one wave (lanes run in lockstep;
+// the fences keep the compiler and the memory model from reordering).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Status word: the first nonzero code written wins.
+__device__ __forceinline__ void set_status(int* status, int code) {
+  atomicCAS(status, 0, code);
+}
+
+__host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+}  // namespace rcq

@@ -1,0 +1,72 @@
+// kernels.h -- internal launch interface between the C-ABI driver and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcq {
+
+constexpr int kGaussian = 0;
+constexpr int kRademacher = 1;
+constexpr int kCountSketch = 2;
+
+constexpr int kPrecF64 = 0;
+constexpr int kPrecF32 = 1;
+constexpr int kPrecMixed = 2;
+
+constexpr int kMaxN = 256;
+constexpr int kMaxK = 1024;
+constexpr int kHhPanel = 16;  // Householder panel width
+
+// Split-K plan of the sketch.
+struct SketchPlan {
+  int nsplit;              // row ranges (multiple of 8 for the dense kernels)
+  int ktiles;              // 64-row tiles of Theta (dense kernels)
+  int kpad;                // padded k of the partials
+  int npad;                // padded n of the partials
+  int64_t rows_per_split;  // rows of X per range
+};
+
+struct GramPlan {
+  int nsplit;
+  int nbb;                 // 64-column blocks
+  int npg;                 // 64 * nbb
+  int64_t rows_per_split;
+};
+
+// sketch.hip
+hipError_t launch_theta_debug(int kind, int k, uint64_t seed, int64_t i0, int64_t ni, int64_t j0,
+                              int64_t nj, double* out, hipStream_t st);
+hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
+                         int kind, uint64_t seed, const SketchPlan& pl, double* part,
+                         uint32_t* keys, double* P, int64_t ldp, hipStream_t st);
+hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
+                               const SketchPlan& pl, double* part, double* P, int64_t ldp,
+                               hipStream_t st);
+
+// small.hip
+hipError_t launch_householder(double* A, int k, int n, double* V, double* beta, double* T,
+                              double* S, int64_t lds, double* Rs, double* R, int64_t ldr,
+                              int* status, hipStream_t st);
+hipError_t launch_cholesky(double* G, int n, int ldg, int* status, hipStream_t st);
+hipError_t launch_triu_product(const double* A, int64_t lda, const double* B, int64_t ldb,
+                               double* C, int64_t ldc, int n, hipStream_t st);
+hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ldb, int n,
+                             hipStream_t st);
+hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
+                              hipStream_t st);
+hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, double* G,
+                              hipStream_t st);
+
+// tall.hip
+hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
+                       void* Q, int64_t ldq, hipStream_t st);
+hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq,
+                       const GramPlan& gp, double* gpart, hipStream_t st);
+
+inline int64_t panel_elems(int n) {
+  const int64_t nb = (n + 15) / 16;
+  return 256 * nb * (nb + 1) / 2;
+}
+
+}  // namespace rcq

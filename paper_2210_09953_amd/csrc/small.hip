@@ -1,0 +1,444 @@
+// small.hip -- the FP64 small-matrix steps (Section 5: minor operations in
+// higher precision), all on the GPU:
+//   * Householder QR of the k x n sketch P (Algorithm 2 step 2; Householder
+//     is the choice of the numerical experiments, Section 6.1), blocked in
+//     16-column panels with the compact WY form H_1..H_16 = I - V T V^T:
+//     one workgroup factors a panel in LDS, then one workgroup per
+//     16-column block of the trailing matrix applies (I - V T^T V^T) on
+//     matrix cores.  The sign fix D = sign(diag R) gives R_s = D R with a
+//     positive diagonal; S = (H_1 ... H_n)[I; 0] D on request.
+//   * Cholesky of the n x n Gram, upper factor A = R'^T R' (Algorithm 3
+//     step 3), blocked right-looking in 32-column panels, one workgroup.
+//   * R = R' R_s, panel packing of R for the tall solve, Gram reduction.
+#include "common.h"
+#include "kernels.h"
+
+namespace rcq {
+
+// ----------------------------------------------------------------------------
+// Householder panel.  A (k x n, ld k) holds the matrix being factored; on
+// exit columns p0..p0+15 hold R above the diagonal (diagonal = alpha) and
+// the tail of each reflector v below it; v's leading entry goes to v0[],
+// 2/(v^T v) to beta[], and the panel's 16 x 16 T to Tp.
+__global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, int k, int n,
+                                                        int p0, double* __restrict__ v0g,
+                                                        double* __restrict__ betag,
+                                                        double* __restrict__ Tp) {
+  extern __shared__ double pan[];  // [16][L], column-major
+  __shared__ double sc[3];
+  __shared__ double v0s[kHhPanel], bs[kHhPanel];
+  __shared__ double y[kHhPanel][kHhPanel];
+  const int L = k - p0;
+  const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  for (int idx = tid; idx < kHhPanel * L; idx += blockDim.x) {
+    const int c = idx / L, i = idx % L;
+    pan[idx] = (c < nbp) ? A[(p0 + i) + static_cast<int64_t>(p0 + c) * k] : 0.0;
+  }
+  __syncthreads();
+
+  for (int j = 0; j < nbp; ++j) {
+    const double* vj = pan + j * L;
+    if (wave == 0) {
+      double t = 0.0;
+      for (int i = j + 1 + lane; i < L; i += 64) t += vj[i] * vj[i];
+      t = wave_sum(t);
+      if (lane == 0) {
+        const double x0 = vj[j];
+        const double nrm = sqrt(x0 * x0 + t);
+        const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vtv = v0 * v0 + t;
+        sc[0] = alpha;
+        sc[1] = v0;
+        sc[2] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+      }
+    }
+    __syncthreads();
+    const double alpha = sc[0], v0 = sc[1], beta = sc[2];
+    if (wave > j && wave < nbp) {
+      double* pc = pan + wave * L;
+      double w = (lane == 0) ? v0 * pc[j] : 0.0;
+      for (int i = j + 1 + lane; i < L; i += 64) w += vj[i] * pc[i];
+      w = wave_sum(w);
+      const double f = beta * w;
+      if (lane == 0) pc[j] -= f * v0;
+      for (int i = j + 1 + lane; i < L; i += 64) pc[i] -= f * vj[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      pan[j * L + j] = alpha;
+      v0s[j] = v0;
+      bs[j] = beta;
+    }
+    __syncthreads();
+  }
+  // y[a][b] = v_a^T v_b for a < b (v_b is zero above row b).
+  for (int pr = wave; pr < kHhPanel * kHhPanel; pr += 16) {
+    const int a = pr / kHhPanel, b = pr % kHhPanel;
+    if (a >= b || b >= nbp) continue;
+    const double* va = pan + a * L;
+    const double* vb = pan + b * L;
+    double s = (lane == 0) ? va[b] * v0s[b] : 0.0;
+    for (int i = b + 1 + lane; i < L; i += 64) s += va[i] * vb[i];
+    s = wave_sum(s);
+    if (lane == 0) y[a][b] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // T upper: T[j][j] = beta_j, T[0:j, j] = -beta_j T[0:j, 0:j] (V_{0:j}^T v_j).
+    double T[kHhPanel][kHhPanel];
+    for (int a = 0; a < kHhPanel; ++a)
+      for (int b = 0; b < kHhPanel; ++b) T[a][b] = 0.0;
+    for (int j = 0; j < nbp; ++j) {
+      for (int a = 0; a < j; ++a) {
+        double s = 0.0;
+        for (int l = a; l < j; ++l) s += T[a][l] * y[l][j];
+        T[a][j] = -bs[j] * s;
+      }
+      T[j][j] = bs[j];
+    }
+    for (int a = 0; a < kHhPanel; ++a)
+      for (int b = 0; b < kHhPanel; ++b) Tp[a + kHhPanel * b] = T[a][b];
+  }
+  if (tid < nbp) {
+    v0g[p0 + tid] = v0s[tid];
+    betag[p0 + tid] = bs[tid];
+  }
+  for (int idx = tid; idx < nbp * L; idx += blockDim.x) {
+    const int c = idx / L, i = idx % L;
+    A[(p0 + i) + static_cast<int64_t>(p0 + c) * k] = pan[idx];
+  }
+}
+
+// Reflector entry V(row, col) of panel columns (row, col relative to A).
+__device__ __forceinline__ double vref(const double* A, int k, int n, const double* v0g, int row,
+                                       int col) {
+  if (col >= n) return 0.0;
+  return (row == col) ? v0g[col] : ((row > col) ? A[row + static_cast<int64_t>(col) * k] : 0.0);
+}
+
+// M(p0:k, c_begin + 16 blockIdx.x + 0..15) <- (I - V T' V^T) M(...) with
+// T' = T^T (trans = 1, factorisation) or T (trans = 0, forming S).
+__global__ __launch_bounds__(256) void hh_update_kernel(const double* __restrict__ A, int k,
+                                                        int n, int p0, const double* __restrict__ v0g,
+                                                        const double* __restrict__ Tp, int trans,
+                                                        double* __restrict__ M, int64_t ldm,
+                                                        int c_begin, int c_end) {
+  __shared__ double wpart[4][kHhPanel][kHhPanel + 1];
+  __shared__ double ys[kHhPanel][kHhPanel + 1];
+  const int cb = c_begin + kHhPanel * blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int L = k - p0;
+  const int nsteps = (L + 3) / 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s = wave; s < nsteps; s += 4) {
+    const int row = p0 + 4 * s + lg;
+    double a = 0.0, b = 0.0;
+    if (row < k) {
+      a = vref(A, k, n, v0g, row, p0 + l16);
+      if (cb + l16 < c_end) b = M[row + static_cast<int64_t>(cb + l16) * ldm];
+    }
+    acc = mfma16x16x4(a, b, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) wpart[wave][drow<double>(lg, v)][l16] = acc[v];
+  __syncthreads();
+  {
+    const int i = tid / 16, c = tid % 16;
+    const double w = ((wpart[0][i][c] + wpart[1][i][c]) + wpart[2][i][c]) + wpart[3][i][c];
+    wpart[0][i][c] = w;
+  }
+  __syncthreads();
+  {
+    const int i = tid / 16, c = tid % 16;
+    double s = 0.0;
+    for (int l = 0; l < kHhPanel; ++l) {
+      const double t = trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l];
+      s += t * wpart[0][l][c];
+    }
+    ys[i][c] = s;
+  }
+  __syncthreads();
+  const int c = tid % 16;
+  if (cb + c >= c_end) return;
+  for (int r = tid / 16; r < L; r += 16) {
+    const int row = p0 + r;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kHhPanel; ++i) s += vref(A, k, n, v0g, row, p0 + i) * ys[i][c];
+    M[row + static_cast<int64_t>(cb + c) * ldm] -= s;
+  }
+}
+
+__global__ void set_identity_kernel(double* S, int64_t lds, int k, int n) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(k) * n) return;
+  const int i = static_cast<int>(idx % k), c = static_cast<int>(idx / k);
+  S[i + c * lds] = (i == c) ? 1.0 : 0.0;
+}
+
+// Sign fix and status.  Rs (n x n, ld n) = D triu(A); R (optional, ld ldr)
+// gets the same; S columns (optional) scaled by D.  Writes the status word:
+// 2 if any R entry is not finite (non-finite input), 1 if a diagonal is 0.
+__global__ __launch_bounds__(256) void hh_finalize_kernel(const double* __restrict__ A, int k,
+                                                          int n, double* __restrict__ Rs,
+                                                          double* __restrict__ R, int64_t ldr,
+                                                          double* __restrict__ S, int64_t lds,
+                                                          int* __restrict__ status) {
+  __shared__ int bad_nonfinite, bad_rank;
+  if (threadIdx.x == 0) {
+    bad_nonfinite = 0;
+    bad_rank = 0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int r = idx % n, c = idx / n;
+    double v = 0.0;
+    if (r <= c) {
+      const double d = (A[r + static_cast<int64_t>(r) * k] < 0.0) ? -1.0 : 1.0;
+      v = d * A[r + static_cast<int64_t>(c) * k];
+      if (!isfinite(v)) atomicOr(&bad_nonfinite, 1);
+      if (r == c && !(v > 0.0)) atomicOr(&bad_rank, 1);
+    }
+    Rs[r + c * n] = v;
+    if (R) R[r + c * ldr] = v;
+  }
+  if (S) {
+    for (int64_t idx = threadIdx.x; idx < static_cast<int64_t>(k) * n; idx += blockDim.x) {
+      const int i = static_cast<int>(idx % k), c = static_cast<int>(idx / k);
+      const double d = (A[c + static_cast<int64_t>(c) * k] < 0.0) ? -1.0 : 1.0;
+      S[i + c * lds] *= d;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *status = bad_nonfinite ? 2 : (bad_rank ? 1 : 0);
+}
+
+hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta, double* T,
+                              double* S, int64_t lds, double* Rs, double* R, int64_t ldr,
+                              int* status, hipStream_t st) {
+  hipError_t e;
+  const size_t shm = static_cast<size_t>(kHhPanel) * k * sizeof(double);
+  static bool attr_done = false;
+  if (!attr_done) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(hh_panel_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(kHhPanel * kMaxK * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  const int npan = static_cast<int>(ceil_div(n, kHhPanel));
+  for (int p = 0; p < npan; ++p) {
+    const int p0 = p * kHhPanel;
+    hh_panel_kernel<<<1, 1024, shm, st>>>(A, k, n, p0, V0, beta, T + p * kHhPanel * kHhPanel);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int cstart = p0 + kHhPanel;
+    if (cstart < n) {
+      const int nblk = static_cast<int>(ceil_div(n - cstart, kHhPanel));
+      hh_update_kernel<<<nblk, 256, 0, st>>>(A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k,
+                                             cstart, n);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (S) {
+    const int64_t tot = static_cast<int64_t>(k) * n;
+    set_identity_kernel<<<static_cast<unsigned>(ceil_div(tot, 256)), 256, 0, st>>>(S, lds, k, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int p = npan - 1; p >= 0; --p) {
+      const int p0 = p * kHhPanel;
+      const int nblk = static_cast<int>(ceil_div(n - p0, kHhPanel));
+      hh_update_kernel<<<nblk, 256, 0, st>>>(A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds,
+                                             p0, n);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hh_finalize_kernel<<<1, 256, 0, st>>>(A, k, n, Rs, R, ldr, S, lds, status);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Cholesky, upper, in place on G (ld ldg); only the upper triangle is read
+// and written.  Status 1000 + j at the first pivot that is not positive and
+// finite (only if the status word is still 0).
+constexpr int kChB = 32;
+
+__global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int n, int ldg,
+                                                    int* __restrict__ status) {
+  __shared__ double dg[kChB][kChB + 1];
+  __shared__ double rp[kChB][kMaxN + 1];
+  __shared__ int fail;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) fail = 0;
+  for (int c0 = 0; c0 < n; c0 += kChB) {
+    const int w = (n - c0 < kChB) ? n - c0 : kChB;
+    for (int idx = tid; idx < kChB * kChB; idx += blockDim.x) {
+      const int i = idx % kChB, c = idx / kChB;
+      double v;
+      if (i < w && c < w)
+        v = (i <= c) ? G[(c0 + i) + static_cast<int64_t>(c0 + c) * ldg] : 0.0;
+      else
+        v = (i == c) ? 1.0 : 0.0;
+      dg[i][c] = v;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int j = 0; j < w; ++j) {
+        if (lane == j) {
+          const double d = dg[j][j];
+          const bool ok = (d > 0.0) && isfinite(d);
+          dg[j][j] = ok ? sqrt(d) : 0.0;
+          if (!ok && fail == 0) fail = c0 + j + 1;
+        }
+        wave_sync();
+        const double r = dg[j][j];
+        if (lane > j && lane < w) {
+          const double t = dg[j][lane] / r;
+          dg[j][lane] = t;
+        }
+        wave_sync();
+        if (lane > j && lane < w) {
+          const double t = dg[j][lane];
+          for (int i = j + 1; i <= lane; ++i) dg[i][lane] -= dg[j][i] * t;
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    if (fail) break;
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      const int i = idx % w, c = idx / w;
+      if (i <= c) G[(c0 + i) + static_cast<int64_t>(c0 + c) * ldg] = dg[i][c];
+    }
+    const int nt = n - c0 - w;
+    if (tid < nt) {
+      const int c = c0 + w + tid;
+      double x[kChB];
+#pragma unroll
+      for (int i = 0; i < kChB; ++i) x[i] = (i < w) ? G[(c0 + i) + static_cast<int64_t>(c) * ldg] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kChB; ++i) {
+        double s = x[i];
+#pragma unroll
+        for (int l = 0; l < i; ++l) s -= dg[l][i] * x[l];
+        x[i] = s / dg[i][i];
+      }
+#pragma unroll
+      for (int i = 0; i < kChB; ++i) {
+        if (i < w) G[(c0 + i) + static_cast<int64_t>(c) * ldg] = x[i];
+        rp[i][tid] = x[i];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nt * nt; idx += blockDim.x) {
+      const int i = idx % nt, c = idx / nt;
+      if (i > c) continue;
+      double s = 0.0;
+      for (int l = 0; l < w; ++l) s += rp[l][i] * rp[l][c];
+      G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] -= s;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0 && fail) atomicCAS(status, 0, 1000 + fail - 1);
+}
+
+hipError_t launch_cholesky(double* G, int n, int ldg, int* status, hipStream_t st) {
+  chol_kernel<<<1, 1024, 0, st>>>(G, n, ldg, status);
+  return hipGetLastError();
+}
+
+// C = A B for upper triangular A, B (strict lower part of C set to 0).
+__global__ void triu_product_kernel(const double* __restrict__ A, int64_t lda,
+                                    const double* __restrict__ B, int64_t ldb,
+                                    double* __restrict__ C, int64_t ldc, int n) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int r = idx % n, c = idx / n;
+  double s = 0.0;
+  for (int l = r; l <= c; ++l) s += A[r + l * lda] * B[l + c * ldb];
+  C[r + c * ldc] = (r <= c) ? s : 0.0;
+}
+
+hipError_t launch_triu_product(const double* A, int64_t lda, const double* B, int64_t ldb,
+                               double* C, int64_t ldc, int n, hipStream_t st) {
+  triu_product_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(A, lda, B, ldb,
+                                                                                    C, ldc, n);
+  return hipGetLastError();
+}
+
+__global__ void copy_upper_kernel(const double* __restrict__ A, int64_t lda, double* __restrict__ B,
+                                  int64_t ldb, int n) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int r = idx % n, c = idx / n;
+  B[r + c * ldb] = (r <= c) ? A[r + c * lda] : 0.0;
+}
+
+hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ldb, int n,
+                             hipStream_t st) {
+  copy_upper_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(A, lda, B, ldb, n);
+  return hipGetLastError();
+}
+
+// Panel packing for the tall solve.  Panel b (16 columns 16b..16b+15)
+// holds rows 0..16b+15 row-major (16 entries per row): -R(r, 16b+c) above
+// the diagonal block (the matrix-core update subtracts), R itself in the
+// diagonal block.  Columns past n are padded with the identity.
+template <typename T>
+__global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, int n,
+                                   T* __restrict__ pan, int64_t total) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  // locate panel b: offset(b) = 256 b (b+1) / 2
+  int b = 0;
+  while (256ll * (b + 1) * (b + 2) / 2 <= idx) ++b;
+  const int64_t off = idx - 256ll * b * (b + 1) / 2;
+  const int r = static_cast<int>(off / 16), c = static_cast<int>(off % 16);
+  const int col = 16 * b + c;
+  double v;
+  if (r < 16 * b) {
+    v = (col < n && r < n) ? -R[r + col * ldr] : 0.0;
+  } else {
+    if (col < n && r < n)
+      v = (r <= col) ? R[r + col * ldr] : 0.0;
+    else
+      v = (r == col) ? 1.0 : 0.0;
+  }
+  pan[idx] = static_cast<T>(v);
+}
+
+hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
+                              hipStream_t st) {
+  const int64_t total = panel_elems(n);
+  const unsigned grid = static_cast<unsigned>(ceil_div(total, 256));
+  if (f32)
+    make_panels_kernel<float><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<float*>(pan), total);
+  else
+    make_panels_kernel<double><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<double*>(pan), total);
+  return hipGetLastError();
+}
+
+// G(r, c) = sum_s gpart[s](r, c) for r <= c < n (ld npg), s ascending.
+__global__ void gram_reduce_kernel(const double* __restrict__ gpart, int nsplit, int npg, int n,
+                                   double* __restrict__ G) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int r = idx % n, c = idx / n;
+  if (r > c) return;
+  const int64_t stride = static_cast<int64_t>(npg) * npg;
+  const double* p = gpart + r + static_cast<int64_t>(c) * npg;
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += p[q * stride];
+  G[r + c * npg] = s;
+}
+
+hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, double* G,
+                              hipStream_t st) {
+  gram_reduce_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(gpart, gp.nsplit,
+                                                                                   gp.npg, n, G);
+  return hipGetLastError();
+}
+
+}  // namespace rcq

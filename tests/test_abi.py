@@ -1,0 +1,51 @@
+"""CPU-side checks of the C ABI: the library loads and exports every symbol
+declared in include/rcholqr.h, and argument validation answers without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rcholqr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rcholqr_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ["rcholqr_workspace_bytes", "rcholqr_factor", "rcholqr_status",
+              "rcholqr_sketch", "rcholqr_debug_theta", "rcholqr_trsm",
+              "rcholqr_error_string"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_workspace_and_argument_errors_without_gpu():
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    assert rq.workspace_bytes(10000, 50, 150, rq.GAUSSIAN, 1, rq.F64) > 0
+    assert rq.workspace_bytes(10, 50, 150, rq.GAUSSIAN, 1, rq.F64) == 0   # m < n
+    assert rq.workspace_bytes(1000, 50, 40, rq.GAUSSIAN, 1, rq.F64) == 0  # k < n
+    assert rq.workspace_bytes(1000, 300, 900, rq.GAUSSIAN, 1, rq.F64) == 0  # n > 256
+    vp = ctypes.c_void_p(8)
+    # bad n (argument 3), bad k (5), bad passes (8): rejected before any launch
+    assert L.rcholqr_factor(vp, 100, 0, 100, 10, 1, 0, 2, 0, vp, 100, vp, 1, None, 1,
+                            None, None, vp, 1 << 30, None) == -3
+    assert L.rcholqr_factor(vp, 100, 10, 100, 5, 1, 0, 2, 0, vp, 100, vp, 10, None, 1,
+                            None, None, vp, 1 << 30, None) == -5
+    assert L.rcholqr_factor(vp, 100, 10, 100, 30, 1, 0, 3, 0, vp, 100, vp, 10, None, 1,
+                            None, None, vp, 1 << 30, None) == -8
+    assert L.rcholqr_factor(vp, 100, 10, 100, 30, 1, 0, 2, 0, vp, 100, vp, 10, None, 1,
+                            None, None, vp, 16, None) == -19
+    assert rq.error_string(1).startswith("zero diagonal")
