@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of randomized Cholesky QR (Balabanov, arXiv 2210.09953) on one
+MI355X: GB/s of X factored and ||Q^T Q - I||_2, mixed precision against
+plain FP64 on the same matrix.
+
+Workload (default "mixed-4m"): X = U diag(sigma) V^T, m = 4,000,000,
+n = 256, sigma log-spaced 1 -> 1e-5, stored in FP32 (synthetic, seeded, drawn
+on the GPU); Rademacher sketch with k = 768 rows, 2 passes (Algorithm 3).
+One step = one rcholqr_factor call on X already resident in HBM.  The FP64
+leg factors the same values promoted exactly to FP64.
+
+Prints one JSON line.  `value` is the mixed-precision leg's GB/s of X
+(m n 4 bytes / time per step).  `roofline` describes the slowest kernel phase
+of that leg, timed live with HIP events recorded by the library on its
+stream; `cpu_baseline` is the FP64 CPU oracle timed on a bounded sample of
+rows of the same matrix on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8.0e12, "f64": 78.6e12, "f32": 157.3e12, "f16": 2.5e15}
+
+WORKLOADS = {
+    # name: (m, n, k, kind, sigma_min, value precision, x dtype bytes)
+    "mixed-4m": dict(m=4_000_000, n=256, k=768, kind="rademacher", sigma=1e-5,
+                     precision="mixed"),
+    "mixed-1m": dict(m=1_000_000, n=256, k=768, kind="rademacher", sigma=1e-5,
+                     precision="mixed"),
+    "f64-gauss-1m": dict(m=1_000_000, n=200, k=600, kind="gaussian", sigma=1e-12,
+                         precision="f64"),
+    "f64-count-1m": dict(m=1_000_000, n=200, k=600, kind="countsketch", sigma=1e-12,
+                         precision="f64"),
+    "f32-gauss-1m": dict(m=1_000_000, n=200, k=600, kind="gaussian", sigma=1e-6,
+                         precision="f32"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def phase_model(phase, m, n, k, kind, prec):
+    """Algorithmic work of one phase: (flops, bytes, matrix-core dtype)."""
+    s = 8 if prec == "f64" else 4
+    mm = {"f64": "f64", "f32": "f32", "mixed": "f32"}[prec]
+    if phase == "sketch":
+        if kind == "countsketch":
+            return float(m * n), float(m * n * s), "hbm"
+        return 2.0 * m * k * n, float(m * n * s), ("f16" if prec == "mixed" else "f64")
+    if phase in ("solve1", "solve2"):
+        return float(m) * n * n, 2.0 * m * n * s, mm
+    if phase == "gram":
+        return float(m) * n * (n + 1), float(m * n * s), "f64"
+    return 0.0, 0.0, "f64"
+
+
+def roofline(phase, ms_per_launch, m, n, k, kind, prec):
+    flops, nbytes, unit = phase_model(phase, m, n, k, kind, prec)
+    t_mem = nbytes / PEAK["hbm"]
+    t_cmp = flops / PEAK[unit] if unit != "hbm" else 0.0
+    t = ms_per_launch * 1e-3
+    if t_cmp > t_mem:
+        a = flops / t / 1e12
+        return {"bound": "mfma", "achieved": round(a, 3), "peak": PEAK[unit] / 1e12,
+                "unit": "TFLOP/s", "frac": round(a * 1e12 / PEAK[unit], 4), "traffic": None,
+                "kernel": phase, "dtype": unit, "ms_per_launch": round(ms_per_launch, 4),
+                "flops_per_launch": flops, "bytes_per_launch": nbytes}
+    a = nbytes / t / 1e9
+    return {"bound": "hbm", "achieved": round(a, 1), "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+            "frac": round(a * 1e9 / PEAK["hbm"], 4), "traffic": None, "kernel": phase,
+            "ms_per_launch": round(ms_per_launch, 4), "flops_per_launch": flops,
+            "bytes_per_launch": nbytes}
+
+
+def quality(torch, X, Q, R, nsample=200000):
+    """||Q^T Q - I||_2 (FP64 accumulation on the GPU) and the max column-wise
+    relative residual ||X_j - (QR)_j|| / ||X_j|| on a row sample."""
+    Qd = Q.double()
+    G = Qd.T @ Qd
+    G -= torch.eye(G.shape[0], dtype=G.dtype, device=G.device)
+    orth = float(torch.linalg.matrix_norm(G.cpu(), ord=2))
+    m = X.shape[0]
+    idx = torch.linspace(0, m - 1, min(nsample, m), device=X.device).long()
+    Xs, Qs = X[idx].double(), Qd[idx]
+    res = Xs - Qs @ R
+    col = torch.linalg.vector_norm(res, dim=0) / torch.linalg.vector_norm(Xs, dim=0)
+    return orth, float(col.max())
+
+
+def time_leg(torch, rq, X, k, kind, prec_code, steps, warmup, seed=1):
+    m, n = X.shape
+    dt = torch.float64 if prec_code == rq.F64 else torch.float32
+    Q = rq.empty_fortran(m, n, dt)
+    R = rq.empty_fortran(n, n, torch.float64)
+    ws = torch.empty(rq.workspace_bytes(m, n, k, kind, 2, prec_code), dtype=torch.uint8,
+                     device="cuda")
+    for _ in range(warmup):
+        rq.factor(X, k, seed, kind, 2, prec_code, ws=ws, Q=Q, R=R)
+    torch.cuda.synchronize()
+    st = rq.status(ws)
+    if st != 0:
+        raise RuntimeError(f"status {st}: {rq.error_string(st)}")
+    rq.profile_enable(True)
+    rq.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        rq.factor(X, k, seed, kind, 2, prec_code, ws=ws, Q=Q, R=R)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    calls, phases = rq.profile_read()
+    rq.profile_enable(False)
+    phases = {p: v / max(calls, 1) for p, v in phases.items()}
+    return ms, phases, Q, R
+
+
+def cpu_baseline(Xs_np, k, kind_code, budget_s=15.0):
+    """FP64 CPU oracle (test infrastructure) on the first rows of X."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    m_all, n = Xs_np.shape
+    m0 = min(m_all, 8192)
+    t0 = time.perf_counter()
+    oracle.rcholqr(Xs_np[:m0], k, 1, kind_code, passes=2)
+    t_small = time.perf_counter() - t0
+    m1 = int(min(m_all, max(m0, m0 * budget_s / max(t_small, 1e-3))))
+    m1 = max(n, (m1 // 1024) * 1024) if m1 > 1024 else m1
+    t0 = time.perf_counter()
+    out = oracle.rcholqr(np.asfortranarray(Xs_np[:m1]), k, 1, kind_code, passes=2)
+    t = time.perf_counter() - t0
+    return m1, t, threads, out["status"]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mixed-4m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2210_09953_amd as rq
+    import synth
+
+    W = WORKLOADS[args.workload]
+    m, n, k = W["m"], W["n"], W["k"]
+    kind = {"gaussian": rq.GAUSSIAN, "rademacher": rq.RADEMACHER,
+            "countsketch": rq.COUNTSKETCH}[W["kind"]]
+    prec = W["precision"]
+    prec_code = {"f64": rq.F64, "f32": rq.F32, "mixed": rq.MIXED}[prec]
+    xdt = torch.float64 if prec == "f64" else torch.float32
+    xbytes = 8 if prec == "f64" else 4
+
+    log(f"[bench] generating X {m}x{n} sigma_min={W['sigma']} on cuda:0")
+    X = synth.make_x_torch(m, n, W["sigma"], seed=0, dtype=xdt, device="cuda")
+    torch.cuda.synchronize()
+    note = None
+    log(f"[bench] value leg: precision={prec} kind={W['kind']} k={k} "
+        f"steps={args.steps} warmup={args.warmup}")
+    try:
+        ms, phases, Q, R = time_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup)
+    except rq.RCholQRError as e:
+        if prec != "mixed":
+            raise
+        note = f"mixed path unavailable ({e}); value leg ran in f32"
+        log("[bench] " + note)
+        prec, prec_code = "f32", rq.F32
+        ms, phases, Q, R = time_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup)
+    orth, res = quality(torch, X, Q, R)
+    value = m * n * xbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] {prec}: {ms:.3f} ms/step {value:.1f} GB/s orth={orth:.2e} resid={res:.2e} "
+        f"phases={ {p: round(v, 4) for p, v in phases.items()} }")
+    dom = max(phases, key=phases.get)
+    roof = roofline(dom, phases[dom], m, n, k, W["kind"], prec)
+    R_value = R.clone()
+    del Q
+
+    fp64 = None
+    if not args.no_fp64_leg and prec != "f64":
+        X64 = X.double()
+        X64 = rq.fortran(X64)
+        ms64, ph64, Q64, R64 = time_leg(torch, rq, X64, k, kind, rq.F64, args.steps,
+                                        args.warmup)
+        orth64, res64 = quality(torch, X64, Q64, R64)
+        dR = float(torch.linalg.matrix_norm(R_value - R64) / torch.linalg.matrix_norm(R64))
+        fp64 = {"value": round(m * n * xbytes / (ms64 * 1e-3) / 1e9, 2),
+                "unit": "GB/s", "ms_per_step": round(ms64, 4), "orth": orth64,
+                "resid": res64, "rel_diff_R_vs_value_leg": dR,
+                "phases_ms": {p: round(v, 4) for p, v in ph64.items()},
+                "speedup_of_value_leg": round(ms64 / ms, 3)}
+        log(f"[bench] f64: {ms64:.3f} ms/step orth={orth64:.2e} resid={res64:.2e} dR={dR:.2e}")
+        del Q64, X64
+
+    cpu = None
+    if not args.no_cpu:
+        ms_rows = min(m, 1 << 20)
+        Xs = X[:ms_rows].double().cpu().numpy()
+        Xs = np.asfortranarray(Xs)
+        log(f"[bench] cpu baseline (FP64 oracle) on up to {ms_rows} rows")
+        m1, t, threads, st = cpu_baseline(Xs, k, kind, args.cpu_budget)
+        cpu = {"value": round(m1 * n * xbytes / t / 1e9, 4), "unit": "GB/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {m1} rows of X (n={n}, k={k}, {W['kind']}, 2 passes, FP64), "
+                         f"{t:.1f} s, status {st}"}
+        log(f"[bench] cpu: {cpu}")
+
+    out = {
+        "metric": "GB/s of X factored + ||Q^T Q - I||: mixed vs FP64 RCholQR, 1 MI355X",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "mixed": "f16+f32+f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "sketch": W["kind"],
+                   "passes": 2, "sigma_min": W["sigma"], "x_dtype": str(xdt).split(".")[-1],
+                   "precision": prec},
+        "orth": orth, "resid": res,
+        "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+        "roofline": roof,
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    if note:
+        out["note"] = note
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

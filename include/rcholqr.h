@@ -135,6 +135,21 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx,
                  const double* R, int64_t ldr, int precision, void* Q,
                  int64_t ldq, void* ws, size_t ws_bytes, void* stream);
 
+/* Phase timing.  rcholqr_profile_enable(1) creates a ring of HIP events
+ * (no device memory is allocated); while enabled, every rcholqr_factor call
+ * records one event at each phase boundary on its own stream:
+ *   0 sketch (Theta X and its reduction)   1 small QR (Householder, sign fix)
+ *   2 first solve (Q1 = X R_s^{-1})        3 Gram (Q1^T Q1 and its reduction)
+ *   4 Cholesky and R = R' R_s               5 second solve (Q = Q1 R'^{-1})
+ * rcholqr_profile_read() waits for the recorded calls, adds their phase
+ * durations into ms[0..5] (milliseconds, summed over calls), returns the
+ * number of calls, and clears the record.  At most 256 calls are kept
+ * between reads (older ones are dropped).  rcholqr_profile_enable(0) frees
+ * the events.  Returns RCHOLQR_ERR_HIP on a runtime error.  Not thread safe. */
+#define RCHOLQR_NPHASES 6
+int rcholqr_profile_enable(int on);
+int rcholqr_profile_read(double* ms);
+
 /* Human-readable text for a return code or status value. */
 const char* rcholqr_error_string(int code);
 

@@ -8,15 +8,14 @@ raise: there is no fallback implementation.
 
 Matrices are column-major: an (m, n) tensor with stride (1, ld), ld >= m.
 """
-import ctypes
-import os
-
 from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, F64, F32, MIXED,
                       LibraryMissing, RCholQRError, lib, lib_path,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
-                      status, error_string, fortran, empty_fortran)
+                      status, error_string, fortran, empty_fortran, PHASES,
+                      profile_enable, profile_read)
 
 __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
            "LibraryMissing", "RCholQRError", "lib", "lib_path",
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
-           "status", "error_string", "fortran", "empty_fortran"]
+           "status", "error_string", "fortran", "empty_fortran", "PHASES",
+           "profile_enable", "profile_read"]

@@ -50,6 +50,10 @@ def lib():
     L.rcholqr_debug_theta.restype = i32
     L.rcholqr_trsm.argtypes = [vp, i64, i64, i64, dp, i64, i32, vp, i64, vp, sz, vp]
     L.rcholqr_trsm.restype = i32
+    L.rcholqr_profile_enable.argtypes = [i32]
+    L.rcholqr_profile_enable.restype = i32
+    L.rcholqr_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    L.rcholqr_profile_read.restype = i32
     L.rcholqr_error_string.argtypes = [i32]
     L.rcholqr_error_string.restype = ctypes.c_char_p
     _LIB = L
@@ -188,3 +192,20 @@ def trsm(X, R, precision=None, Q=None, ws=None):
                               _ld(Q), _ptr(ws), ws.numel(), _stream())
     _check(code, "rcholqr_trsm")
     return Q
+
+
+PHASES = ("sketch", "small_qr", "solve1", "gram", "cholesky", "solve2")
+
+
+def profile_enable(on=True):
+    """Record HIP events at the phase boundaries of every factor() call."""
+    _check(lib().rcholqr_profile_enable(1 if on else 0), "rcholqr_profile_enable")
+
+
+def profile_read():
+    """(calls, {phase: total ms}) since the last read; waits for the events."""
+    ms = (ctypes.c_double * len(PHASES))()
+    n = lib().rcholqr_profile_read(ms)
+    if n < 0:
+        raise RCholQRError(n, "rcholqr_profile_read")
+    return n, {p: float(ms[i]) for i, p in enumerate(PHASES)}

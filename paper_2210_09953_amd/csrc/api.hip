@@ -36,7 +36,29 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   Layout L{};
   SketchPlan& sp = L.sp;
   sp.npad = static_cast<int>(round_up(n, 16));
-  if (kind == kCountSketch) {
+  if (prec == kPrecMixed) {
+    // FP16 matrix-core sketch: 256 Theta rows x 64 columns per workgroup,
+    // one workgroup per CU; splits chosen so the grid fills whole CU rounds.
+    const int nh = static_cast<int>(ceil_div(n, 64));
+    sp.npad = (nh > 1) ? 64 * nh : static_cast<int>(round_up(n, 16));
+    sp.ktiles = static_cast<int>(ceil_div(k, 256));
+    sp.kpad = 256 * sp.ktiles;
+    const int64_t tps = static_cast<int64_t>(sp.ktiles) * nh;
+    const int64_t maxs = round_up(ceil_div(m, 128), 8);
+    int64_t best = 8;
+    double best_eff = -1.0;
+    for (int64_t ns = 8; ns <= 512 && ns <= maxs; ns += 8) {
+      const int64_t w = ns * tps;
+      const double eff = static_cast<double>(w) / (256.0 * ceil_div(w, 256));
+      const double score = eff - ((w < 512) ? 0.5 : 0.0) - 1e-4 * static_cast<double>(w / 256);
+      if (score > best_eff + 1e-9) {
+        best_eff = score;
+        best = ns;
+      }
+    }
+    sp.nsplit = static_cast<int>(best);
+    sp.rows_per_split = round_up(ceil_div(m, sp.nsplit), 128);
+  } else if (kind == kCountSketch) {
     const int panels = static_cast<int>(ceil_div(n, 8));
     const int64_t ntile = ceil_div(m, 256);
     int64_t ns = ceil_div(1024, panels);
@@ -93,6 +115,34 @@ T* at(void* ws, size_t off) {
     if ((expr) != hipSuccess) return RCHOLQR_ERR_HIP; \
   } while (0)
 
+// Phase-boundary events (see rcholqr_profile_enable).
+constexpr int kRing = 256;
+constexpr int kEv = RCHOLQR_NPHASES + 1;
+struct Profiler {
+  bool on = false;
+  hipEvent_t ev[kRing][kEv];
+  bool used[kRing][kEv];
+  int head = 0, count = 0;
+};
+Profiler g_prof;
+
+// Records boundary `b` of the current call (no-op when profiling is off).
+void prof_mark(int b, hipStream_t st) {
+  if (!g_prof.on) return;
+  const int slot = g_prof.head;
+  if (hipEventRecord(g_prof.ev[slot][b], st) == hipSuccess) g_prof.used[slot][b] = true;
+}
+void prof_begin(hipStream_t st) {
+  if (!g_prof.on) return;
+  for (int b = 0; b < kEv; ++b) g_prof.used[g_prof.head][b] = false;
+  prof_mark(0, st);
+}
+void prof_end() {
+  if (!g_prof.on) return;
+  g_prof.head = (g_prof.head + 1) % kRing;
+  if (g_prof.count < kRing) ++g_prof.count;
+}
+
 }  // namespace
 
 extern "C" {
@@ -117,7 +167,7 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   if (sketch_kind < 0 || sketch_kind > 2) return -7;
   if (passes < 1 || passes > 2) return -8;
   if (precision < 0 || precision > 2) return -9;
-  if (precision == kPrecMixed) return -9;
+  if (precision == kPrecMixed && sketch_kind != kRademacher) return -9;
   if (!Q) return -10;
   if (ldq < m) return -11;
   if (!R) return -12;
@@ -134,29 +184,76 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   double* Rsw = at<double>(ws, L.Rs);
   void* pan = at<void>(ws, L.pan);
 
+  prof_begin(st);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
                                 at<double>(ws, L.part), P, k, st));
   else
     RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
                           at<uint32_t>(ws, L.keys), P, k, st));
+  prof_mark(1, st);
   RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
                              at<double>(ws, L.T), S, lds, Rsw, passes == 1 ? R : nullptr, ldr,
                              status, st));
   if (Rs) RCQ_TRY(launch_copy_upper(Rsw, n, Rs, n, ni, st));
   RCQ_TRY(launch_make_panels(Rsw, n, ni, f32, pan, st));
+  prof_mark(2, st);
   RCQ_TRY(launch_trsm(X, f32, m, ni, ldx, pan, Q, ldq, st));
-  if (passes == 1) return 0;
-
+  prof_mark(3, st);
+  if (passes == 1) {
+    prof_end();
+    return 0;
+  }
   double* G = at<double>(ws, L.G);
   RCQ_TRY(launch_gram(Q, f32, m, ni, ldq, L.gp, at<double>(ws, L.gpart), st));
   RCQ_TRY(launch_gram_reduce(at<double>(ws, L.gpart), L.gp, ni, G, st));
+  prof_mark(4, st);
   RCQ_TRY(launch_cholesky(G, ni, L.gp.npg, status, st));
   RCQ_TRY(launch_triu_product(G, L.gp.npg, Rsw, n, R, ldr, ni, st));
   if (Rp) RCQ_TRY(launch_copy_upper(G, L.gp.npg, Rp, n, ni, st));
   RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, f32, pan, st));
+  prof_mark(5, st);
   RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  prof_mark(6, st);
+  prof_end();
   return 0;
+}
+
+int rcholqr_profile_enable(int on) {
+  if (on && !g_prof.on) {
+    for (int i = 0; i < kRing; ++i)
+      for (int b = 0; b < kEv; ++b) {
+        if (hipEventCreate(&g_prof.ev[i][b]) != hipSuccess) return RCHOLQR_ERR_HIP;
+        g_prof.used[i][b] = false;
+      }
+    g_prof.on = true;
+    g_prof.head = g_prof.count = 0;
+  } else if (!on && g_prof.on) {
+    for (int i = 0; i < kRing; ++i)
+      for (int b = 0; b < kEv; ++b) (void)hipEventDestroy(g_prof.ev[i][b]);
+    g_prof.on = false;
+  }
+  return 0;
+}
+
+int rcholqr_profile_read(double* ms) {
+  if (!ms) return -1;
+  for (int p = 0; p < RCHOLQR_NPHASES; ++p) ms[p] = 0.0;
+  if (!g_prof.on) return 0;
+  const int n = g_prof.count;
+  for (int c = 0; c < n; ++c) {
+    const int slot = (g_prof.head - 1 - c + kRing) % kRing;
+    for (int p = 0; p < RCHOLQR_NPHASES; ++p) {
+      if (!g_prof.used[slot][p] || !g_prof.used[slot][p + 1]) continue;
+      if (hipEventSynchronize(g_prof.ev[slot][p + 1]) != hipSuccess) return RCHOLQR_ERR_HIP;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, g_prof.ev[slot][p], g_prof.ev[slot][p + 1]) != hipSuccess)
+        return RCHOLQR_ERR_HIP;
+      ms[p] += t;
+    }
+  }
+  g_prof.count = 0;
+  return n;
 }
 
 int rcholqr_status(const void* ws, int* info) {

@@ -40,6 +40,8 @@ hipError_t launch_theta_debug(int kind, int k, uint64_t seed, int64_t i0, int64_
 hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
                          int kind, uint64_t seed, const SketchPlan& pl, double* part,
                          uint32_t* keys, double* P, int64_t ldp, hipStream_t st);
+hipError_t launch_sketch_reduce(const double* part, const SketchPlan& pl, int k, int n,
+                                double scale, double* P, int64_t ldp, hipStream_t st);
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
                                hipStream_t st);

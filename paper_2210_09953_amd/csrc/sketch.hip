@@ -301,6 +301,11 @@ hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t
     if (e != hipSuccess) return e;
   }
   const double scale = (kind == kCountSketch) ? 1.0 : 1.0 / sqrt(static_cast<double>(k));
+  return launch_sketch_reduce(part, pl, k, n, scale, P, ldp, st);
+}
+
+hipError_t launch_sketch_reduce(const double* part, const SketchPlan& pl, int k, int n,
+                                double scale, double* P, int64_t ldp, hipStream_t st) {
   const int64_t total = static_cast<int64_t>(k) * n;
   sketch_reduce_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, st>>>(
       part, pl.nsplit, k, n, pl.kpad, pl.npad, scale, P, ldp);

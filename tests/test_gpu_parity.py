@@ -217,3 +217,40 @@ def test_bitwise_deterministic(rq):
         b = rq.factor(X, 144, 7, kind, passes=2)
         torch.cuda.synchronize()
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ----------------------------------------------------------------------------- mixed
+@pytest.mark.parametrize("m,n,k", [(5000, 64, 192), (3333, 200, 600), (1031, 17, 51),
+                                   (20000, 256, 768)])
+def test_mixed_sketch_parity(rq, orc, m, n, k):
+    """FP16 hi+lo matrix-core sketch against the FP64 oracle on the same FP32
+    values: the split keeps ~22 bits, FP32 sums are flushed to FP64."""
+    X32 = synth.make_x(m, n, 1e-5, seed=9, dtype=np.float32)
+    # wide column scales: the per-column power-of-two scaling must absorb them
+    X32 = (X32 * np.float32(10.0) ** np.linspace(-3, 3, n, dtype=np.float32)).astype(np.float32)
+    X32 = np.asfortranarray(X32)
+    P = _np(rq.sketch(_gpu(X32), k, 21, kind=rq.RADEMACHER, precision=rq.MIXED))
+    X = X32.astype(np.float64)
+    Pr = orc.sketch(orc.RADEMACHER, X, k, 21)
+    rel = np.linalg.norm(P - Pr, axis=0) / np.linalg.norm(X, axis=0)
+    print(f"mixed sketch m={m} n={n}: max column error / ||X_j|| = {rel.max():.2e}")
+    assert rel.max() <= 2e-6
+
+
+@pytest.mark.parametrize("m,n,k,sig", [(50000, 64, 192, 1e-5), (100000, 256, 768, 1e-5)])
+def test_mixed_two_pass(rq, orc, m, n, k, sig):
+    X32 = synth.make_x(m, n, sig, seed=10, dtype=np.float32)
+    Q, R, ex = rq.factor(_gpu(X32), k, 3, rq.RADEMACHER, passes=2, precision=rq.MIXED,
+                         want_factors=True)
+    assert rq.status(ex["ws"]) == 0
+    Qn, Rn = _np(Q).astype(np.float64), _np(R)
+    X = X32.astype(np.float64)
+    orth = np.linalg.norm(Qn.T @ Qn - np.eye(n), 2)
+    res = _colres(X, Qn, Rn)
+    ref = orc.rcholqr(X, k, 3, orc.RADEMACHER, passes=2)
+    dR = np.linalg.norm(Rn - ref["R"]) / np.linalg.norm(ref["R"])
+    dQ = np.linalg.norm(Qn - ref["Q"]) / np.linalg.norm(ref["Q"])
+    print(f"mixed 2-pass m={m} n={n}: orth={orth:.2e} resid={res:.2e} dR={dR:.2e} dQ={dQ:.2e}")
+    assert orth <= 1e-6
+    assert res <= 1e-5
+    assert dR <= 1e-4 and dQ <= 1e-3
