@@ -23,7 +23,7 @@ namespace {
 struct Layout {
   SketchPlan sp;
   GramPlan gp;
-  size_t status, part, keys, P, v0, beta, T, Rs, pan, gpart, G, total;
+  size_t status, part, keys, P, v0, beta, T, Rs, pan, Tinv, gpart, G, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -97,7 +97,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   L.beta = off; off += align256(static_cast<size_t>(n) * sizeof(double));
   L.T = off; off += align256(static_cast<size_t>(ceil_div(n, kHhPanel)) * kHhPanel * kHhPanel * sizeof(double));
   L.Rs = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
-  L.pan = off; off += align256(static_cast<size_t>(panel_elems(static_cast<int>(n))) * esz);
+  (void)esz;
+  L.pan = off; off += align256(static_cast<size_t>(panel_elems(static_cast<int>(n))) * sizeof(double));
+  L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   L.gpart = off;
   if (passes == 2) off += align256(static_cast<size_t>(gp.nsplit) * gp.npg * gp.npg * sizeof(double));
   L.G = off; off += align256(static_cast<size_t>(gp.npg) * gp.npg * sizeof(double));
@@ -211,9 +213,15 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   RCQ_TRY(launch_cholesky(G, ni, L.gp.npg, status, st));
   RCQ_TRY(launch_triu_product(G, L.gp.npg, Rsw, n, R, ldr, ni, st));
   if (Rp) RCQ_TRY(launch_copy_upper(G, L.gp.npg, Rp, n, ni, st));
-  RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, f32, pan, st));
+  // T = R'^{-1} by the row-wise solve applied to the identity (FP64), then
+  // the second solve as the triangular product Q = Q1 T in place.
+  double* Tinv = at<double>(ws, L.Tinv);
+  RCQ_TRY(launch_set_identity(Tinv, n, ni, ni, st));
+  RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, false, pan, st));
+  RCQ_TRY(launch_trsm(Tinv, false, ni, ni, n, pan, Tinv, n, st));
+  RCQ_TRY(launch_make_panels(Tinv, n, ni, f32, pan, st, false));
   prof_mark(5, st);
-  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  RCQ_TRY(launch_trmm(Q, f32, m, ni, ldq, pan, st));
   prof_mark(6, st);
   prof_end();
   return 0;

@@ -56,7 +56,8 @@ hipError_t launch_triu_product(const double* A, int64_t lda, const double* B, in
 hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ldb, int n,
                              hipStream_t st);
 hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
-                              hipStream_t st);
+                              hipStream_t st, bool negate = true);
+hipError_t launch_set_identity(double* A, int64_t lda, int rows, int cols, hipStream_t st);
 hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, double* G,
                               hipStream_t st);
 
@@ -65,6 +66,8 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
                        void* Q, int64_t ldq, hipStream_t st);
 hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq,
                        const GramPlan& gp, double* gpart, hipStream_t st);
+hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,
+                       hipStream_t st);
 
 inline int64_t panel_elems(int n) {
   const int64_t nb = (n + 15) / 16;

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   __shared__ double sc[3];
   __shared__ double v0s[kHhPanel], bs[kHhPanel];
   __shared__ double y[kHhPanel][kHhPanel];
+  __shared__ double tT[kHhPanel][kHhPanel + 1];
   const int L = k - p0;
   const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -86,21 +87,27 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
     if (lane == 0) y[a][b] = s;
   }
   __syncthreads();
-  if (tid == 0) {
-    // T upper: T[j][j] = beta_j, T[0:j, j] = -beta_j T[0:j, 0:j] (V_{0:j}^T v_j).
-    double T[kHhPanel][kHhPanel];
-    for (int a = 0; a < kHhPanel; ++a)
-      for (int b = 0; b < kHhPanel; ++b) T[a][b] = 0.0;
-    for (int j = 0; j < nbp; ++j) {
-      for (int a = 0; a < j; ++a) {
-        double s = 0.0;
-        for (int l = a; l < j; ++l) s += T[a][l] * y[l][j];
-        T[a][j] = -bs[j] * s;
+  // T upper (compact WY of the panel): T[j][j] = beta_j and
+  // T[0:j, j] = -beta_j T[0:j, 0:j] (V_{0:j}^T v_j); column j needs the
+  // previous columns only, so one wave builds it in LDS, lane a = row a.
+  if (wave == 0) {
+    const int a = lane;
+    for (int j = 0; j < kHhPanel; ++j) {
+      double tv = 0.0;
+      if (j < nbp) {
+        if (a < j) {
+          double acc = 0.0;
+          for (int l = a; l < j; ++l) acc += tT[a][l] * y[l][j];
+          tv = -bs[j] * acc;
+        } else if (a == j) {
+          tv = bs[j];
+        }
       }
-      T[j][j] = bs[j];
+      if (a < kHhPanel) tT[a][j] = tv;
+      wave_sync();
     }
-    for (int a = 0; a < kHhPanel; ++a)
-      for (int b = 0; b < kHhPanel; ++b) Tp[a + kHhPanel * b] = T[a][b];
+    if (a < kHhPanel)
+      for (int b = 0; b < kHhPanel; ++b) Tp[a + kHhPanel * b] = tT[a][b];
   }
   if (tid < nbp) {
     v0g[p0 + tid] = v0s[tid];
@@ -260,16 +267,22 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
 
 // ----------------------------------------------------------------------------
 // Cholesky, upper, in place on G (ld ldg); only the upper triangle is read
-// and written.  Status 1000 + j at the first pivot that is not positive and
-// finite (only if the status word is still 0).
+// and written.  Blocked right-looking in 32-column panels: one wave factors
+// the 32 x 32 diagonal block in LDS, threads solve the panel's rows to the
+// right (multiplying by the pivots' reciprocals), and the trailing update
+// G -= Rp^T Rp runs on FP64 matrix cores in 16 x 16 tiles.  Status
+// 1000 + j at the first pivot that is not positive and finite (only if the
+// status word is still 0).
 constexpr int kChB = 32;
 
 __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int n, int ldg,
                                                     int* __restrict__ status) {
   __shared__ double dg[kChB][kChB + 1];
+  __shared__ double rinv[kChB];
   __shared__ double rp[kChB][kMaxN + 1];
   __shared__ int fail;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
   if (tid == 0) fail = 0;
   for (int c0 = 0; c0 < n; c0 += kChB) {
     const int w = (n - c0 < kChB) ? n - c0 : kChB;
@@ -284,23 +297,28 @@ __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int 
     }
     __syncthreads();
     if (wave == 0) {
-      for (int j = 0; j < w; ++j) {
+      const int c = lane;  // lanes 0..31 own columns of the block
+#pragma unroll
+      for (int j = 0; j < kChB; ++j) {
+        const double d = dg[j][j];
+        const bool ok = (d > 0.0) && isfinite(d);
+        const double r = ok ? sqrt(d) : 1.0;
+        const double ri = 1.0 / r;
+        if (!ok && lane == 0 && fail == 0 && j < w) fail = c0 + j + 1;
+        double rjc = 0.0;
+        if (c < kChB && c > j) {
+          rjc = dg[j][c] * ri;
+          dg[j][c] = rjc;
+        }
         if (lane == j) {
-          const double d = dg[j][j];
-          const bool ok = (d > 0.0) && isfinite(d);
-          dg[j][j] = ok ? sqrt(d) : 0.0;
-          if (!ok && fail == 0) fail = c0 + j + 1;
+          dg[j][j] = r;
+          rinv[j] = ri;
         }
         wave_sync();
-        const double r = dg[j][j];
-        if (lane > j && lane < w) {
-          const double t = dg[j][lane] / r;
-          dg[j][lane] = t;
-        }
-        wave_sync();
-        if (lane > j && lane < w) {
-          const double t = dg[j][lane];
-          for (int i = j + 1; i <= lane; ++i) dg[i][lane] -= dg[j][i] * t;
+        if (c < kChB && c > j) {
+#pragma unroll
+          for (int i = j + 1; i < kChB; ++i)
+            if (i <= c) dg[i][c] -= dg[j][i] * rjc;
         }
         wave_sync();
       }
@@ -312,31 +330,46 @@ __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int 
       if (i <= c) G[(c0 + i) + static_cast<int64_t>(c0 + c) * ldg] = dg[i][c];
     }
     const int nt = n - c0 - w;
-    if (tid < nt) {
+    if (tid < nt) {  // one thread per column to the right: Rp = Rd^{-T} G_panel
       const int c = c0 + w + tid;
-      double x[kChB];
-#pragma unroll
-      for (int i = 0; i < kChB; ++i) x[i] = (i < w) ? G[(c0 + i) + static_cast<int64_t>(c) * ldg] : 0.0;
-#pragma unroll
       for (int i = 0; i < kChB; ++i) {
-        double s = x[i];
-#pragma unroll
-        for (int l = 0; l < i; ++l) s -= dg[l][i] * x[l];
-        x[i] = s / dg[i][i];
-      }
-#pragma unroll
-      for (int i = 0; i < kChB; ++i) {
-        if (i < w) G[(c0 + i) + static_cast<int64_t>(c) * ldg] = x[i];
-        rp[i][tid] = x[i];
+        double sv = (i < w) ? G[(c0 + i) + static_cast<int64_t>(c) * ldg] : 0.0;
+        for (int l = 0; l < i; ++l) sv -= dg[l][i] * rp[l][tid];
+        sv *= rinv[i];
+        rp[i][tid] = sv;
+        if (i < w) G[(c0 + i) + static_cast<int64_t>(c) * ldg] = sv;
       }
     }
     __syncthreads();
-    for (int idx = tid; idx < nt * nt; idx += blockDim.x) {
-      const int i = idx % nt, c = idx / nt;
-      if (i > c) continue;
-      double s = 0.0;
-      for (int l = 0; l < w; ++l) s += rp[l][i] * rp[l][c];
-      G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] -= s;
+    // Trailing update on 16 x 16 tiles (ti <= tj) of the remaining nt columns.
+    const int ntt = (nt + 15) / 16;
+    const int ntiles = ntt * (ntt + 1) / 2;
+    for (int tile = wave; tile < ntiles; tile += 16) {
+      int ti = 0, tj = 0, cnt = tile;
+      while (cnt > tj) {  // decode upper-triangular tile index (row ti, column tj)
+        cnt -= tj + 1;
+        ++tj;
+      }
+      ti = cnt;
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
+        acc[v] = (i < nt && c < nt) ? G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] : 0.0;
+      }
+#pragma unroll
+      for (int ks = 0; ks < kChB / 4; ++ks) {
+        const int kk = 4 * ks + lg;
+        const int ci = 16 * ti + l16, cj = 16 * tj + l16;
+        const double a = (ci < nt) ? -rp[kk][ci] : 0.0;
+        const double b = (cj < nt) ? rp[kk][cj] : 0.0;
+        acc = mfma16x16x4(a, b, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
+        if (i < nt && c < nt && i <= c) G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] = acc[v];
+      }
     }
     __syncthreads();
   }
@@ -382,13 +415,14 @@ hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ld
   return hipGetLastError();
 }
 
-// Panel packing for the tall solve.  Panel b (16 columns 16b..16b+15)
-// holds rows 0..16b+15 row-major (16 entries per row): -R(r, 16b+c) above
-// the diagonal block (the matrix-core update subtracts), R itself in the
-// diagonal block.  Columns past n are padded with the identity.
+// Panel packing for the tall passes.  Panel b (16 columns 16b..16b+15)
+// holds rows 0..16b+15 row-major (16 entries per row): the upper triangle
+// of R in the diagonal block, and above it R times offdiag_sign: -1 for the
+// solve (its matrix-core update subtracts), +1 for the triangular product.
+// Columns past n are padded with the identity.
 template <typename T>
 __global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, int n,
-                                   T* __restrict__ pan, int64_t total) {
+                                   T* __restrict__ pan, int64_t total, double offdiag_sign) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   // locate panel b: offset(b) = 256 b (b+1) / 2
@@ -399,7 +433,7 @@ __global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, in
   const int col = 16 * b + c;
   double v;
   if (r < 16 * b) {
-    v = (col < n && r < n) ? -R[r + col * ldr] : 0.0;
+    v = (col < n && r < n) ? offdiag_sign * R[r + col * ldr] : 0.0;
   } else {
     if (col < n && r < n)
       v = (r <= col) ? R[r + col * ldr] : 0.0;
@@ -410,13 +444,20 @@ __global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, in
 }
 
 hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
-                              hipStream_t st) {
+                              hipStream_t st, bool negate) {
   const int64_t total = panel_elems(n);
   const unsigned grid = static_cast<unsigned>(ceil_div(total, 256));
+  const double sg = negate ? -1.0 : 1.0;
   if (f32)
-    make_panels_kernel<float><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<float*>(pan), total);
+    make_panels_kernel<float><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<float*>(pan), total, sg);
   else
-    make_panels_kernel<double><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<double*>(pan), total);
+    make_panels_kernel<double><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<double*>(pan), total, sg);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_identity(double* A, int64_t lda, int rows, int cols, hipStream_t st) {
+  const int64_t tot = static_cast<int64_t>(rows) * cols;
+  set_identity_kernel<<<static_cast<unsigned>(ceil_div(tot, 256)), 256, 0, st>>>(A, lda, rows, cols);
   return hipGetLastError();
 }
 

@@ -14,41 +14,72 @@
 // each lane group holds 4 consecutive panel columns for the diagonal solve.
 // Works in place (Q == X).
 //
-// gram_kernel: A = Q^T Q (Algorithm 3 step 2), split-K over rows with FP64
-// matrix-core accumulation; one wave per 64 x 64 block of the upper
-// triangle, rows staged through LDS; per-split partials are reduced in a
+// trmm_kernel: Q = Q1 T for the upper triangular T = R'^{-1} (the second
+// solve as a product; R' is well conditioned).
+//
+// gram_kernel: A = Q^T Q (Algorithm 3 step 2), split-K over rows on matrix
+// cores in the working precision, FP64 partial sums per split (FP32 sums are
+// folded into FP64 every 2048 rows); per-split partials are reduced in a
 // fixed order by gram_reduce_kernel.
 #include "common.h"
 #include "kernels.h"
 
 namespace rcq {
 
+// Copies panel b (rows 0..16b+15 x 16 columns) of the packed R array to
+// registers (staging toward LDS): thread t holds elements t, t+256, ...
+template <typename T, int NB>
+__device__ __forceinline__ void panel_fetch(const T* __restrict__ pan, int b, T (&st)[NB]) {
+  const T* pb = pan + 256 * (b * (b + 1) / 2);
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (q <= b) st[q] = pb[threadIdx.x + 256 * q];
+}
+template <typename T, int NB>
+__device__ __forceinline__ void panel_store(T* __restrict__ buf, int b, const T (&st)[NB]) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (q <= b) buf[threadIdx.x + 256 * q] = st[q];
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n, int64_t ldx,
                                                    const T* __restrict__ pan, T* Q, int64_t ldq) {
   typedef typename Acc4<T>::type A4;
   __shared__ T tr[4][16][17];
+  __shared__ T pbuf[2][256 * NB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
   const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
+  const bool rok = row < m;
   // A rows permuted so that D element v of lane group lg is panel column 4 lg + v.
   const int acol = arow_for_blocked_d<T>(l16);
-  const bool rok = row < m;
   T qa[4 * NB];
+  T stg[NB];
 
+  panel_fetch<T, NB>(pan, 0, stg);
+  panel_store<T, NB>(pbuf[0], 0, stg);
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const T* pb = pan + 256 * (b * (b + 1) / 2);
-    A4 D;
+    const T* pb = pbuf[b & 1];
+    if (b + 1 < NB) panel_fetch<T, NB>(pan, b + 1, stg);  // overlap with this panel
+    A4 D, E;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int col = 16 * b + 4 * lg + v;
       D[v] = (rok && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
+      E[v] = T(0);
     }
-    // D <- X_b^T - R_{<b,b}^T Q_{<b}^T  (A = -R^T block, B = Q^T block)
+    // D <- X_b^T - R_{<b,b}^T Q_{<b}^T (A = -R^T block, B = Q^T block), two chains.
 #pragma unroll
-    for (int s = 0; s < 4 * (NB - 1); ++s)
-      if (s < 4 * b) D = mfma16x16x4(pb[(4 * s + lg) * 16 + acol], qa[s], D);
+    for (int s = 0; s < 4 * (NB - 1); s += 2)
+      if (s < 4 * b) {
+        D = mfma16x16x4(pb[(4 * s + lg) * 16 + acol], qa[s], D);
+        E = mfma16x16x4(pb[(4 * (s + 1) + lg) * 16 + acol], qa[s + 1], E);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) D[v] += E[v];
 
     // Diagonal block: column c = 4*lg + v of the panel lives in lane group lg.
     const T* dgb = pb + 16 * b * 16;
@@ -89,7 +120,8 @@ __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n,
       wave_sync();
 #pragma unroll
       for (int s = 0; s < 4; ++s) qa[4 * b + s] = tr[wave][4 * s + lg][l16];
-      wave_sync();
+      panel_store<T, NB>(pbuf[(b + 1) & 1], b + 1, stg);
+      __syncthreads();
     }
   }
 }
@@ -124,19 +156,113 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
 }
 
 // ----------------------------------------------------------------------------
-constexpr int kGrRows = 16;
+// Q = Q1 T for an upper triangular T (T = R'^{-1}, Algorithm 3 step 4 as a
+// product: R' comes from the Cholesky factor of the Gram of a well
+// conditioned Q1, so its inverse is safe to form).  Same layout as the
+// solve: a wave loads its 16 rows of Q1 into registers first (so the
+// product can overwrite them), then each 16-column output panel is a chain
+// of 16x16x4 matrix-core products with no diagonal solve.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void trmm_kernel(T* Q, int64_t m, int n, int64_t ldq,
+                                                   const T* __restrict__ pan) {
+  typedef typename Acc4<T>::type A4;
+  __shared__ T pbuf[2][256 * NB];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
+  const bool rok = row < m;
+  const int acol = arow_for_blocked_d<T>(l16);
+  T qa[4 * NB];
+  T stg[NB];
+#pragma unroll
+  for (int s = 0; s < 4 * NB; ++s) {
+    const int col = 4 * s + lg;
+    qa[s] = (rok && col < n) ? Q[row + static_cast<int64_t>(col) * ldq] : T(0);
+  }
+  panel_fetch<T, NB>(pan, 0, stg);
+  panel_store<T, NB>(pbuf[0], 0, stg);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const T* pb = pbuf[b & 1];
+    if (b + 1 < NB) panel_fetch<T, NB>(pan, b + 1, stg);
+    A4 D, E;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      D[v] = T(0);
+      E[v] = T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4 * NB; s += 2)
+      if (s < 4 * (b + 1)) {
+        D = mfma16x16x4(pb[(4 * s + lg) * 16 + acol], qa[s], D);
+        E = mfma16x16x4(pb[(4 * (s + 1) + lg) * 16 + acol], qa[s + 1], E);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = 16 * b + 4 * lg + v;
+      if (rok && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[v] + E[v];
+    }
+    if (b + 1 < NB) {
+      panel_store<T, NB>(pbuf[(b + 1) & 1], b + 1, stg);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+static hipError_t trmm_dispatch(int nb, T* Q, int64_t m, int n, int64_t ldq, const T* pan,
+                                hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+#define RCQ_TM_CASE(NBV)                                                  \
+  case NBV:                                                               \
+    trmm_kernel<T, NBV><<<grid, 256, 0, st>>>(Q, m, n, ldq, pan);         \
+    break;
+  switch (nb) {
+    RCQ_TM_CASE(1) RCQ_TM_CASE(2) RCQ_TM_CASE(3) RCQ_TM_CASE(4) RCQ_TM_CASE(5) RCQ_TM_CASE(6)
+    RCQ_TM_CASE(7) RCQ_TM_CASE(8) RCQ_TM_CASE(9) RCQ_TM_CASE(10) RCQ_TM_CASE(11) RCQ_TM_CASE(12)
+    RCQ_TM_CASE(13) RCQ_TM_CASE(14) RCQ_TM_CASE(15) RCQ_TM_CASE(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef RCQ_TM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,
+                       hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  if (f32)
+    return trmm_dispatch<float>(nb, static_cast<float*>(Q), m, n, ldq,
+                                static_cast<const float*>(pan), st);
+  return trmm_dispatch<double>(nb, static_cast<double*>(Q), m, n, ldq,
+                               static_cast<const double*>(pan), st);
+}
+
+// ----------------------------------------------------------------------------
+// Gram A = Q^T Q.  One wave per 64 x 64 block of the upper triangle; rows
+// staged through LDS 32 at a time; products on matrix cores in the working
+// precision.  FP64 data accumulates in FP64.  FP32 data accumulates in FP32
+// for at most kGrFlush rows, then the sums are added into the workgroup's
+// own FP64 partial in memory (written by this workgroup only: deterministic).
+constexpr int kGrFlush = 2048;
+template <typename T>
+struct GramRows {
+  static constexpr int value = sizeof(T) == 4 ? 32 : 16;
+};
 
 template <typename T, int NBB>
-__global__ __launch_bounds__(640) void gram_kernel(const T* __restrict__ Q, int64_t m, int n,
+__global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T* __restrict__ Q, int64_t m, int n,
                                                    int64_t ldq, int64_t rows_per_split,
                                                    double* __restrict__ gpart) {
+  typedef typename Acc4<T>::type A4;
   constexpr int NP = 64 * NBB;
   constexpr int NW = NBB * (NBB + 1) / 2;
-  __shared__ double qs[kGrRows][NP + 1];
+  constexpr int kGrRows = GramRows<T>::value;
+  __shared__ T qs[kGrRows][NP + 1];
   const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  // wave -> upper block (bi, bj), bi <= bj
   int bi = 0, bj = 0, cnt = 0;
   for (int j = 0; j < NBB; ++j)
     for (int i = 0; i <= j; ++i) {
@@ -148,23 +274,72 @@ __global__ __launch_bounds__(640) void gram_kernel(const T* __restrict__ Q, int6
     }
   const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
-  d4 acc[4][4];
+  double* dst = gpart + static_cast<int64_t>(s) * NP * NP;
+  A4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGrRows) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kGrRows * NP; idx += NW * 64) {
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
+  bool first = true;
+  // Element (a, b, v) of this lane sits at dst + lane_off + constant; the
+  // offset is laundered at each flush so the 64 addresses are not kept live
+  // across the row loop.
+  const int64_t lane_off = (64 * bi + drow<T>(lg, 0)) + static_cast<int64_t>(64 * bj + l16) * NP;
+#define RCQ_GRAM_FLUSH()                                                        \
+  do {                                                                          \
+    int64_t lo = lane_off;                                                      \
+    asm volatile("" : "+v"(lo));                                                \
+    double* base = dst + lo;                                                    \
+    _Pragma("unroll") for (int a = 0; a < 4; ++a)                               \
+    _Pragma("unroll") for (int b = 0; b < 4; ++b)                               \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v) {                             \
+      double* p = base + (16 * a + (drow<T>(lg, v) - drow<T>(lg, 0))) +         \
+                  static_cast<int64_t>(16 * b) * NP;                            \
+      const double val = static_cast<double>(acc[a][b][v]);                     \
+      *p = first ? val : *p + val;                                              \
+      acc[a][b][v] = T(0);                                                      \
+      if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);                  \
+    }                                                                           \
+    first = false;                                                              \
+  } while (0)
+  // FP32: register prefetch of the next stage (kGrRows x NP values over
+  // NW*64 threads).  FP64 (accumulators twice as large): direct staging.
+  constexpr bool kPre = sizeof(T) == 4;
+  constexpr int PER = kPre ? (kGrRows * NP + NW * 64 - 1) / (NW * 64) : 1;
+  T pre[PER];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * NW * 64;
       const int jj = idx % kGrRows, c = idx / kGrRows;
       const int64_t r = r0 + jj;
-      qs[jj][c] = (r < r_end && c < n) ? static_cast<double>(Q[r + static_cast<int64_t>(c) * ldq]) : 0.0;
+      pre[q] = (idx < kGrRows * NP && r < r_end && c < n) ? Q[r + static_cast<int64_t>(c) * ldq] : T(0);
+    }
+  };
+  if (kPre && r_begin < r_end) fetch(r_begin);
+  int64_t since = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGrRows) {
+    __syncthreads();
+    if (kPre) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = threadIdx.x + q * NW * 64;
+        if (idx < kGrRows * NP) qs[idx % kGrRows][idx / kGrRows] = pre[q];
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < kGrRows * NP; idx += NW * 64) {
+        const int jj = idx % kGrRows, c = idx / kGrRows;
+        const int64_t r = r0 + jj;
+        qs[jj][c] = (r < r_end && c < n) ? Q[r + static_cast<int64_t>(c) * ldq] : T(0);
+      }
     }
     __syncthreads();
+    if (kPre && r0 + kGrRows < r_end) fetch(r0 + kGrRows);
 #pragma unroll
     for (int ks = 0; ks < kGrRows / 4; ++ks) {
-      double av[4], bv[4];
+      T av[4], bv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         av[t] = qs[4 * ks + lg][64 * bi + 16 * t + l16];
@@ -175,20 +350,15 @@ __global__ __launch_bounds__(640) void gram_kernel(const T* __restrict__ Q, int6
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
     }
+    since += kGrRows;
+    if (sizeof(T) == 4 && since >= kGrFlush) {
+      RCQ_GRAM_FLUSH();
+      since = 0;
+    }
   }
-  double* dst = gpart + static_cast<int64_t>(s) * NP * NP;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 64 * bi + 16 * a + drow<double>(lg, v);
-        const int c = 64 * bj + 16 * b + l16;
-        dst[r + static_cast<int64_t>(c) * NP] = acc[a][b][v];
-      }
+  RCQ_GRAM_FLUSH();
+#undef RCQ_GRAM_FLUSH
 }
-
 template <typename T>
 static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const GramPlan& gp,
                                 double* gpart, hipStream_t st) {
