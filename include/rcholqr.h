@@ -135,6 +135,29 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx,
                  const double* R, int64_t ldr, int precision, void* Q,
                  int64_t ldq, void* ws, size_t ws_bytes, void* stream);
 
+/* Reverse-mode derivative of the 2-pass factorisation (the positive-diagonal
+ * thin QR X = Q R, which Algorithm 3 returns; the paper does not treat
+ * derivatives).  Given dQ (m x n) and dR (n x n, upper triangle used),
+ *     M = R dR^T - dQ^T Q,   N = copyltu(M) (lower triangle mirrored up),
+ *     dX = (dQ + Q N) R^{-T}.
+ * Q is not stored by the forward call: it is recomputed from X and the
+ * saved R_s, R' (the `Rs`, `Rp` outputs of rcholqr_factor with passes = 2)
+ * by the same kernels, so it equals the forward Q bit for bit.  The final
+ * R^{-T} is applied by row-wise substitution (R = R' R_s is formed in FP64).
+ *  X      [in]  m x n, ldx >= m, FP64 (precision F64) or FP32 (F32/MIXED).
+ *  Rs, Rp [in]  n x n FP64, ld = n, upper triangular.
+ *  dQ     [in]  m x n, lddq >= m, same dtype as X.
+ *  dR     [in, optional] n x n FP64, ld lddr >= n; NULL means zero.
+ *  dX     [out] m x n, lddx >= m, same dtype as X; must not overlap X or dQ.
+ *  ws     workspace of rcholqr_backward_workspace_bytes(m, n, precision).
+ * Returns 0, -i for the i-th invalid argument, or RCHOLQR_ERR_HIP. */
+size_t rcholqr_backward_workspace_bytes(int64_t m, int64_t n, int precision);
+int rcholqr_backward(const void* X, int64_t m, int64_t n, int64_t ldx,
+                     const double* Rs, const double* Rp, const void* dQ,
+                     int64_t lddq, const double* dR, int64_t lddr, int precision,
+                     void* dX, int64_t lddx, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* Phase timing.  rcholqr_profile_enable(1) creates a ring of HIP events
  * (no device memory is allocated); while enabled, every rcholqr_factor call
  * records one event at each phase boundary on its own stream:

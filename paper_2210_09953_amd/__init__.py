@@ -12,10 +12,11 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, F64, F32, MIXED,
                       LibraryMissing, RCholQRError, lib, lib_path,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
                       status, error_string, fortran, empty_fortran, PHASES,
-                      profile_enable, profile_read)
+                      profile_enable, profile_read, backward)
+from .autograd import RCholQR2, rcholqr2
 
 __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
            "LibraryMissing", "RCholQRError", "lib", "lib_path",
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",
-           "profile_enable", "profile_read"]
+           "profile_enable", "profile_read", "backward", "RCholQR2", "rcholqr2"]

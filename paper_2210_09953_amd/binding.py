@@ -50,6 +50,11 @@ def lib():
     L.rcholqr_debug_theta.restype = i32
     L.rcholqr_trsm.argtypes = [vp, i64, i64, i64, dp, i64, i32, vp, i64, vp, sz, vp]
     L.rcholqr_trsm.restype = i32
+    L.rcholqr_backward_workspace_bytes.argtypes = [i64, i64, i32]
+    L.rcholqr_backward_workspace_bytes.restype = sz
+    L.rcholqr_backward.argtypes = [vp, i64, i64, i64, dp, dp, vp, i64, dp, i64, i32, vp, i64,
+                                   vp, sz, vp]
+    L.rcholqr_backward.restype = i32
     L.rcholqr_profile_enable.argtypes = [i32]
     L.rcholqr_profile_enable.restype = i32
     L.rcholqr_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
@@ -209,3 +214,27 @@ def profile_read():
     if n < 0:
         raise RCholQRError(n, "rcholqr_profile_read")
     return n, {p: float(ms[i]) for i, p in enumerate(PHASES)}
+
+
+def backward(X, Rs, Rp, dQ, dR=None, precision=None, dX=None, ws=None):
+    """dX for the 2-pass factorisation X = Q R given cotangents dQ, dR.
+
+    Q is recomputed from X, Rs, Rp (as saved by factor(..., want_factors=True))
+    by the forward kernels; dR may be None (zero)."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X, dQ = fortran(X), fortran(dQ)
+    Rs, Rp = fortran(Rs), fortran(Rp)
+    if dR is not None:
+        dR = fortran(dR.to(torch.float64))
+    m, n = X.shape
+    need = int(lib().rcholqr_backward_workspace_bytes(m, n, precision))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    if dX is None:
+        dX = empty_fortran(m, n, X.dtype, X.device)
+    code = lib().rcholqr_backward(_ptr(X), m, n, _ld(X), _ptr(Rs), _ptr(Rp), _ptr(dQ), _ld(dQ),
+                                  _ptr(dR), _ld(dR) if dR is not None else n, precision,
+                                  _ptr(dX), _ld(dX), _ptr(ws), ws.numel(), _stream())
+    _check(code, "rcholqr_backward")
+    return dX

@@ -227,6 +227,86 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   return 0;
 }
 
+namespace {
+struct BwdLayout {
+  GramPlan gp;
+  size_t pan, Tinv, Rw, Nm, Rrev, Cm, gpart, total;
+};
+BwdLayout make_bwd_layout(int64_t m, int64_t n) {
+  BwdLayout L{};
+  L.gp = make_layout(m, n, n, kGaussian, 2, kPrecF64).gp;
+  size_t off = 256;
+  const int ni = static_cast<int>(n);
+  const int64_t pe = panel_elems(ni) > dense_panel_elems(ni) ? panel_elems(ni) : dense_panel_elems(ni);
+  L.pan = off; off += align256(static_cast<size_t>(pe) * sizeof(double));
+  L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
+  L.Rw = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
+  L.Nm = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
+  L.Rrev = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
+  L.Cm = off; off += align256(static_cast<size_t>(L.gp.npg) * L.gp.npg * sizeof(double));
+  L.gpart = off; off += align256(static_cast<size_t>(L.gp.nsplit) * L.gp.npg * L.gp.npg * sizeof(double));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t rcholqr_backward_workspace_bytes(int64_t m, int64_t n, int precision) {
+  if (n < 1 || n > kMaxN || m < n || precision < 0 || precision > 2) return 0;
+  return make_bwd_layout(m, n).total;
+}
+
+int rcholqr_backward(const void* X, int64_t m, int64_t n, int64_t ldx, const double* Rs,
+                     const double* Rp, const void* dQ, int64_t lddq, const double* dR,
+                     int64_t lddr, int precision, void* dX, int64_t lddx, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (!Rs) return -5;
+  if (!Rp) return -6;
+  if (!dQ) return -7;
+  if (lddq < m) return -8;
+  if (dR && lddr < n) return -10;
+  if (precision < 0 || precision > 2) return -11;
+  if (!dX) return -12;
+  if (lddx < m) return -13;
+  if (!ws) return -14;
+  const BwdLayout L = make_bwd_layout(m, n);
+  if (ws_bytes < L.total) return -15;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f32 = precision != kPrecF64;
+  const int ni = static_cast<int>(n);
+  void* pan = at<void>(ws, L.pan);
+  double* Tinv = at<double>(ws, L.Tinv);
+  double* Rw = at<double>(ws, L.Rw);
+  double* Nm = at<double>(ws, L.Nm);
+  double* Rrev = at<double>(ws, L.Rrev);
+  double* Cm = at<double>(ws, L.Cm);
+  // Q recomputed into dX exactly as the forward pass formed it.
+  RCQ_TRY(launch_make_panels(Rs, n, ni, f32, pan, st));
+  RCQ_TRY(launch_trsm(X, f32, m, ni, ldx, pan, dX, lddx, st));
+  RCQ_TRY(launch_set_identity(Tinv, n, ni, ni, st));
+  RCQ_TRY(launch_make_panels(Rp, n, ni, false, pan, st));
+  RCQ_TRY(launch_trsm(Tinv, false, ni, ni, n, pan, Tinv, n, st));
+  RCQ_TRY(launch_make_panels(Tinv, n, ni, f32, pan, st, false));
+  RCQ_TRY(launch_trmm(dX, f32, m, ni, lddx, pan, st));
+  // dQ^T Q, then M, N = copyltu(M) and J R^T J in FP64.
+  RCQ_TRY(launch_triu_product(Rp, n, Rs, n, Rw, n, ni, st));
+  RCQ_TRY(launch_cross_gram(dQ, dX, f32, m, ni, lddq, lddx, L.gp, at<double>(ws, L.gpart), st));
+  RCQ_TRY(launch_gram_reduce_full(at<double>(ws, L.gpart), L.gp, ni, Cm, st));
+  RCQ_TRY(launch_adjoint_small(Rw, dR, lddr, Cm, L.gp.npg, ni, Nm, Rrev, st));
+  // Y = dQ + Q N (in place over Q).
+  RCQ_TRY(launch_make_dense_panels(Nm, n, ni, f32, pan, st));
+  RCQ_TRY(launch_gemm_add(dX, f32, m, ni, lddx, pan, dQ, lddq, st));
+  // dX = Y R^{-T}: row-wise substitution with J R^T J on column-reversed views.
+  RCQ_TRY(launch_make_panels(Rrev, n, ni, f32, pan, st));
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  void* dX_rev = static_cast<char*>(dX) + static_cast<size_t>(n - 1) * lddx * esz;
+  RCQ_TRY(launch_trsm(dX_rev, f32, m, ni, -lddx, pan, dX_rev, -lddx, st));
+  return 0;
+}
+
 int rcholqr_profile_enable(int on) {
   if (on && !g_prof.on) {
     for (int i = 0; i < kRing; ++i)

@@ -58,6 +58,13 @@ hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ld
 hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
                               hipStream_t st, bool negate = true);
 hipError_t launch_set_identity(double* A, int64_t lda, int rows, int cols, hipStream_t st);
+hipError_t launch_gram_reduce_full(const double* gpart, const GramPlan& gp, int n, double* G,
+                                   hipStream_t st);
+hipError_t launch_adjoint_small(const double* R, const double* dR, int64_t lddr,
+                                const double* C, int ldc, int n, double* Nm, double* Rrev,
+                                hipStream_t st);
+hipError_t launch_make_dense_panels(const double* B, int64_t ldb, int n, bool f32, void* pan,
+                                    hipStream_t st);
 hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, double* G,
                               hipStream_t st);
 
@@ -68,6 +75,15 @@ hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq,
                        const GramPlan& gp, double* gpart, hipStream_t st);
 hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,
                        hipStream_t st);
+hipError_t launch_gemm_add(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,
+                           const void* C, int64_t ldc, hipStream_t st);
+hipError_t launch_cross_gram(const void* A, const void* B, bool f32, int64_t m, int n, int64_t lda,
+                             int64_t ldb, const GramPlan& gp, double* gpart, hipStream_t st);
+
+inline int64_t dense_panel_elems(int n) {
+  const int64_t nb = (n + 15) / 16;
+  return 256 * nb * nb;
+}
 
 inline int64_t panel_elems(int n) {
   const int64_t nb = (n + 15) / 16;

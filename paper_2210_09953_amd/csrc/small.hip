@@ -439,6 +439,7 @@ __global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, in
       v = (r <= col) ? R[r + col * ldr] : 0.0;
     else
       v = (r == col) ? 1.0 : 0.0;
+    if (r == col && offdiag_sign < 0.0) v = 1.0 / v;  // the solve multiplies by 1/R_jj
   }
   pan[idx] = static_cast<T>(v);
 }
@@ -479,6 +480,82 @@ hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, do
                               hipStream_t st) {
   gram_reduce_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(gpart, gp.nsplit,
                                                                                    gp.npg, n, G);
+  return hipGetLastError();
+}
+
+// C(r, c) = sum_s gpart[s](r, c) for all r, c < n (ld npg).
+__global__ void gram_reduce_full_kernel(const double* __restrict__ gpart, int nsplit, int npg, int n,
+                                        double* __restrict__ G) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int r = idx % n, c = idx / n;
+  const int64_t stride = static_cast<int64_t>(npg) * npg;
+  const double* p = gpart + r + static_cast<int64_t>(c) * npg;
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += p[q * stride];
+  G[r + c * npg] = s;
+}
+
+hipError_t launch_gram_reduce_full(const double* gpart, const GramPlan& gp, int n, double* G,
+                                   hipStream_t st) {
+  gram_reduce_full_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(
+      gpart, gp.nsplit, gp.npg, n, G);
+  return hipGetLastError();
+}
+
+// Small step of the adjoint of the positive-diagonal thin QR X = Q R:
+//   M = R dR^T - dQ^T Q (C = dQ^T Q given), N = copyltu(M) (the lower
+//   triangle of M mirrored to the upper one), and Rrev = J R^T J, the upper
+//   triangular matrix whose row-wise solve gives dX = Y R^{-T} on
+//   column-reversed views.  All n x n, FP64.  dR may be null (zero).
+__global__ void adjoint_small_kernel(const double* __restrict__ R, const double* __restrict__ dR,
+                                     int64_t lddr, const double* __restrict__ C, int ldc, int n,
+                                     double* __restrict__ Nm, double* __restrict__ Rrev) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int a = idx % n, b = idx / n;
+  // N(a, b) = M(max, min)
+  const int i = (a >= b) ? a : b, j = (a >= b) ? b : a;
+  double s = 0.0;  // (R dR^T)(i, j) = sum_{l >= i} R(i, l) dR(j, l), dR(j, l) = 0 for l < j
+  if (dR)
+    for (int l = i; l < n; ++l) s += R[i + l * n] * dR[j + l * lddr];
+  Nm[a + b * n] = s - C[i + j * ldc];
+  // Rrev(a, b) = R(n-1-b, n-1-a)
+  Rrev[a + b * n] = R[(n - 1 - b) + (n - 1 - a) * n];
+}
+
+hipError_t launch_adjoint_small(const double* R, const double* dR, int64_t lddr,
+                                const double* C, int ldc, int n, double* Nm, double* Rrev,
+                                hipStream_t st) {
+  adjoint_small_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(
+      R, dR, lddr, C, ldc, n, Nm, Rrev);
+  return hipGetLastError();
+}
+
+// Dense panel packing: panel b holds all rows 0..16 NB - 1 of columns
+// 16b..16b+15, row-major, zero-padded.
+template <typename T>
+__global__ void make_dense_panels_kernel(const double* __restrict__ B, int64_t ldb, int n,
+                                         T* __restrict__ pan, int np) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = 16ll * np;
+  if (idx >= per * (np / 16)) return;
+  const int b = static_cast<int>(idx / per);
+  const int64_t off = idx - per * b;
+  const int r = static_cast<int>(off / 16), c = static_cast<int>(off % 16);
+  const int col = 16 * b + c;
+  pan[idx] = static_cast<T>((r < n && col < n) ? B[r + col * ldb] : 0.0);
+}
+
+hipError_t launch_make_dense_panels(const double* B, int64_t ldb, int n, bool f32, void* pan,
+                                    hipStream_t st) {
+  const int np = static_cast<int>(round_up(n, 16));
+  const int64_t total = dense_panel_elems(n);
+  const unsigned grid = static_cast<unsigned>(ceil_div(total, 256));
+  if (f32)
+    make_dense_panels_kernel<float><<<grid, 256, 0, st>>>(B, ldb, n, static_cast<float*>(pan), np);
+  else
+    make_dense_panels_kernel<double><<<grid, 256, 0, st>>>(B, ldb, n, static_cast<double*>(pan), np);
   return hipGetLastError();
 }
 

@@ -42,19 +42,29 @@ __device__ __forceinline__ void panel_store(T* __restrict__ buf, int b, const T 
     if (q <= b) buf[threadIdx.x + 256 * q] = st[q];
 }
 
+// Rows per wave: 16 x RB (two 16-row blocks share every A operand in FP32;
+// FP64 keeps one to stay within the register file).
+#ifndef RCQ_F32_ROW_BLOCKS
+#define RCQ_F32_ROW_BLOCKS 1
+#endif
+template <typename T>
+struct RowBlocks {
+  static constexpr int value = sizeof(T) == 4 ? RCQ_F32_ROW_BLOCKS : 1;
+};
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n, int64_t ldx,
                                                    const T* __restrict__ pan, T* Q, int64_t ldq) {
   typedef typename Acc4<T>::type A4;
-  __shared__ T tr[4][16][17];
+  constexpr int RB = RowBlocks<T>::value;
+  __shared__ T tq[4][RB][16][4];
   __shared__ T pbuf[2][256 * NB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
-  const bool rok = row < m;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64 * RB + wave * 16 * RB + l16;
   // A rows permuted so that D element v of lane group lg is panel column 4 lg + v.
   const int acol = arow_for_blocked_d<T>(l16);
-  T qa[4 * NB];
+  T qa[RB][4 * NB];
   T stg[NB];
 
   panel_fetch<T, NB>(pan, 0, stg);
@@ -64,62 +74,79 @@ __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n,
   for (int b = 0; b < NB; ++b) {
     const T* pb = pbuf[b & 1];
     if (b + 1 < NB) panel_fetch<T, NB>(pan, b + 1, stg);  // overlap with this panel
-    A4 D, E;
+    A4 D[RB], E[RB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = 16 * b + 4 * lg + v;
-      D[v] = (rok && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
-      E[v] = T(0);
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t row = row0 + 16 * rb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + 4 * lg + v;
+        D[rb][v] = (row < m && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
+        E[rb][v] = T(0);
+      }
     }
     // D <- X_b^T - R_{<b,b}^T Q_{<b}^T (A = -R^T block, B = Q^T block), two chains.
 #pragma unroll
     for (int s = 0; s < 4 * (NB - 1); s += 2)
       if (s < 4 * b) {
-        D = mfma16x16x4(pb[(4 * s + lg) * 16 + acol], qa[s], D);
-        E = mfma16x16x4(pb[(4 * (s + 1) + lg) * 16 + acol], qa[s + 1], E);
+        const T a0 = pb[(4 * s + lg) * 16 + acol];
+        const T a1 = pb[(4 * (s + 1) + lg) * 16 + acol];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          D[rb] = mfma16x16x4(a0, qa[rb][s], D[rb]);
+          E[rb] = mfma16x16x4(a1, qa[rb][s + 1], E[rb]);
+        }
       }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) D[v] += E[v];
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) D[rb][v] += E[rb][v];
 
-    // Diagonal block: column c = 4*lg + v of the panel lives in lane group lg.
+    // Diagonal block (its diagonal holds 1/R_jj): lane group gs substitutes
+    // its 4 columns, the solved 16 x 4 piece goes through LDS into the B
+    // layout (which is also the register copy of Q for later panels), and
+    // one matrix-core product subtracts it from the panel's later columns.
     const T* dgb = pb + 16 * b * 16;
 #pragma unroll
     for (int gs = 0; gs < 4; ++gs) {
-      if (lg == gs) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        T x[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          T x = D[v];
+          T t = D[rb][v];
 #pragma unroll
-          for (int vp = 0; vp < v; ++vp) x -= D[vp] * dgb[(4 * gs + vp) * 16 + 4 * gs + v];
-          D[v] = x / dgb[(4 * gs + v) * 16 + 4 * gs + v];
+          for (int vp = 0; vp < v; ++vp) t -= x[vp] * dgb[(4 * gs + vp) * 16 + 4 * gs + v];
+          x[v] = t * dgb[(4 * gs + v) * 16 + 4 * gs + v];
         }
-      }
-      if (gs < 3) {
-        T q[4];
-#pragma unroll
-        for (int vp = 0; vp < 4; ++vp) q[vp] = __shfl(D[vp], l16 + 16 * gs, 64);
-        if (lg > gs) {
+        if (lg == gs) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            T x = D[v];
-#pragma unroll
-            for (int vp = 0; vp < 4; ++vp) x -= q[vp] * dgb[(4 * gs + vp) * 16 + 4 * lg + v];
-            D[v] = x;
+            D[rb][v] = x[v];
+            tq[wave][rb][l16][v] = x[v];
           }
         }
       }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = 16 * b + 4 * lg + v;
-      if (rok && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[v];
-    }
-    if (b + 1 < NB) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) tr[wave][4 * lg + v][l16] = D[v];
       wave_sync();
 #pragma unroll
-      for (int s = 0; s < 4; ++s) qa[4 * b + s] = tr[wave][4 * s + lg][l16];
+      for (int rb = 0; rb < RB; ++rb) qa[rb][4 * b + gs] = tq[wave][rb][l16][lg];
+      wave_sync();
+      if (gs < 3) {
+        const T a = (acol > 4 * gs + 3) ? -dgb[(4 * gs + lg) * 16 + acol] : T(0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) D[rb] = mfma16x16x4(a, qa[rb][4 * b + gs], D[rb]);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t row = row0 + 16 * rb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + 4 * lg + v;
+        if (row < m && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[rb][v];
+      }
+    }
+    if (b + 1 < NB) {
       panel_store<T, NB>(pbuf[(b + 1) & 1], b + 1, stg);
       __syncthreads();
     }
@@ -129,7 +156,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n,
 template <typename T>
 static hipError_t trsm_dispatch(int nb, const T* X, int64_t m, int n, int64_t ldx, const T* pan,
                                 T* Q, int64_t ldq, hipStream_t st) {
-  const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+  const unsigned grid = static_cast<unsigned>(ceil_div(m, 64 * RowBlocks<T>::value));
 #define RCQ_TR_CASE(NBV)                                                       \
   case NBV:                                                                    \
     trsm_kernel<T, NBV><<<grid, 256, 0, st>>>(X, m, n, ldx, pan, Q, ldq);      \
@@ -162,61 +189,101 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
 // solve: a wave loads its 16 rows of Q1 into registers first (so the
 // product can overwrite them), then each 16-column output panel is a chain
 // of 16x16x4 matrix-core products with no diagonal solve.
-template <typename T, int NB>
+// FULL = false: Q <- Q T for upper triangular T (panel b holds rows 0..16b+15).
+// FULL = true:  Q <- C + Q B for a dense n x n B (panel b holds all rows);
+// C (ld ldc) may be null.  Both work in place.
+template <typename T, int NB, bool FULL>
 __global__ __launch_bounds__(256) void trmm_kernel(T* Q, int64_t m, int n, int64_t ldq,
-                                                   const T* __restrict__ pan) {
+                                                   const T* __restrict__ pan,
+                                                   const T* __restrict__ C, int64_t ldc) {
   typedef typename Acc4<T>::type A4;
+  constexpr int RB = RowBlocks<T>::value;
   __shared__ T pbuf[2][256 * NB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
-  const bool rok = row < m;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64 * RB + wave * 16 * RB + l16;
   const int acol = arow_for_blocked_d<T>(l16);
-  T qa[4 * NB];
+  T qa[RB][4 * NB];
   T stg[NB];
 #pragma unroll
-  for (int s = 0; s < 4 * NB; ++s) {
-    const int col = 4 * s + lg;
-    qa[s] = (rok && col < n) ? Q[row + static_cast<int64_t>(col) * ldq] : T(0);
+  for (int rb = 0; rb < RB; ++rb) {
+    const int64_t row = row0 + 16 * rb;
+#pragma unroll
+    for (int s = 0; s < 4 * NB; ++s) {
+      const int col = 4 * s + lg;
+      qa[rb][s] = (row < m && col < n) ? Q[row + static_cast<int64_t>(col) * ldq] : T(0);
+    }
   }
-  panel_fetch<T, NB>(pan, 0, stg);
-  panel_store<T, NB>(pbuf[0], 0, stg);
+  auto fetch = [&](int b) {
+    if (FULL) {
+      const T* pb = pan + 256 * NB * b;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) stg[q] = pb[threadIdx.x + 256 * q];
+    } else {
+      panel_fetch<T, NB>(pan, b, stg);
+    }
+  };
+  auto store = [&](T* buf, int b) {
+    if (FULL) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) buf[threadIdx.x + 256 * q] = stg[q];
+    } else {
+      panel_store<T, NB>(buf, b, stg);
+    }
+  };
+  fetch(0);
+  store(pbuf[0], 0);
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const T* pb = pbuf[b & 1];
-    if (b + 1 < NB) panel_fetch<T, NB>(pan, b + 1, stg);
-    A4 D, E;
+    if (b + 1 < NB) fetch(b + 1);
+    A4 D[RB], E[RB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      D[v] = T(0);
-      E[v] = T(0);
-    }
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int s = 0; s < 4 * NB; s += 2)
-      if (s < 4 * (b + 1)) {
-        D = mfma16x16x4(pb[(4 * s + lg) * 16 + acol], qa[s], D);
-        E = mfma16x16x4(pb[(4 * (s + 1) + lg) * 16 + acol], qa[s + 1], E);
+      for (int v = 0; v < 4; ++v) {
+        D[rb][v] = T(0);
+        E[rb][v] = T(0);
       }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = 16 * b + 4 * lg + v;
-      if (rok && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[v] + E[v];
+    for (int s = 0; s < 4 * NB; s += 2)
+      if (FULL || s < 4 * (b + 1)) {
+        const T a0 = pb[(4 * s + lg) * 16 + acol];
+        const T a1 = pb[(4 * (s + 1) + lg) * 16 + acol];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          D[rb] = mfma16x16x4(a0, qa[rb][s], D[rb]);
+          E[rb] = mfma16x16x4(a1, qa[rb][s + 1], E[rb]);
+        }
+      }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t row = row0 + 16 * rb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + 4 * lg + v;
+        if (row < m && col < n) {
+          T y = D[rb][v] + E[rb][v];
+          if (C) y += C[row + static_cast<int64_t>(col) * ldc];
+          Q[row + static_cast<int64_t>(col) * ldq] = y;
+        }
+      }
     }
     if (b + 1 < NB) {
-      panel_store<T, NB>(pbuf[(b + 1) & 1], b + 1, stg);
+      store(pbuf[(b + 1) & 1], b + 1);
       __syncthreads();
     }
   }
 }
 
-template <typename T>
+template <typename T, bool FULL>
 static hipError_t trmm_dispatch(int nb, T* Q, int64_t m, int n, int64_t ldq, const T* pan,
-                                hipStream_t st) {
-  const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
-#define RCQ_TM_CASE(NBV)                                                  \
-  case NBV:                                                               \
-    trmm_kernel<T, NBV><<<grid, 256, 0, st>>>(Q, m, n, ldq, pan);         \
+                                const T* C, int64_t ldc, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>(ceil_div(m, 64 * RowBlocks<T>::value));
+#define RCQ_TM_CASE(NBV)                                                            \
+  case NBV:                                                                         \
+    trmm_kernel<T, NBV, FULL><<<grid, 256, 0, st>>>(Q, m, n, ldq, pan, C, ldc);     \
     break;
   switch (nb) {
     RCQ_TM_CASE(1) RCQ_TM_CASE(2) RCQ_TM_CASE(3) RCQ_TM_CASE(4) RCQ_TM_CASE(5) RCQ_TM_CASE(6)
@@ -233,10 +300,23 @@ hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const v
   if (m == 0) return hipSuccess;
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32)
-    return trmm_dispatch<float>(nb, static_cast<float*>(Q), m, n, ldq,
-                                static_cast<const float*>(pan), st);
-  return trmm_dispatch<double>(nb, static_cast<double*>(Q), m, n, ldq,
-                               static_cast<const double*>(pan), st);
+    return trmm_dispatch<float, false>(nb, static_cast<float*>(Q), m, n, ldq,
+                                       static_cast<const float*>(pan), nullptr, 0, st);
+  return trmm_dispatch<double, false>(nb, static_cast<double*>(Q), m, n, ldq,
+                                      static_cast<const double*>(pan), nullptr, 0, st);
+}
+
+hipError_t launch_gemm_add(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,
+                           const void* C, int64_t ldc, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  if (f32)
+    return trmm_dispatch<float, true>(nb, static_cast<float*>(Q), m, n, ldq,
+                                      static_cast<const float*>(pan), static_cast<const float*>(C),
+                                      ldc, st);
+  return trmm_dispatch<double, true>(nb, static_cast<double*>(Q), m, n, ldq,
+                                     static_cast<const double*>(pan), static_cast<const double*>(C),
+                                     ldc, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -251,27 +331,39 @@ struct GramRows {
   static constexpr int value = sizeof(T) == 4 ? 32 : 16;
 };
 
-template <typename T, int NBB>
-__global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T* __restrict__ Q, int64_t m, int n,
-                                                   int64_t ldq, int64_t rows_per_split,
-                                                   double* __restrict__ gpart) {
+// CROSS = false: A = Q^T Q, upper 64 x 64 blocks.  CROSS = true: C = Q^T B
+// for a second tall matrix B (ld ldb), all blocks (used by the adjoint).
+template <typename T, int NBB, bool CROSS>
+__global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) void gram_kernel(
+    const T* __restrict__ Q, int64_t m, int n, int64_t ldq, int64_t rows_per_split,
+    double* __restrict__ gpart, const T* __restrict__ B, int64_t ldb) {
   typedef typename Acc4<T>::type A4;
   constexpr int NP = 64 * NBB;
-  constexpr int NW = NBB * (NBB + 1) / 2;
+  constexpr int NW = CROSS ? NBB * NBB : NBB * (NBB + 1) / 2;
   constexpr int kGrRows = GramRows<T>::value;
-  __shared__ T qs[kGrRows][NP + 1];
+  // Column-major staging: rows of a column are contiguous (conflict-free
+  // stores of the coalesced loads); the row stride kLd = kGrRows + 4 words
+  // spreads the 16 columns x 4 rows of an operand read over distinct banks.
+  constexpr int kLd = kGrRows + 4;
+  __shared__ T qs[NP][kLd];
+  __shared__ T bs[CROSS ? NP : 1][CROSS ? kLd : 1];
   const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
   int bi = 0, bj = 0, cnt = 0;
-  for (int j = 0; j < NBB; ++j)
-    for (int i = 0; i <= j; ++i) {
-      if (cnt == wave) {
-        bi = i;
-        bj = j;
+  if (CROSS) {
+    bi = wave % NBB;
+    bj = wave / NBB;
+  } else {
+    for (int j = 0; j < NBB; ++j)
+      for (int i = 0; i <= j; ++i) {
+        if (cnt == wave) {
+          bi = i;
+          bj = j;
+        }
+        ++cnt;
       }
-      ++cnt;
-    }
+  }
   const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   double* dst = gpart + static_cast<int64_t>(s) * NP * NP;
@@ -306,7 +398,7 @@ __global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T*
   } while (0)
   // FP32: register prefetch of the next stage (kGrRows x NP values over
   // NW*64 threads).  FP64 (accumulators twice as large): direct staging.
-  constexpr bool kPre = sizeof(T) == 4;
+  constexpr bool kPre = sizeof(T) == 4 && !CROSS;
   constexpr int PER = kPre ? (kGrRows * NP + NW * 64 - 1) / (NW * 64) : 1;
   T pre[PER];
   auto fetch = [&](int64_t r0) {
@@ -326,13 +418,15 @@ __global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T*
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int idx = threadIdx.x + q * NW * 64;
-        if (idx < kGrRows * NP) qs[idx % kGrRows][idx / kGrRows] = pre[q];
+        if (idx < kGrRows * NP) qs[idx / kGrRows][idx % kGrRows] = pre[q];
       }
     } else {
       for (int idx = threadIdx.x; idx < kGrRows * NP; idx += NW * 64) {
         const int jj = idx % kGrRows, c = idx / kGrRows;
         const int64_t r = r0 + jj;
-        qs[jj][c] = (r < r_end && c < n) ? Q[r + static_cast<int64_t>(c) * ldq] : T(0);
+        const bool in = r < r_end && c < n;
+        qs[c][jj] = in ? Q[r + static_cast<int64_t>(c) * ldq] : T(0);
+        if (CROSS) bs[c][jj] = in ? B[r + static_cast<int64_t>(c) * ldb] : T(0);
       }
     }
     __syncthreads();
@@ -342,8 +436,8 @@ __global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T*
       T av[4], bv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        av[t] = qs[4 * ks + lg][64 * bi + 16 * t + l16];
-        bv[t] = qs[4 * ks + lg][64 * bj + 16 * t + l16];
+        av[t] = qs[64 * bi + 16 * t + l16][4 * ks + lg];
+        bv[t] = CROSS ? bs[64 * bj + 16 * t + l16][4 * ks + lg] : qs[64 * bj + 16 * t + l16][4 * ks + lg];
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -359,15 +453,16 @@ __global__ __launch_bounds__(64 * NBB * (NBB + 1) / 2) void gram_kernel(const T*
   RCQ_GRAM_FLUSH();
 #undef RCQ_GRAM_FLUSH
 }
-template <typename T>
+template <typename T, bool CROSS>
 static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const GramPlan& gp,
-                                double* gpart, hipStream_t st) {
+                                double* gpart, const T* B, int64_t ldb, hipStream_t st) {
   const unsigned grid = static_cast<unsigned>(gp.nsplit);
+  auto nw = [](int b) { return CROSS ? b * b : b * (b + 1) / 2; };
   switch (gp.nbb) {
-    case 1: gram_kernel<T, 1><<<grid, 64, 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart); break;
-    case 2: gram_kernel<T, 2><<<grid, 192, 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart); break;
-    case 3: gram_kernel<T, 3><<<grid, 384, 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart); break;
-    case 4: gram_kernel<T, 4><<<grid, 640, 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart); break;
+    case 1: gram_kernel<T, 1, CROSS><<<grid, 64 * nw(1), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
+    case 2: gram_kernel<T, 2, CROSS><<<grid, 64 * nw(2), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
+    case 3: gram_kernel<T, 3, CROSS><<<grid, 64 * nw(3), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
+    case 4: gram_kernel<T, 4, CROSS><<<grid, 64 * nw(4), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -375,8 +470,18 @@ static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const
 
 hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq, const GramPlan& gp,
                        double* gpart, hipStream_t st) {
-  if (f32) return gram_dispatch<float>(static_cast<const float*>(Q), m, n, ldq, gp, gpart, st);
-  return gram_dispatch<double>(static_cast<const double*>(Q), m, n, ldq, gp, gpart, st);
+  if (f32)
+    return gram_dispatch<float, false>(static_cast<const float*>(Q), m, n, ldq, gp, gpart, nullptr, 0, st);
+  return gram_dispatch<double, false>(static_cast<const double*>(Q), m, n, ldq, gp, gpart, nullptr, 0, st);
+}
+
+hipError_t launch_cross_gram(const void* A, const void* B, bool f32, int64_t m, int n, int64_t lda,
+                             int64_t ldb, const GramPlan& gp, double* gpart, hipStream_t st) {
+  if (f32)
+    return gram_dispatch<float, true>(static_cast<const float*>(A), m, n, lda, gp, gpart,
+                                      static_cast<const float*>(B), ldb, st);
+  return gram_dispatch<double, true>(static_cast<const double*>(A), m, n, lda, gp, gpart,
+                                     static_cast<const double*>(B), ldb, st);
 }
 
 }  // namespace rcq
