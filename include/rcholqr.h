@@ -135,6 +135,39 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx,
                  const double* R, int64_t ldr, int precision, void* Q,
                  int64_t ldq, void* ws, size_t ws_bytes, void* stream);
 
+/* Batched factorisation of independent problems (for example the panels of
+ * a block Krylov method, Section 3.2) with one sketch kind, pass count and
+ * precision.  `probs` is a HOST array of `batch` descriptors; every X, Q, R
+ * inside is a device pointer with the same rules as rcholqr_factor (R is
+ * n x n FP64, Q has X's dtype).  Instance i uses its own slice of `ws`
+ * (size rcholqr_batched_workspace_bytes()).  The call fans the instances
+ * out over an internal pool of 8 non-blocking streams forked from and
+ * joined back to `stream` with events, performs no allocation, memset or
+ * synchronisation, and can therefore be captured into a HIP graph and
+ * replayed (the pool is created on the first call, outside any capture).
+ * Returns 0, -i for an invalid argument i, RCHOLQR_ERR_BATCH_ENTRY - j if
+ * problem j is invalid, or RCHOLQR_ERR_HIP. */
+typedef struct rcholqr_problem {
+  const void* X;
+  int64_t m, n, ldx, k;
+  uint64_t seed;
+  void* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+} rcholqr_problem;
+#define RCHOLQR_ERR_BATCH_ENTRY (-2000000)
+size_t rcholqr_batched_workspace_bytes(const rcholqr_problem* probs, int batch,
+                                       int sketch_kind, int passes, int precision);
+int rcholqr_factor_batched(const rcholqr_problem* probs, int batch,
+                           int sketch_kind, int passes, int precision, void* ws,
+                           size_t ws_bytes, void* stream);
+/* Status words of a completed batched call (synchronises): info[i] for
+ * problem i, same codes as rcholqr_status. */
+int rcholqr_batched_status(const rcholqr_problem* probs, int batch,
+                           int sketch_kind, int passes, int precision,
+                           const void* ws, int* info);
+
 /* Reverse-mode derivative of the 2-pass factorisation (the positive-diagonal
  * thin QR X = Q R, which Algorithm 3 returns; the paper does not treat
  * derivatives).  Given dQ (m x n) and dR (n x n, upper triangle used),

@@ -11,6 +11,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 
+class Problem(ctypes.Structure):
+    """Mirror of rcholqr_problem (include/rcholqr.h)."""
+    _fields_ = [("X", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("k", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64), ("R", ctypes.c_void_p),
+                ("ldr", ctypes.c_int64)]
+
+
 class LibraryMissing(RuntimeError):
     pass
 
@@ -55,6 +63,13 @@ def lib():
     L.rcholqr_backward.argtypes = [vp, i64, i64, i64, dp, dp, vp, i64, dp, i64, i32, vp, i64,
                                    vp, sz, vp]
     L.rcholqr_backward.restype = i32
+    L.rcholqr_batched_workspace_bytes.argtypes = [ctypes.POINTER(Problem), i32, i32, i32, i32]
+    L.rcholqr_batched_workspace_bytes.restype = sz
+    L.rcholqr_factor_batched.argtypes = [ctypes.POINTER(Problem), i32, i32, i32, i32, vp, sz, vp]
+    L.rcholqr_factor_batched.restype = i32
+    L.rcholqr_batched_status.argtypes = [ctypes.POINTER(Problem), i32, i32, i32, i32, vp,
+                                         ctypes.POINTER(i32)]
+    L.rcholqr_batched_status.restype = i32
     L.rcholqr_profile_enable.argtypes = [i32]
     L.rcholqr_profile_enable.restype = i32
     L.rcholqr_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
@@ -238,3 +253,58 @@ def backward(X, Rs, Rp, dQ, dR=None, precision=None, dX=None, ws=None):
                                   _ptr(dX), _ld(dX), _ptr(ws), ws.numel(), _stream())
     _check(code, "rcholqr_backward")
     return dX
+
+
+class BatchedFactor:
+    """A fixed batch of independent factorisations (one kind, pass count and
+    precision), its outputs and its workspace.  run() enqueues one
+    rcholqr_factor_batched call on the current stream; capture() records it
+    in a HIP graph (torch.cuda.CUDAGraph) and replay() launches that graph."""
+
+    def __init__(self, Xs, ks, seeds, kind=RADEMACHER, passes=2, precision=MIXED):
+        self.Xs = [fortran(X) for X in Xs]
+        self.kind, self.passes, self.precision = kind, passes, precision
+        dt = _dtype_for(precision)
+        for X in self.Xs:
+            if X.dtype != dt:
+                raise TypeError(f"every X must be {dt} for precision {precision}")
+        self.Qs = [empty_fortran(X.shape[0], X.shape[1], dt, X.device) for X in self.Xs]
+        self.Rs = [empty_fortran(X.shape[1], X.shape[1], torch.float64, X.device)
+                   for X in self.Xs]
+        n = len(self.Xs)
+        self.probs = (Problem * n)()
+        for i, (X, Q, R) in enumerate(zip(self.Xs, self.Qs, self.Rs)):
+            self.probs[i] = Problem(X.data_ptr(), X.shape[0], X.shape[1], _ld(X), int(ks[i]),
+                                    int(seeds[i]), Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R))
+        need = int(lib().rcholqr_batched_workspace_bytes(self.probs, n, kind, passes, precision))
+        if need == 0:
+            raise RCholQRError(-1, "invalid batched problem")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=self.Xs[0].device)
+        self.graph = None
+
+    def run(self):
+        code = lib().rcholqr_factor_batched(self.probs, len(self.Xs), self.kind, self.passes,
+                                            self.precision, _ptr(self.ws), self.ws.numel(),
+                                            _stream())
+        _check(code, "rcholqr_factor_batched")
+        return self.Qs, self.Rs
+
+    def capture(self):
+        self.run()                       # creates the stream pool outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.Qs, self.Rs
+
+    def status(self):
+        n = len(self.Xs)
+        info = (ctypes.c_int * n)()
+        _check(lib().rcholqr_batched_status(self.probs, n, self.kind, self.passes, self.precision,
+                                            _ptr(self.ws), info), "rcholqr_batched_status")
+        return [int(v) for v in info]

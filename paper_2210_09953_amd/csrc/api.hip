@@ -157,10 +157,14 @@ size_t rcholqr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
   return make_layout(m, n, k, sketch_kind, passes, precision).total;
 }
 
-int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
-                   int sketch_kind, int passes, int precision, void* Q, int64_t ldq, double* R,
-                   int64_t ldr, double* S, int64_t lds, double* Rs, double* Rp, void* ws,
-                   size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the single and batched entry points (0 or -arg).
+int check_factor_args(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+                      int sketch_kind, int passes, int precision, const void* Q, int64_t ldq,
+                      const double* R, int64_t ldr, const double* S, int64_t lds) {
   if (!X) return -1;
   if (n < 1 || n > kMaxN) return -3;
   if (m < n) return -2;
@@ -175,41 +179,44 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   if (!R) return -12;
   if (ldr < n) return -13;
   if (S && lds < k) return -15;
-  if (!ws) return -18;
-  const Layout L = make_layout(m, n, k, sketch_kind, passes, precision);
-  if (ws_bytes < L.total) return -19;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  return 0;
+}
+
+// The launch sequence of Algorithm 2 / 3 for one problem on one stream.
+int factor_one(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
+               int sketch_kind, int passes, int precision, void* Q, int64_t ldq, double* R,
+               int64_t ldr, double* S, int64_t lds, double* Rs, double* Rp, void* ws,
+               const Layout& L, hipStream_t st, bool profile) {
   const bool f32 = precision != kPrecF64;
   const int ni = static_cast<int>(n), ki = static_cast<int>(k);
   int* status = at<int>(ws, L.status);
   double* P = at<double>(ws, L.P);
   double* Rsw = at<double>(ws, L.Rs);
   void* pan = at<void>(ws, L.pan);
-
-  prof_begin(st);
+  if (profile) prof_begin(st);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
                                 at<double>(ws, L.part), P, k, st));
   else
     RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
                           at<uint32_t>(ws, L.keys), P, k, st));
-  prof_mark(1, st);
+  if (profile) prof_mark(1, st);
   RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
                              at<double>(ws, L.T), S, lds, Rsw, passes == 1 ? R : nullptr, ldr,
                              status, st));
   if (Rs) RCQ_TRY(launch_copy_upper(Rsw, n, Rs, n, ni, st));
   RCQ_TRY(launch_make_panels(Rsw, n, ni, f32, pan, st));
-  prof_mark(2, st);
+  if (profile) prof_mark(2, st);
   RCQ_TRY(launch_trsm(X, f32, m, ni, ldx, pan, Q, ldq, st));
-  prof_mark(3, st);
+  if (profile) prof_mark(3, st);
   if (passes == 1) {
-    prof_end();
+    if (profile) prof_end();
     return 0;
   }
   double* G = at<double>(ws, L.G);
   RCQ_TRY(launch_gram(Q, f32, m, ni, ldq, L.gp, at<double>(ws, L.gpart), st));
   RCQ_TRY(launch_gram_reduce(at<double>(ws, L.gpart), L.gp, ni, G, st));
-  prof_mark(4, st);
+  if (profile) prof_mark(4, st);
   RCQ_TRY(launch_cholesky(G, ni, L.gp.npg, status, st));
   RCQ_TRY(launch_triu_product(G, L.gp.npg, Rsw, n, R, ldr, ni, st));
   if (Rp) RCQ_TRY(launch_copy_upper(G, L.gp.npg, Rp, n, ni, st));
@@ -220,10 +227,123 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, false, pan, st));
   RCQ_TRY(launch_trsm(Tinv, false, ni, ni, n, pan, Tinv, n, st));
   RCQ_TRY(launch_make_panels(Tinv, n, ni, f32, pan, st, false));
-  prof_mark(5, st);
+  if (profile) prof_mark(5, st);
   RCQ_TRY(launch_trmm(Q, f32, m, ni, ldq, pan, st));
-  prof_mark(6, st);
-  prof_end();
+  if (profile) {
+    prof_mark(6, st);
+    prof_end();
+  }
+  return 0;
+}
+
+// Streams and fork/join events of the batched entry point (created once,
+// default priority, non-blocking; no device memory is allocated).
+constexpr int kPool = 8;
+struct Pool {
+  bool ready = false;
+  hipStream_t s[kPool];
+  hipEvent_t fork, join[kPool];
+};
+Pool g_pool;
+
+int ensure_pool() {
+  if (g_pool.ready) return 0;
+  for (int i = 0; i < kPool; ++i) {
+    if (hipStreamCreateWithFlags(&g_pool.s[i], hipStreamNonBlocking) != hipSuccess) return RCHOLQR_ERR_HIP;
+    if (hipEventCreateWithFlags(&g_pool.join[i], hipEventDisableTiming) != hipSuccess) return RCHOLQR_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&g_pool.fork, hipEventDisableTiming) != hipSuccess) return RCHOLQR_ERR_HIP;
+  g_pool.ready = true;
+  return 0;
+}
+
+size_t batched_offset(const rcholqr_problem* probs, int i, int kind, int passes, int precision) {
+  size_t off = 0;
+  for (int j = 0; j < i; ++j)
+    off += align256(make_layout(probs[j].m, probs[j].n, probs[j].k, kind, passes, precision).total);
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
+                   int sketch_kind, int passes, int precision, void* Q, int64_t ldq, double* R,
+                   int64_t ldr, double* S, int64_t lds, double* Rs, double* Rp, void* ws,
+                   size_t ws_bytes, void* stream) {
+  const int bad = check_factor_args(X, m, n, ldx, k, sketch_kind, passes, precision, Q, ldq, R,
+                                    ldr, S, lds);
+  if (bad) return bad;
+  if (!ws) return -18;
+  const Layout L = make_layout(m, n, k, sketch_kind, passes, precision);
+  if (ws_bytes < L.total) return -19;
+  return factor_one(X, m, n, ldx, k, seed, sketch_kind, passes, precision, Q, ldq, R, ldr, S, lds,
+                    Rs, Rp, ws, L, static_cast<hipStream_t>(stream), true);
+}
+
+size_t rcholqr_batched_workspace_bytes(const rcholqr_problem* probs, int batch, int sketch_kind,
+                                       int passes, int precision) {
+  if (!probs || batch < 1) return 0;
+  for (int i = 0; i < batch; ++i)
+    if (!valid_dims(probs[i].m, probs[i].n, probs[i].k)) return 0;
+  if (sketch_kind < 0 || sketch_kind > 2 || passes < 1 || passes > 2 || precision < 0 ||
+      precision > 2)
+    return 0;
+  return batched_offset(probs, batch, sketch_kind, passes, precision);
+}
+
+int rcholqr_factor_batched(const rcholqr_problem* probs, int batch, int sketch_kind, int passes,
+                           int precision, void* ws, size_t ws_bytes, void* stream) {
+  if (!probs) return -1;
+  if (batch < 1) return -2;
+  if (sketch_kind < 0 || sketch_kind > 2) return -3;
+  if (passes < 1 || passes > 2) return -4;
+  if (precision < 0 || precision > 2) return -5;
+  for (int i = 0; i < batch; ++i) {
+    const rcholqr_problem& p = probs[i];
+    if (check_factor_args(p.X, p.m, p.n, p.ldx, p.k, sketch_kind, passes, precision, p.Q, p.ldq,
+                          p.R, p.ldr, nullptr, 0) != 0)
+      return RCHOLQR_ERR_BATCH_ENTRY - i;
+  }
+  if (!ws) return -6;
+  if (ws_bytes < batched_offset(probs, batch, sketch_kind, passes, precision)) return -7;
+  if (ensure_pool() != 0) return RCHOLQR_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int used = batch < kPool ? batch : kPool;
+  RCQ_TRY(hipEventRecord(g_pool.fork, st));
+  for (int q = 0; q < used; ++q) RCQ_TRY(hipStreamWaitEvent(g_pool.s[q], g_pool.fork, 0));
+  size_t off = 0;
+  int rc = 0;
+  for (int i = 0; i < batch && rc == 0; ++i) {
+    const rcholqr_problem& p = probs[i];
+    const Layout L = make_layout(p.m, p.n, p.k, sketch_kind, passes, precision);
+    rc = factor_one(p.X, p.m, p.n, p.ldx, p.k, p.seed, sketch_kind, passes, precision, p.Q,
+                    p.ldq, p.R, p.ldr, nullptr, 0, nullptr, nullptr,
+                    static_cast<char*>(ws) + off, L, g_pool.s[i % kPool], false);
+    off += align256(L.total);
+  }
+  // Join every forked stream even after a failed launch, so that a stream
+  // capture in progress is left well formed.
+  for (int q = 0; q < used; ++q) {
+    RCQ_TRY(hipEventRecord(g_pool.join[q], g_pool.s[q]));
+    RCQ_TRY(hipStreamWaitEvent(st, g_pool.join[q], 0));
+  }
+  return rc;
+}
+
+int rcholqr_batched_status(const rcholqr_problem* probs, int batch, int sketch_kind, int passes,
+                           int precision, const void* ws, int* info) {
+  if (!probs || batch < 1 || !ws || !info) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
+  size_t off = 0;
+  for (int i = 0; i < batch; ++i) {
+    const Layout L = make_layout(probs[i].m, probs[i].n, probs[i].k, sketch_kind, passes, precision);
+    if (hipMemcpy(&info[i], static_cast<const char*>(ws) + off + L.status, sizeof(int),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return RCHOLQR_ERR_HIP;
+    off += align256(L.total);
+  }
   return 0;
 }
 

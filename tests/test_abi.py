@@ -20,7 +20,9 @@ def test_header_declares_entry_points():
     names = _declared()
     for n in ["rcholqr_workspace_bytes", "rcholqr_factor", "rcholqr_status",
               "rcholqr_sketch", "rcholqr_debug_theta", "rcholqr_trsm",
-              "rcholqr_error_string"]:
+              "rcholqr_error_string", "rcholqr_batched_workspace_bytes",
+              "rcholqr_factor_batched", "rcholqr_batched_status",
+              "rcholqr_backward_workspace_bytes", "rcholqr_backward"]:
         assert n in names
 
 
@@ -49,3 +51,22 @@ def test_workspace_and_argument_errors_without_gpu():
     assert L.rcholqr_factor(vp, 100, 10, 100, 30, 1, 0, 2, 0, vp, 100, vp, 10, None, 1,
                             None, None, vp, 16, None) == -19
     assert rq.error_string(1).startswith("zero diagonal")
+
+
+def test_batched_argument_errors_without_gpu():
+    import paper_2210_09953_amd as rq
+    from paper_2210_09953_amd.binding import Problem
+    L = rq.lib()
+    probs = (Problem * 3)()
+    for i in range(3):
+        probs[i] = Problem(8, 5000, 32, 5000, 96, i, 8, 5000, 8, 32)
+    assert L.rcholqr_batched_workspace_bytes(probs, 3, rq.RADEMACHER, 2, rq.MIXED) > 0
+    probs[2].k = 16                                  # k < n in the third instance
+    assert L.rcholqr_batched_workspace_bytes(probs, 3, rq.RADEMACHER, 2, rq.MIXED) == 0
+    vp = ctypes.c_void_p(8)
+    assert L.rcholqr_factor_batched(probs, 3, rq.RADEMACHER, 2, rq.MIXED, vp, 1 << 30,
+                                    None) == -2000000 - 2
+    assert L.rcholqr_factor_batched(probs, 0, rq.RADEMACHER, 2, rq.MIXED, vp, 1 << 30, None) == -2
+    assert L.rcholqr_factor_batched(probs, 3, 7, 2, rq.MIXED, vp, 1 << 30, None) == -3
+    probs[2].k = 96
+    assert L.rcholqr_factor_batched(probs, 3, rq.RADEMACHER, 2, rq.MIXED, vp, 64, None) == -7
