@@ -40,6 +40,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_threads.restype = i32
         L.orc_ln.argtypes = [ctypes.c_double]
         L.orc_ln.restype = ctypes.c_double
         L.orc_sincos2pi_dyadic.argtypes = [u64, dp, dp]
@@ -83,6 +84,11 @@ def philox4x32_10(counter, key):
     o = (ctypes.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return [int(o[i]) for i in range(4)]
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def ln(x: float) -> float:

@@ -29,8 +29,10 @@
  *     the accumulated sketch.  Rademacher: +-1 / sqrt(k).  CountSketch: one
  *     +-1 per column at a hashed row, no scaling.
  *   - Theta's entries come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
- *     SC'11), counter = (row j of X, block of Theta rows, stream tag),
- *     key = seed, then the transforms below.
+ *     SC'11), key = seed, then the transforms below.  Gaussian: counter =
+ *     (row j of X, pair of Theta rows, stream tag).  Rademacher: counter =
+ *     (block j >> 7 of 128 rows of X, Theta row, stream tag), one bit per
+ *     row of X.  CountSketch: counter = (row j of X, 0, stream tag).
  *
  * All arithmetic is IEEE binary64, round-to-nearest; compile with
  * -ffp-contract=off so that no multiply-add is fused behind our back (the
@@ -47,6 +49,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_GAUSSIAN 0
 #define ORC_RADEMACHER 1
@@ -192,6 +197,15 @@ static void gauss_pair(uint64_t seed, int64_t j, uint32_t b, double* z0,
   *z1 = rho * sn;
 }
 
+/* Rademacher sign for column offset r (0..127) of a 128-column block, from
+ * the four Philox words of that block and Theta row: writing
+ * r = 32 q + 4 t + e (q < 4, t < 8, e < 4), the sign is -1 when bit
+ * 8 e + t of word q is set. */
+static double radem_sign(const uint32_t w[4], int r) {
+  int q = r >> 5, t = (r & 31) >> 2, e = r & 3;
+  return ((w[q] >> (8 * e + t)) & 1u) ? -1.0 : 1.0;
+}
+
 /* Raw (unscaled) Theta entry at row i, column j. */
 static double theta_raw(int kind, int64_t k, uint64_t seed, int64_t i,
                         int64_t j) {
@@ -201,9 +215,8 @@ static double theta_raw(int kind, int64_t k, uint64_t seed, int64_t i,
     return (i & 1) ? z1 : z0;
   } else if (kind == ORC_RADEMACHER) {
     uint32_t w[4];
-    philox_at(seed, j, (uint32_t)(i >> 7), ORC_TAG_RADEM, w);
-    int bit = (int)((w[(i & 127) >> 5] >> (i & 31)) & 1u);
-    return bit ? -1.0 : 1.0;
+    philox_at(seed, j >> 7, (uint32_t)i, ORC_TAG_RADEM, w);
+    return radem_sign(w, (int)(j & 127));
   } else if (kind == ORC_COUNTSKETCH) {
     uint32_t w[4];
     philox_at(seed, j, 0u, ORC_TAG_COUNT, w);
@@ -263,15 +276,17 @@ void orc_sketch(int kind, int64_t m, int64_t n, int64_t k, uint64_t seed,
       for (int64_t i = 0; i < k; ++i) P[i + c * ldp] = X[i + c * ldx];
     return;
   }
-  /* Dense kinds: Gaussian pairs of rows, Rademacher blocks of 128 rows. */
-  int64_t rows_per_draw = (kind == ORC_GAUSSIAN) ? 2 : 128;
+  /* Dense kinds, in groups of Theta rows: Gaussian pairs; Rademacher rows
+ * one at a time (a row's draws cover 128 columns each). */
+  int64_t rows_per_draw = (kind == ORC_GAUSSIAN) ? 2 : 1;
   int64_t ndraw = (k + rows_per_draw - 1) / rows_per_draw;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t d = 0; d < ndraw; ++d) {
     int64_t i0 = d * rows_per_draw;
     int64_t ni = (i0 + rows_per_draw <= k) ? rows_per_draw : (k - i0);
     double* acc = (double*)calloc((size_t)(ni * n), sizeof(double));
-    double th[128];
+    double th[2];
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
     for (int64_t j = 0; j < m; ++j) {
       if (kind == ORC_GAUSSIAN) {
         double z0, z1;
@@ -279,10 +294,9 @@ void orc_sketch(int kind, int64_t m, int64_t n, int64_t k, uint64_t seed,
         th[0] = z0;
         th[1] = z1; /* dropped when k is odd and this is the last pair */
       } else {
-        uint32_t w[4];
-        philox_at(seed, j, (uint32_t)(i0 >> 7), ORC_TAG_RADEM, w);
-        for (int64_t ii = 0; ii < ni; ++ii)
-          th[ii] = ((w[ii >> 5] >> (ii & 31)) & 1u) ? -1.0 : 1.0;
+        if ((j & 127) == 0)
+          philox_at(seed, j >> 7, (uint32_t)i0, ORC_TAG_RADEM, w);
+        th[0] = radem_sign(w, (int)(j & 127));
       }
       for (int64_t c = 0; c < n; ++c) {
         double x = X[j + c * ldx];
@@ -522,4 +536,13 @@ void orc_qr_backward(int64_t m, int64_t n, const double* Q, int64_t ldq,
   }
   free(N);
   free(M);
+}
+
+/* Number of threads the parallel loops above use (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

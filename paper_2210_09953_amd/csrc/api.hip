@@ -37,27 +37,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   SketchPlan& sp = L.sp;
   sp.npad = static_cast<int>(round_up(n, 16));
   if (prec == kPrecMixed) {
-    // FP16 matrix-core sketch: 256 Theta rows x 64 columns per workgroup,
-    // one workgroup per CU; splits chosen so the grid fills whole CU rounds.
-    const int nh = static_cast<int>(ceil_div(n, 64));
-    sp.npad = (nh > 1) ? 64 * nh : static_cast<int>(round_up(n, 16));
-    sp.ktiles = static_cast<int>(ceil_div(k, 256));
-    sp.kpad = 256 * sp.ktiles;
-    const int64_t tps = static_cast<int64_t>(sp.ktiles) * nh;
-    const int64_t maxs = round_up(ceil_div(m, 128), 8);
-    int64_t best = 8;
-    double best_eff = -1.0;
-    for (int64_t ns = 8; ns <= 512 && ns <= maxs; ns += 8) {
-      const int64_t w = ns * tps;
-      const double eff = static_cast<double>(w) / (256.0 * ceil_div(w, 256));
-      const double score = eff - ((w < 512) ? 0.5 : 0.0) - 1e-4 * static_cast<double>(w / 256);
-      if (score > best_eff + 1e-9) {
-        best_eff = score;
-        best = ns;
-      }
-    }
-    sp.nsplit = static_cast<int>(best);
-    sp.rows_per_split = round_up(ceil_div(m, sp.nsplit), 128);
+    // int8 matrix-core sketch (mixed.hip) chooses its own tiles and splits.
+    mixed_sketch_plan(m, static_cast<int>(k), static_cast<int>(n), sp);
   } else if (kind == kCountSketch) {
     const int panels = static_cast<int>(ceil_div(n, 8));
     const int64_t ntile = ceil_div(m, 256);

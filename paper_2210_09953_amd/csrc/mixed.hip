@@ -1,252 +1,408 @@
-// mixed.hip -- Rademacher sketch P = Theta X on FP16 matrix cores for FP32 X.
+// mixed.hip -- Rademacher sketch P = Theta X for FP32 X on int8 matrix cores.
 //
 // Section 5 asks for the sketch to be computed more accurately than the
-// working precision; here X is FP32 and the products run at FP16 rate while
-// keeping ~22 bits of X:
-//   * Theta entries are +-1, exact in FP16 (the 1/sqrt(k) goes on P).
-//   * Each FP32 x is scaled by a power of two 2^s chosen per column and
-//     split into x 2^s ~ hi + lo with hi = fp16(x 2^s), lo = fp16(x 2^s - hi)
-//     (the difference is exact in FP32), so |x - (hi + lo) 2^-s| <=
-//     ~2^-22 |max of the column|.  s keeps the column's running maximum in
-//     [2^14, 2^15) (no FP16 overflow) and only decreases, so values rescale
-//     rarely; P's error budget is relative to the column norm anyway.
-//   * v_mfma_f32_16x16x32_f16 accumulates Theta hi + Theta lo in FP32; the
-//     FP32 accumulators are flushed into FP64 totals every 1024 rows and
-//     whenever a column's scale changes, then the per-split FP64 partials are
-//     reduced in a fixed order (sketch_reduce_kernel).
-// A workgroup owns 256 rows of Theta and 64 columns of X (8 waves x 32
-// Theta rows), so every converted X element feeds 256 Theta rows.  Stages
-// of 128 rows of X: global loads for the next stage are issued before the
-// matrix-core loop of the current one.  Theta comes from the Philox bits
-// directly: the A operand (16 Theta rows x 32 X rows) is packed from bits
-// with integer ops, 0x3C00 | sign << 15 per FP16 entry.
+// working precision.  Here the products Theta X are exact integer sums:
+//   * Theta entries are +-1, exact in int8 (the 1/sqrt(k) goes on P).
+//   * Each column of X is quantised to integers q = rint(x 2^s), with a power
+//     of two 2^s that keeps the column's running maximum in [2^20, 2^22), so
+//     |x - q 2^-s| <= 2^-21 max|x| over the rows seen; q is split into three
+//     signed bytes, q = 2^16 h + 2^8 d + l.
+//   * v_mfma_i32_16x16x64_i8 accumulates Theta h, Theta d and Theta l in
+//     three int32 accumulators, exactly (|sum| < 2^31 for up to 2^24 rows).
+//   * A column's accumulators are folded into its FP64 partial only when the
+//     column's scale has to grow (rare: the maximum must double twice) and
+//     at the end: part += (2^16 H + 2^8 D + L) 2^-s, exact in FP64.
+// The only rounding in P is therefore the quantisation of X and the FP64
+// sum over row splits: the result is bitwise reproducible.
+//
+// Quantiser: y = fma(x, 2^s, 1.5 2^23) holds rint(x 2^s) + 2^22 in its
+// mantissa; adding 0x408080 - 0x4B000000 to its bits leaves 0 in the top
+// byte and l + 128, d + 128, h + 128 in the low three bytes, and XOR 0x80
+// per byte turns each into its signed digit.  A non-finite x leaves a
+// non-zero top byte, which marks the workgroup's partials NaN.
+//
+// Theta from Philox bits: a Rademacher draw of Theta row i covers 128 rows
+// of X, with rows 4t..4t+3 of each 32 at bit t of the four bytes of a word
+// (theta.h), so one rotate, one AND and one byte permute give four +-1
+// bytes of an A operand.
+//
+// Work split: a workgroup of wt x wc waves streams one row split of X in
+// stages of 128 rows (one Philox block) for Tg = 64 wt Theta rows and
+// Cg = 16 CT wc columns.  Per stage every thread quantises 16 rows of one
+// column into three LDS digit planes and threads 0..Tg-1 draw their Theta
+// row's words; then each wave (TT = 4 Theta tiles x CT column tiles, 3 TT CT
+// int32 tiles) issues two matrix-core steps of 64 rows.  The matrix-core
+// K slot (lane group g, byte 4t + e) carries row 16g + 4t + e of the step in
+// both operands.
 #include "common.h"
 #include "theta.h"
 #include "kernels.h"
 
 namespace rcq {
 
-constexpr int kMxRows = 128;    // rows of X per stage
-constexpr int kMxTheta = 256;   // Theta rows per workgroup
-constexpr int kMxCols = 64;     // columns of X per workgroup
-constexpr int kMxLd = kMxRows + 8;  // LDS row stride (halves) of the transposed X tile
-constexpr int kMxFlushStages = 8;
+constexpr int kQBlock = 128;                 // rows of X per Philox block
+constexpr int kQZs = 5;                      // LDS words per Theta row and block (4 + pad)
+constexpr int kQTT = 4;                      // Theta tiles of 16 per wave
+constexpr float kQMagic = 12582912.0f;       // 1.5 * 2^23
+constexpr uint32_t kQDigitBias = 0xB5408080u;  // 0x408080 - 0x4B000000 (mod 2^32)
+constexpr int kQUnset = -100000;             // column scale not chosen yet
 
-typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float pow2f(int s) {
-  return __int_as_float((s + 127) << 23);
+__device__ __forceinline__ float pow2f(int s) { return __int_as_float((s + 127) << 23); }
+
+__device__ __forceinline__ uint32_t bperm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-template <int NB>  // column tiles of 16 in this workgroup's column slice
-__global__ __launch_bounds__(512, 1) void sketch_mixed_kernel(
-    const float* __restrict__ X, int64_t m, int n, int64_t ldx, uint64_t seed, int ktiles,
-    int nh, int64_t rows_per_split, int kpad, int npad, double* __restrict__ part) {
-  constexpr int NPW = NB * 16;
-  __shared__ __align__(16) _Float16 xhi[kMxCols][kMxLd];
-  __shared__ __align__(16) _Float16 xlo[kMxCols][kMxLd];
-  __shared__ __align__(16) uint32_t zb[2][4][kMxRows];  // [philox block][word][x row]
-  __shared__ int rexp[kMxCols];       // running exponent of the column maximum
-  __shared__ int flush_flag;
+// CT: column tiles per wave.  SB: Philox blocks (128 rows) per stage.
+// NSL: quantiser task slots per thread.  FULL: the tasks fill every slot of
+// every thread (no per-slot guards).
+template <int CT, int SB, int NSL, bool FULL>
+__global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
+    const float* __restrict__ X, int64_t m, int n, int64_t ldx, int k, uint64_t seed, int wt,
+    int wc, int ktiles, int nh, int64_t rows_per_split, int kpad, int npad,
+    double* __restrict__ part) {
+  constexpr int S = kQBlock * SB;  // rows per stage
+  constexpr int KS = S / 64;       // matrix-core steps per stage
+  constexpr int LD = S + 16;       // LDS bytes per column of a digit plane
+  constexpr int G = S / 16;        // quantiser row groups per column
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Tg = wt * kQTT * 16, Cg = wc * CT * 16;
+  const int dig_sz = 3 * Cg * LD;           // bytes of one digit buffer
+  const int zb_sz = Tg * SB * kQZs;         // words of one Philox buffer
+  unsigned char* dig = smem;                                           // [2][3][Cg][LD]
+  uint32_t* zb = reinterpret_cast<uint32_t*>(smem + 2 * dig_sz);      // [2][SB][Tg][kQZs]
+  int* colexp = reinterpret_cast<int*>(zb + 2 * zb_sz);               // [2][Cg]
+  int* badflag = colexp + 2 * Cg;
 
+  // XCD-aware decode: ids are dealt round-robin to the 8 XCDs; consecutive
+  // ids on one XCD walk the Theta and column groups of one row split.
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
   const int tps = ktiles * nh;
   const int jt = slot % tps;
-  const int t = jt % ktiles, h = jt / ktiles;
+  const int tgi = jt % ktiles, h = jt / ktiles;
   const int s = (slot / tps) * 8 + xcd;
 
+  const int nthr = static_cast<int>(blockDim.x);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int c0 = h * kMxCols;              // first column of the slice
-  const int theta0 = t * kMxTheta;         // first Theta row of the workgroup
+  const int wrow = wave % wt, wcol = wave / wt;
+  const int c0 = h * Cg, theta0 = tgi * Tg;
   const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  const int ntask = G * Cg;  // quantiser task: 16 rows (group g) of one column
+  const bool vec = ((ldx & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
 
-  // Loader mapping: column group cg (2 columns), 8 consecutive rows.
-  const int cg = tid >> 4, sub = tid & 15;
-  float xv[2][8];
+  if (tid < 2 * Cg) colexp[tid] = kQUnset;
+  if (tid == 0) *badflag = 0;
+
+  // Quantiser state: NSL task slots per thread; a task's column is fixed, so
+  // its scale exponent sq persists across stages.  Columns past n read
+  // column n - 1 (their sums are never used).
+  float xv[NSL][16];
+  int sq[NSL];
+  int qcol[NSL], qg[NSL];
+  const float* qsrc[NSL];
+#pragma unroll
+  for (int sl = 0; sl < NSL; ++sl) {
+    sq[sl] = kQUnset;
+    const int task = tid + sl * nthr;
+    qcol[sl] = task / G;
+    qg[sl] = task % G;
+    const int c = (c0 + qcol[sl] < n) ? c0 + qcol[sl] : n - 1;
+    qsrc[sl] = X + static_cast<int64_t>(c) * ldx + 16 * qg[sl];
+  }
+  uint32_t orv = 0;
 
   auto load_stage = [&](int64_t r0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = c0 + 2 * cg + q;
+    for (int sl = 0; sl < NSL; ++sl) {
+      if (!FULL && tid + sl * nthr >= ntask) continue;
+      const float* src = qsrc[sl] + r0;
+      const int64_t rr = r0 + 16 * qg[sl];
+      if (vec && rr + 16 <= r_end) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t r = r0 + 8 * sub + e;
-        xv[q][e] = (r < r_end && c < n && 2 * cg + q < NPW) ? X[r + static_cast<int64_t>(c) * ldx] : 0.f;
+        for (int v = 0; v < 4; ++v) {
+          const float4 f = reinterpret_cast<const float4*>(src)[v];
+          xv[sl][4 * v] = f.x;
+          xv[sl][4 * v + 1] = f.y;
+          xv[sl][4 * v + 2] = f.z;
+          xv[sl][4 * v + 3] = f.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) xv[sl][e] = (rr + e < r_end) ? src[e] : 0.f;
       }
     }
   };
 
-  f4 acc[2][NB];
-  double tot[2][NB][4];
+  // Quantise slot sl's 16 rows into digit buffer buf; choose or grow the
+  // column scale first (every lane of the column's group agrees on it).
+  auto quantise = [&](int sl, int buf) {
+    if (!FULL && tid + sl * nthr >= ntask) return;
+    float mx = 0.f;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+    for (int e = 0; e < 16; ++e) mx = fmaxf(mx, fabsf(xv[sl][e]));
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      acc[rt][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int off = 1; off < G; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off, G));
+    const int ex = static_cast<int>((__float_as_uint(mx) >> 23) & 0xffu) - 127;
+    int sn = 20 - ex;
+    sn = sn > 126 ? 126 : (sn < -126 ? -126 : sn);
+    const int sc = sq[sl];
+    const bool grow = (mx > 0.f) && (sc == kQUnset || ex >= 22 - sc);
+    sq[sl] = grow ? sn : sc;
+    colexp[buf * Cg + qcol[sl]] = sq[sl];
+    const float f = pow2f(sq[sl] == kQUnset ? 0 : sq[sl]);
+    uint32_t u[16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tot[rt][b][v] = 0.0;
+    for (int e = 0; e < 16; ++e) {
+      u[e] = __float_as_uint(__builtin_fmaf(xv[sl][e], f, kQMagic)) + kQDigitBias;
+      orv |= u[e];
     }
-  // Exponent currently applied to each of this lane's accumulator columns.
-  int cur_s[NB];
+    unsigned char* d = dig + buf * dig_sz + qcol[sl] * LD + 16 * qg[sl];
+    uint32_t pl[3][4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) cur_s[b] = 0;
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t r01 = bperm(u[4 * t + 1], u[4 * t], 0x05010400u);
+      const uint32_t r23 = bperm(u[4 * t + 3], u[4 * t + 2], 0x05010400u);
+      const uint32_t s01 = bperm(u[4 * t + 1], u[4 * t], 0x0C0C0602u);
+      const uint32_t s23 = bperm(u[4 * t + 3], u[4 * t + 2], 0x0C0C0602u);
+      pl[0][t] = bperm(r23, r01, 0x05040100u) ^ 0x80808080u;
+      pl[1][t] = bperm(r23, r01, 0x07060302u) ^ 0x80808080u;
+      pl[2][t] = bperm(s23, s01, 0x05040100u) ^ 0x80808080u;
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      *reinterpret_cast<i4v*>(d + p * Cg * LD) =
+          i4v{static_cast<int>(pl[p][0]), static_cast<int>(pl[p][1]), static_cast<int>(pl[p][2]),
+              static_cast<int>(pl[p][3])};
+  };
 
-  if (tid < kMxCols) rexp[tid] = -1000;
-  if (tid == 0) flush_flag = 0;
-
-  auto flush = [&]() {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const double inv = static_cast<double>(pow2f(-cur_s[b]));
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) tot[rt][b][v] += static_cast<double>(acc[rt][b][v]) * inv;
-        acc[rt][b] = f4{0.f, 0.f, 0.f, 0.f};
-      }
+  // Philox words of the stage starting at row r0 into buffer buf: draw c is
+  // Theta row theta0 + c % Tg, block (r0 >> 7) + c / Tg.
+  auto draw = [&](int64_t r0, int buf) {
+    for (int c = tid; c < Tg * SB; c += nthr) {
+      const int r = c % Tg, sb = c / Tg;
+      const int i = theta0 + r;
+      Words w{0u, 0u, 0u, 0u};
+      if (FULL || i < k) w = radem_words(seed, i, (r0 >> 7) + sb);
+      uint32_t* z = zb + buf * zb_sz + (sb * Tg + r) * kQZs;
+      z[0] = w.w0;
+      z[1] = w.w1;
+      z[2] = w.w2;
+      z[3] = w.w3;
     }
   };
 
-  int stage = 0;
-  if (r_begin < r_end) load_stage(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kMxRows, ++stage) {
-    __syncthreads();  // previous stage's tiles are consumed
-    // Column maxima of this stage: 16 lanes (one DPP row) share a column.
-    float cmax[2];
+  i4v acc[3][kQTT][CT];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      float mx = 0.f;
+  for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(xv[q][e]));
+    for (int tt = 0; tt < kQTT; ++tt)
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 16));
-      cmax[q] = mx;
-    }
-    if (sub == 0) {
+      for (int b = 0; b < CT; ++b) acc[p][tt][b] = i4v{0, 0, 0, 0};
+  int cur_s[CT];
+  bool written[CT];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int cl = 2 * cg + q;
-        if (cmax[q] > 0.f) {
-          const int e = ((__float_as_int(cmax[q]) >> 23) & 0xff) - 127;
-          const int old = rexp[cl];
-          if (e > old) {
-            rexp[cl] = e;
-            flush_flag = 1;
-          }
-        }
-      }
-    }
-    // Theta bits for the stage: 128 x rows x 2 Philox blocks.
-    if (tid < 2 * kMxRows) {
-      const int xr = tid & (kMxRows - 1), blk = tid >> 7;
-      const int64_t r = r0 + xr;
-      Words w = Words{0u, 0u, 0u, 0u};
-      if (r < r_end) w = radem_words(seed, r, static_cast<uint32_t>((theta0 >> 7) + blk));
-      zb[blk][0][xr] = w.w0;
-      zb[blk][1][xr] = w.w1;
-      zb[blk][2][xr] = w.w2;
-      zb[blk][3][xr] = w.w3;
-    }
-    __syncthreads();
-    // Split this thread's values into hi + lo with the column's scale.
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int cl = 2 * cg + q;
-      int ex = rexp[cl];
-      int sc = 14 - ex;
-      sc = sc > 126 ? 126 : (sc < -126 ? -126 : sc);
-      const float f = pow2f(sc);
-      _Float16 hv[8], lv[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float y = xv[q][e] * f;
-        const _Float16 hi = static_cast<_Float16>(y);
-        hv[e] = hi;
-        lv[e] = static_cast<_Float16>(y - static_cast<float>(hi));
-      }
-      *reinterpret_cast<u4v*>(&xhi[cl][8 * sub]) = *reinterpret_cast<u4v*>(hv);
-      *reinterpret_cast<u4v*>(&xlo[cl][8 * sub]) = *reinterpret_cast<u4v*>(lv);
-    }
-    // Prefetch the next stage while this one is consumed.
-    if (r0 + kMxRows < r_end) load_stage(r0 + kMxRows);
-    __syncthreads();
-    // Scale changes or periodic flush: fold FP32 sums into FP64 totals.
-    const bool periodic = (stage % kMxFlushStages) == 0;
-    if (flush_flag || periodic) {
-      flush();
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        int sc = 14 - rexp[16 * b + l16];
-        cur_s[b] = sc > 126 ? 126 : (sc < -126 ? -126 : sc);
-      }
-    }
-    // Matrix-core loop: 4 steps of 32 rows.
-#pragma unroll
-    for (int ks = 0; ks < kMxRows / 32; ++ks) {
-      h8 a[2];
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const int r = 32 * wave + 16 * rt + l16;  // local Theta row
-        const int blk = r >> 7, wd = (r & 127) >> 5, bit = r & 31;
-        const u4v w0 = *reinterpret_cast<const u4v*>(&zb[blk][wd][32 * ks + 8 * lg]);
-        const u4v w1 = *reinterpret_cast<const u4v*>(&zb[blk][wd][32 * ks + 8 * lg + 4]);
-        uint32_t pk[4];
-        pk[0] = 0x3C003C00u | (((w0.x >> bit) & 1u) << 15) | (((w0.y >> bit) & 1u) << 31);
-        pk[1] = 0x3C003C00u | (((w0.z >> bit) & 1u) << 15) | (((w0.w >> bit) & 1u) << 31);
-        pk[2] = 0x3C003C00u | (((w1.x >> bit) & 1u) << 15) | (((w1.y >> bit) & 1u) << 31);
-        pk[3] = 0x3C003C00u | (((w1.z >> bit) & 1u) << 15) | (((w1.w >> bit) & 1u) << 31);
-        a[rt] = *reinterpret_cast<h8*>(pk);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const h8 bh = *reinterpret_cast<const h8*>(&xhi[16 * b + l16][32 * ks + 8 * lg]);
-        const h8 bl = *reinterpret_cast<const h8*>(&xlo[16 * b + l16][32 * ks + 8 * lg]);
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-          acc[rt][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[rt], bh, acc[rt][b], 0, 0, 0);
-          acc[rt][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[rt], bl, acc[rt][b], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
-    if (tid == 0) flush_flag = 0;
+  for (int b = 0; b < CT; ++b) {
+    cur_s[b] = kQUnset;
+    written[b] = false;
   }
-  flush();
-  // part[s][c][i] (ld kpad); D element v of lane group lg is Theta row 4 lg + v.
-  double* dst = part + static_cast<int64_t>(s) * npad * kpad;
+
+  // Fold column tile b's integer sums into the FP64 partials (exact: each
+  // sum is below 2^31, so 2^16 H + 2^8 D + L is below 2^48).
+  auto fold = [&](int b, bool nan_out) {
+    const double sc = (cur_s[b] == kQUnset) ? 1.0 : static_cast<double>(pow2f(-cur_s[b]));
+    const int c = c0 + wcol * CT * 16 + 16 * b + l16;
+    double* dst = part + (static_cast<int64_t>(s) * npad + c) * kpad + theta0 + wrow * kQTT * 16;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int tt = 0; tt < kQTT; ++tt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = theta0 + 32 * wave + 16 * rt + 4 * lg + v;
-        const int c = c0 + 16 * b + l16;
-        dst[static_cast<int64_t>(c) * kpad + i] = tot[rt][b][v];
+        double val = (65536.0 * static_cast<double>(acc[2][tt][b][v]) +
+                      256.0 * static_cast<double>(acc[1][tt][b][v]) +
+                      static_cast<double>(acc[0][tt][b][v])) * sc;
+        if (nan_out) val = __builtin_nan("");
+        double* p = dst + 16 * tt + 4 * lg + v;
+        *p = written[b] ? *p + val : val;
       }
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p][tt][b] = i4v{0, 0, 0, 0};
+    }
+    written[b] = true;
+  };
+
+  // Rotations that bring this lane's Theta bits to bit 2 of each byte.
+  uint32_t rot[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) rot[t] = static_cast<uint32_t>((4 * (lg & 1) + t - 2) & 31);
+
+  // One matrix-core step: rows 64 ks .. 64 ks + 63 of the stage in buffer buf.
+  auto step = [&](int ks, int buf) {
+    const uint32_t* z = zb + buf * zb_sz + ((ks >> 1) * Tg + wrow * kQTT * 16 + l16) * kQZs +
+                        2 * (ks & 1) + (lg >> 1);
+    i4v a[kQTT];
+#pragma unroll
+    for (int tt = 0; tt < kQTT; ++tt) {
+      const uint32_t w = z[16 * tt * kQZs];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t sel = __builtin_amdgcn_alignbit(w, w, rot[t]) & 0x04040404u;
+        a[tt][t] = static_cast<int>(bperm(0xFFFFFFFFu, 0x01010101u, sel));
+      }
+    }
+    const unsigned char* d = dig + buf * dig_sz + (wcol * CT * 16 + l16) * LD + 64 * ks + 16 * lg;
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      i4v bp[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        bp[p] = *reinterpret_cast<const i4v*>(d + (p * Cg + 16 * b) * LD);
+#pragma unroll
+      for (int tt = 0; tt < kQTT; ++tt)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          acc[p][tt][b] =
+              __builtin_amdgcn_mfma_i32_16x16x64_i8(a[tt], bp[p], acc[p][tt][b], 0, 0, 0);
+    }
+  };
+
+  __syncthreads();
+  int64_t r0 = r_begin;
+  int cur = 0;
+  if (r0 < r_end) {
+    load_stage(r0);
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) quantise(sl, 0);
+    draw(r0, 0);
+  }
+  __syncthreads();
+  if (r0 + S < r_end) load_stage(r0 + S);
+  for (; r0 < r_end; r0 += S, cur ^= 1) {
+    // Columns whose scale grew for this stage: fold at the old scale.
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int ns = colexp[cur * Cg + wcol * CT * 16 + 16 * b + l16];
+      if (ns != cur_s[b]) {
+        if (cur_s[b] != kQUnset) fold(b, false);
+        cur_s[b] = ns;
+      }
+    }
+    // This stage's matrix-core steps, with the next stage's quantisation
+    // and Philox draws in between (on the last stage they work on stale
+    // registers into the idle buffer, which is never read).
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      step(ks, cur);
+      if (ks < NSL) quantise(ks, cur ^ 1);
+    }
+#pragma unroll
+    for (int sl = KS; sl < NSL; ++sl) quantise(sl, cur ^ 1);
+    draw(r0 + S, cur ^ 1);
+    if (r0 + 2 * S < r_end) load_stage(r0 + 2 * S);
+    if (orv >> 24) *badflag = 1;
+    __syncthreads();
+  }
+  const bool bad = *badflag != 0;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) fold(b, bad);
+}
+
+// Launch plan of the int8 sketch for (k, n).
+struct I8Plan {
+  int ct, sb, wt, wc, ktiles, nh, kpad, npad;
+  bool full;  // four Theta waves x two column waves of two tiles: one task per thread
+};
+
+static I8Plan i8_plan(int k, int n) {
+  I8Plan p{};
+  p.ct = (n <= 16) ? 1 : 2;
+  p.wc = (n > 16 * p.ct) ? 2 : 1;
+  const int kt = static_cast<int>(ceil_div(k, 16 * kQTT));
+  // Waves along Theta: 1, 2 or 4 (at most 8 waves), fewest padded tiles.
+  int best_wt = 1, best_slots = 1 << 30;
+  for (int wt = 1; wt <= 8 / p.wc && wt <= 4; wt *= 2) {
+    const int slots = wt * static_cast<int>(ceil_div(kt, wt));
+    if (slots <= best_slots) {
+      best_slots = slots;
+      best_wt = wt;
+    }
+  }
+  p.wt = best_wt;
+  p.ktiles = static_cast<int>(ceil_div(kt, p.wt));
+  if (p.ct > p.wt) p.ct = 1;  // at most two quantiser tasks per thread
+  p.full = (p.ct == 2 && p.wt == 4 && p.wc == 2);
+  p.sb = 1;
+  const int cg = 16 * p.ct * p.wc;
+  p.nh = static_cast<int>(ceil_div(n, cg));
+  p.kpad = 16 * kQTT * p.wt * p.ktiles;
+  p.npad = cg * p.nh;
+  return p;
+}
+
+static size_t i8_lds_bytes(const I8Plan& p) {
+  const int tg = 16 * kQTT * p.wt, cg = 16 * p.ct * p.wc, ld = kQBlock * p.sb + 16;
+  return static_cast<size_t>(2 * 3 * cg * ld + 2 * tg * p.sb * kQZs * 4 + 2 * cg * 4 + 16);
+}
+
+void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp) {
+  const I8Plan p = i8_plan(k, n);
+  sp.ktiles = p.ktiles;
+  sp.kpad = p.kpad;
+  sp.npad = p.npad;
+  // Splits (multiples of 8, for the XCD decode) chosen so that the grid
+  // fills whole rounds of one workgroup per CU; at most 2^23 rows a split
+  // keeps the int32 sums exact.
+  const int64_t stage = kQBlock * p.sb;
+  const int64_t tps = static_cast<int64_t>(p.ktiles) * p.nh;
+  const int64_t maxs = round_up(ceil_div(m, stage), 8);
+  const int64_t mins = round_up(ceil_div(m, int64_t{1} << 23), 8);
+  int64_t best = mins > 8 ? mins : 8;
+  double best_eff = -1.0;
+  for (int64_t ns = best; ns <= 512 && ns <= maxs; ns += 8) {
+    const int64_t w = ns * tps;
+    const double eff = static_cast<double>(w) / (256.0 * ceil_div(w, 256));
+    const double score = eff - ((w < 512) ? 0.5 : 0.0) - 1e-4 * static_cast<double>(w / 256);
+    if (score > best_eff + 1e-9) {
+      best_eff = score;
+      best = ns;
+    }
+  }
+  sp.nsplit = static_cast<int>(best);
+  sp.rows_per_split = round_up(ceil_div(m, sp.nsplit), stage);
 }
 
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
                                hipStream_t st) {
-  const int nh = static_cast<int>(ceil_div(n, kMxCols));
-  const int npw = static_cast<int>((nh > 1) ? kMxCols : round_up(n, 16));
-  const int nb = npw / 16;
-  const dim3 grid(pl.nsplit * pl.ktiles * nh), block(512);
-#define RCQ_MX_CASE(NBV)                                                                          \
-  case NBV:                                                                                       \
-    sketch_mixed_kernel<NBV><<<grid, block, 0, st>>>(X, m, n, ldx, seed, pl.ktiles, nh,           \
-                                                     pl.rows_per_split, pl.kpad, pl.npad, part);  \
-    break;
-  switch (nb) {
-    RCQ_MX_CASE(1) RCQ_MX_CASE(2) RCQ_MX_CASE(3) RCQ_MX_CASE(4)
-    default: return hipErrorInvalidValue;
-  }
-#undef RCQ_MX_CASE
-  hipError_t e = hipGetLastError();
+  const I8Plan p = i8_plan(k, n);
+  if (p.ktiles != pl.ktiles || p.kpad != pl.kpad || p.npad != pl.npad ||
+      (pl.rows_per_split % (kQBlock * p.sb)) != 0 || (pl.nsplit % 8) != 0 ||
+      pl.rows_per_split > (int64_t{1} << 23))
+    return hipErrorInvalidValue;
+  const size_t shm = i8_lds_bytes(p);
+  const dim3 grid(pl.nsplit * p.ktiles * p.nh), block(64 * p.wt * p.wc);
+  hipError_t e = hipSuccess;
+#define RCQ_I8(CTV, SBV, NSLV, FV)                                                             \
+  do {                                                                                         \
+    const void* fn = reinterpret_cast<const void*>(&sketch_i8_kernel<CTV, SBV, NSLV, FV>);     \
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,                    \
+                            static_cast<int>(shm));                                            \
+    if (e != hipSuccess) return e;                                                             \
+    sketch_i8_kernel<CTV, SBV, NSLV, FV><<<grid, block, shm, st>>>(                            \
+        X, m, n, ldx, k, seed, p.wt, p.wc, p.ktiles, p.nh, pl.rows_per_split, pl.kpad, pl.npad, \
+        part);                                                                                 \
+  } while (0)
+  if (p.full)
+    RCQ_I8(2, 1, 1, true);
+  else if (p.ct == 2)
+    RCQ_I8(2, 1, 2, false);
+  else
+    RCQ_I8(1, 1, 2, false);
+#undef RCQ_I8
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sketch_reduce(part, pl, k, n, 1.0 / sqrt(static_cast<double>(k)), P, ldp, st);
 }

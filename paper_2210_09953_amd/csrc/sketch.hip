@@ -35,10 +35,8 @@ __global__ void theta_debug_kernel(int kind, int k, uint64_t seed, int64_t i0, i
     gauss_pair(seed, j, static_cast<uint32_t>(i >> 1), z0, z1);
     v = (i & 1) ? z1 : z0;
   } else if (kind == kRademacher) {
-    const Words w = radem_words(seed, j, static_cast<uint32_t>(i >> 7));
-    const int r = static_cast<int>(i & 127);
-    const uint32_t word = (r < 32) ? w.w0 : (r < 64) ? w.w1 : (r < 96) ? w.w2 : w.w3;
-    v = ((word >> (r & 31)) & 1u) ? -1.0 : 1.0;
+    const Words w = radem_words(seed, static_cast<int>(i), j >> 7);
+    v = radem_bit(w, static_cast<int>(j & 127)) ? -1.0 : 1.0;
   } else {
     int h, neg;
     count_hash(seed, j, k, h, neg);
@@ -77,6 +75,8 @@ __global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict_
   d4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  Words rw{0u, 0u, 0u, 0u};  // Rademacher words of this lane's Theta row
+  int64_t rblk = -1;
 
   for (int64_t r0 = r_begin; r0 < r_end; r0 += kSkRows) {
     __syncthreads();
@@ -101,18 +101,20 @@ __global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict_
         zs[wave][jj][2 * ip + 1] = z1;
       }
     } else {
-      const int jj = lane >> 2, qq = lane & 3;
-      const int64_t row = r0 + jj;
-      const int r128 = (ibase & 127) + 4 * qq;  // first of this lane's 4 rows
-      uint32_t word = 0;
-      if (row < r_end) {
-        const Words w = radem_words(seed, row, static_cast<uint32_t>(ibase >> 7));
-        word = (r128 < 32) ? w.w0 : (r128 < 64) ? w.w1 : (r128 < 96) ? w.w2 : w.w3;
+      // Lane: Theta row ibase + (lane & 15), rows jj0..jj0+3 of the stage.
+      // The row's words cover a 128-row block of X; a 16-row stage never
+      // straddles two blocks (stages start at multiples of 16).
+      const int ii = lane & 15, jj0 = 4 * (lane >> 4);
+      const int64_t blk = r0 >> 7;
+      if (blk != rblk) {
+        rw = radem_words(seed, ibase + ii, blk);
+        rblk = blk;
       }
+      const int o = static_cast<int>(r0 & 127) + jj0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int bit = (word >> ((r128 + e) & 31)) & 1u;
-        zs[wave][jj][4 * qq + e] = (row < r_end) ? (bit ? -1.0 : 1.0) : 0.0;
+        const int64_t row = r0 + jj0 + e;
+        zs[wave][jj0 + e][ii] = (row < r_end) ? (radem_bit(rw, o + e) ? -1.0 : 1.0) : 0.0;
       }
     }
     __syncthreads();

@@ -5,12 +5,16 @@
 // function handle).  Column j of Theta belongs to row j of X, so a kernel
 // streaming rows of X regenerates exactly the Theta columns it needs.
 //
-// Generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter =
-// (lo32 j, hi32 j, block index, stream tag), key = (lo32 seed, hi32 seed).
-//   Gaussian   : block b -> Theta rows 2b, 2b+1 via Box-Muller (1958).
-//   Rademacher : block b -> Theta rows 128b..128b+127, one bit each
-//                (bit 1 -> -1, bit 0 -> +1; word w holds rows 32w..32w+31).
-//   CountSketch: block 0 -> h(j) = (w0 * k) >> 32, s(j) = w1 & 1 ? -1 : +1.
+// Generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
+// (lo32 seed, hi32 seed), counter = (lo32 a, hi32 a, b, stream tag):
+//   Gaussian   : a = j, b = pair index: Theta rows 2b, 2b+1 of column j via
+//                Box-Muller (1958).
+//   Rademacher : a = j >> 7, b = Theta row i: one bit for each of the 128
+//                columns 128a..128a+127 of row i (bit 1 -> -1).  Column
+//                offset r = 32q + 4t + e (q < 4, t < 8, e < 4) is bit
+//                8e + t of word q, so that four consecutive columns sit at
+//                the same bit of the four bytes of a word.
+//   CountSketch: a = j, b = 0: h(j) = (w0 * k) >> 32, s(j) = w1 & 1 ? -1 : +1.
 // The Box-Muller transform uses only IEEE +, -, *, /, sqrt and explicit fma
 // in a fixed order (contraction disabled here), so that its bits are the
 // same on any conforming machine:
@@ -33,22 +37,29 @@ struct Words {
   uint32_t w0, w1, w2, w3;
 };
 
+// Full 32 x 32 -> 64-bit product in one instruction (the compiler would
+// otherwise split it into separate low and high multiplies).
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
+  uint64_t r;
+  asm("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(r) : "v"(a), "s"(b) : "vcc");
+  return r;
+}
+
 // Ten Philox rounds.  Round multipliers and Weyl key increments are the
 // published Philox4x32 constants.
 __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t p0_lo = 0xD2511F53u * c0;
-    const uint32_t p0_hi = __umulhi(0xD2511F53u, c0);
-    const uint32_t p1_lo = 0xCD9E8D57u * c2;
-    const uint32_t p1_hi = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = p1_hi ^ c1 ^ k0;
-    const uint32_t n2 = p0_hi ^ c3 ^ k1;
+    // One 32 x 32 -> 64-bit product each (a single v_mad_u64_u32).
+    const uint64_t p0 = mul_wide(c0, 0xD2511F53u);
+    const uint64_t p1 = mul_wide(c2, 0xCD9E8D57u);
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = p1_lo;
+    c1 = static_cast<uint32_t>(p1);
     c2 = n2;
-    c3 = p0_lo;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -152,9 +163,16 @@ __device__ __forceinline__ void gauss_pair(uint64_t seed, int64_t j, uint32_t b,
   z1 = rho * sn;
 }
 
-// Rademacher words for Theta rows 128 blk .. 128 blk + 127 of column j.
-__device__ __forceinline__ Words radem_words(uint64_t seed, int64_t j, uint32_t blk) {
-  return theta_words(seed, j, blk, kTagRadem);
+// Rademacher words of Theta row i for columns 128 blk .. 128 blk + 127.
+__device__ __forceinline__ Words radem_words(uint64_t seed, int i, int64_t blk) {
+  return theta_words(seed, blk, static_cast<uint32_t>(i), kTagRadem);
+}
+
+// Rademacher bit (1 -> -1) of column offset r (0..127) within a block.
+__device__ __forceinline__ uint32_t radem_bit(const Words& w, int r) {
+  const int q = r >> 5, t = (r & 31) >> 2, e = r & 3;
+  const uint32_t word = (q == 0) ? w.w0 : (q == 1) ? w.w1 : (q == 2) ? w.w2 : w.w3;
+  return (word >> (8 * e + t)) & 1u;
 }
 
 // CountSketch bucket and sign of column j.

@@ -66,6 +66,24 @@ def test_philox_matches_independent_library(orc, tmp_path):
         assert orc.philox4x32_10(c[:4], c[4:]) == ref, c
 
 
+def test_rademacher_bit_layout(orc):
+    """Theta(i, j) is one bit of the Philox draw for (block j >> 7, row i):
+    offset r = 32 q + 4 t + e within the block reads bit 8 e + t of word q,
+    bit 1 meaning -1.  Checked entry by entry against Philox words from the
+    library-pinned generator, on blocks far from the origin too."""
+    seed = 0x0123456789ABCDEF
+    for j0 in (0, 128 * 5 + 0, (1 << 40) + 256):
+        th = orc.theta_block(RD, 300, j0 + 128, seed, 250, 4, j0, 128)
+        for ii in range(4):
+            b = j0 >> 7
+            w = orc.philox4x32_10([b & 0xffffffff, b >> 32, 250 + ii, 0x52414445],
+                                  [seed & 0xffffffff, seed >> 32])
+            for r in range(128):
+                q, t, e = r >> 5, (r & 31) >> 2, r & 3
+                want = -1.0 if (w[q] >> (8 * e + t)) & 1 else 1.0
+                assert th[ii, r] == want, (j0, ii, r)
+
+
 def test_philox_bits_uniform(orc):
     """Rademacher entries are single Philox bits: chi-square over 2^16
     counters of the four-bit nibbles, and bit balance."""
