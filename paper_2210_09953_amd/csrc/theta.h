@@ -45,25 +45,34 @@ __device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
   return r;
 }
 
-// Ten Philox rounds.  Round multipliers and Weyl key increments are the
-// published Philox4x32 constants.
+// Philox counter and key while the rounds run.
+struct PhiloxState {
+  uint32_t c0, c1, c2, c3, k0, k1;
+};
+
+// One Philox4x32 round and key bump.  Round multipliers and Weyl key
+// increments are the published Philox4x32 constants.
+__device__ __forceinline__ void philox_round(PhiloxState& p) {
+  // One 32 x 32 -> 64-bit product each (a single v_mad_u64_u32).
+  const uint64_t p0 = mul_wide(p.c0, 0xD2511F53u);
+  const uint64_t p1 = mul_wide(p.c2, 0xCD9E8D57u);
+  const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ p.c1 ^ p.k0;
+  const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ p.c3 ^ p.k1;
+  p.c0 = n0;
+  p.c1 = static_cast<uint32_t>(p1);
+  p.c2 = n2;
+  p.c3 = static_cast<uint32_t>(p0);
+  p.k0 += 0x9E3779B9u;
+  p.k1 += 0xBB67AE85u;
+}
+
+// Ten Philox rounds.
 __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+  PhiloxState p{c0, c1, c2, c3, k0, k1};
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    // One 32 x 32 -> 64-bit product each (a single v_mad_u64_u32).
-    const uint64_t p0 = mul_wide(c0, 0xD2511F53u);
-    const uint64_t p1 = mul_wide(c2, 0xCD9E8D57u);
-    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
-    c0 = n0;
-    c1 = static_cast<uint32_t>(p1);
-    c2 = n2;
-    c3 = static_cast<uint32_t>(p0);
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return Words{c0, c1, c2, c3};
+  for (int r = 0; r < 10; ++r) philox_round(p);
+  return Words{p.c0, p.c1, p.c2, p.c3};
 }
 
 __device__ __forceinline__ Words theta_words(uint64_t seed, int64_t j, uint32_t block,
