@@ -61,11 +61,27 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   }
   GramPlan& gp = L.gp;
   gp.nbb = static_cast<int>(ceil_div(n, 64));
-  gp.npg = 64 * gp.nbb;
-  int64_t gs = ceil_div(m, 16);
-  if (gs > 256) gs = 256;
-  gp.rows_per_split = round_up(ceil_div(m, gs), 16);
-  gp.nsplit = static_cast<int>(ceil_div(m, gp.rows_per_split));
+  gp.npg = 128 * static_cast<int>(ceil_div(n, 128));  // ld of the partials: whole 128-blocks
+  // Row splits: a multiple of 8 (the XCD-aware decode of the FP32 Gram),
+  // chosen so that the FP32 Gram's grid (splits x 128-blocks, two 4-wave
+  // workgroups per CU) fills whole rounds; splits past m stay empty.
+  {
+    const int64_t nbp = ceil_div(n, 128) * (ceil_div(n, 128) + 1) / 2;
+    const int64_t maxs = round_up(ceil_div(m, 16), 8);
+    int64_t best = 8;
+    double best_score = -1.0;
+    for (int64_t ns = 8; ns <= 256 && ns <= maxs; ns += 8) {
+      const int64_t w = ns * nbp;
+      const double eff = static_cast<double>(w) / (512.0 * ceil_div(w, 512));
+      const double score = eff - ((w < 256) ? 0.5 : 0.0) - 1e-4 * static_cast<double>(w / 512);
+      if (score > best_score + 1e-9) {
+        best_score = score;
+        best = ns;
+      }
+    }
+    gp.rows_per_split = round_up(ceil_div(m, best), 16);
+    gp.nsplit = static_cast<int>(best);
+  }
 
   const size_t esz = (prec == kPrecF64) ? sizeof(double) : sizeof(float);
   size_t off = 0;
@@ -79,7 +95,11 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   L.T = off; off += align256(static_cast<size_t>(ceil_div(n, kHhPanel)) * kHhPanel * kHhPanel * sizeof(double));
   L.Rs = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   (void)esz;
-  L.pan = off; off += align256(static_cast<size_t>(panel_elems(static_cast<int>(n))) * sizeof(double));
+  {
+    const int64_t pb = panel_elems(static_cast<int>(n)) * static_cast<int64_t>(sizeof(double));
+    const int64_t p3 = bf3_panel_bytes(static_cast<int>(n));
+    L.pan = off; off += align256(static_cast<size_t>(pb > p3 ? pb : p3));
+  }
   L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   L.gpart = off;
   if (passes == 2) off += align256(static_cast<size_t>(gp.nsplit) * gp.npg * gp.npg * sizeof(double));
@@ -207,7 +227,10 @@ int factor_one(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   RCQ_TRY(launch_set_identity(Tinv, n, ni, ni, st));
   RCQ_TRY(launch_make_panels(G, L.gp.npg, ni, false, pan, st));
   RCQ_TRY(launch_trsm(Tinv, false, ni, ni, n, pan, Tinv, n, st));
-  RCQ_TRY(launch_make_panels(Tinv, n, ni, f32, pan, st, false));
+  if (f32)
+    RCQ_TRY(launch_make_bf3_panels(Tinv, n, ni, pan, st));
+  else
+    RCQ_TRY(launch_make_panels(Tinv, n, ni, false, pan, st, false));
   if (profile) prof_mark(5, st);
   RCQ_TRY(launch_trmm(Q, f32, m, ni, ldq, pan, st));
   if (profile) {
@@ -338,8 +361,10 @@ BwdLayout make_bwd_layout(int64_t m, int64_t n) {
   L.gp = make_layout(m, n, n, kGaussian, 2, kPrecF64).gp;
   size_t off = 256;
   const int ni = static_cast<int>(n);
-  const int64_t pe = panel_elems(ni) > dense_panel_elems(ni) ? panel_elems(ni) : dense_panel_elems(ni);
-  L.pan = off; off += align256(static_cast<size_t>(pe) * sizeof(double));
+  int64_t pe = panel_elems(ni) > dense_panel_elems(ni) ? panel_elems(ni) : dense_panel_elems(ni);
+  pe *= static_cast<int64_t>(sizeof(double));
+  if (bf3_panel_bytes(ni) > pe) pe = bf3_panel_bytes(ni);
+  L.pan = off; off += align256(static_cast<size_t>(pe));
   L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   L.Rw = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   L.Nm = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
@@ -390,7 +415,10 @@ int rcholqr_backward(const void* X, int64_t m, int64_t n, int64_t ldx, const dou
   RCQ_TRY(launch_set_identity(Tinv, n, ni, ni, st));
   RCQ_TRY(launch_make_panels(Rp, n, ni, false, pan, st));
   RCQ_TRY(launch_trsm(Tinv, false, ni, ni, n, pan, Tinv, n, st));
-  RCQ_TRY(launch_make_panels(Tinv, n, ni, f32, pan, st, false));
+  if (f32)
+    RCQ_TRY(launch_make_bf3_panels(Tinv, n, ni, pan, st));
+  else
+    RCQ_TRY(launch_make_panels(Tinv, n, ni, false, pan, st, false));
   RCQ_TRY(launch_trmm(dX, f32, m, ni, lddx, pan, st));
   // dQ^T Q, then M, N = copyltu(M) and J R^T J in FP64.
   RCQ_TRY(launch_triu_product(Rp, n, Rs, n, Rw, n, ni, st));

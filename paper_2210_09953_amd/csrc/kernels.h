@@ -59,6 +59,8 @@ hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ld
 hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
                               hipStream_t st, bool negate = true);
 hipError_t launch_set_identity(double* A, int64_t lda, int rows, int cols, hipStream_t st);
+int64_t bf3_panel_bytes(int n);
+hipError_t launch_make_bf3_panels(const double* T, int64_t ldt, int n, void* pan3, hipStream_t st);
 hipError_t launch_gram_reduce_full(const double* gpart, const GramPlan& gp, int n, double* G,
                                    hipStream_t st);
 hipError_t launch_adjoint_small(const double* R, const double* dR, int64_t lddr,

@@ -456,6 +456,62 @@ hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, voi
   return hipGetLastError();
 }
 
+// bf16 x 3 operand panels of an upper triangular T (n x n, ld ldt) for
+// trmm_bf3_kernel: panel b, chunk ch <= b/2, plane p (h, d, l), lane
+// (lg, l16) holds the 8 values T(32 ch + 8 lg + e, 16 b + l16), e < 8, of
+// FP32(T) split exactly into three bf16 parts, as 16 bytes.  Entries below
+// the diagonal or past n are 0, except 1 on the diagonal past n.
+__global__ void make_bf3_panels_kernel(const double* __restrict__ T, int64_t ldt, int n, int nb,
+                                       unsigned char* __restrict__ pan3) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (b, ch, lane)
+  // panel b has (b/2 + 1) chunks of 64 lanes
+  int b = 0, base = 0;
+  while (b < nb && base + 64 * (b / 2 + 1) <= idx) {
+    base += 64 * (b / 2 + 1);
+    ++b;
+  }
+  if (b >= nb) return;
+  const int rem = idx - base, ch = rem / 64, lane = rem % 64;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int col = 16 * b + l16;
+  uint32_t hp[8], dp[8], lp[8];
+  for (int e = 0; e < 8; ++e) {
+    const int k = 32 * ch + 8 * lg + e;
+    double v;
+    if (k < n && col < n)
+      v = (k <= col) ? T[k + static_cast<int64_t>(col) * ldt] : 0.0;
+    else
+      v = (k == col) ? 1.0 : 0.0;
+    const float x = static_cast<float>(v);
+    hp[e] = __float_as_uint(x) & 0xFFFF0000u;
+    const float r = x - __uint_as_float(hp[e]);
+    dp[e] = __float_as_uint(r) & 0xFFFF0000u;
+    lp[e] = __float_as_uint(r - __uint_as_float(dp[e]));
+  }
+  // chunk ch of panel b: 3 planes x 64 lanes x 16 bytes
+  unsigned char* dst = pan3 + 3072 * (base / 64 + ch);
+  for (int w = 0; w < 4; ++w) {
+    reinterpret_cast<uint32_t*>(dst + 16 * lane)[w] = (hp[2 * w] >> 16) | (hp[2 * w + 1] & 0xFFFF0000u);
+    reinterpret_cast<uint32_t*>(dst + 1024 + 16 * lane)[w] = (dp[2 * w] >> 16) | (dp[2 * w + 1] & 0xFFFF0000u);
+    reinterpret_cast<uint32_t*>(dst + 2048 + 16 * lane)[w] = (lp[2 * w] >> 16) | (lp[2 * w + 1] & 0xFFFF0000u);
+  }
+}
+
+int64_t bf3_panel_bytes(int n) {
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  int64_t chunks = 0;
+  for (int b = 0; b < nb; ++b) chunks += b / 2 + 1;
+  return 3072 * chunks;
+}
+
+hipError_t launch_make_bf3_panels(const double* T, int64_t ldt, int n, void* pan3, hipStream_t st) {
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  const int64_t lanes = bf3_panel_bytes(n) / 3072 * 64;
+  make_bf3_panels_kernel<<<static_cast<unsigned>(ceil_div(lanes, 256)), 256, 0, st>>>(
+      T, ldt, n, nb, static_cast<unsigned char*>(pan3));
+  return hipGetLastError();
+}
+
 hipError_t launch_set_identity(double* A, int64_t lda, int rows, int cols, hipStream_t st) {
   const int64_t tot = static_cast<int64_t>(rows) * cols;
   set_identity_kernel<<<static_cast<unsigned>(ceil_div(tot, 256)), 256, 0, st>>>(A, lda, rows, cols);

@@ -15,7 +15,8 @@
 // Works in place (Q == X).
 //
 // trmm_kernel: Q = Q1 T for the upper triangular T = R'^{-1} (the second
-// solve as a product; R' is well conditioned).
+// solve as a product; R' is well conditioned); trmm_bf3_kernel does the FP32
+// case on bf16 matrix cores with FP32-accurate three-way splits.
 //
 // gram_kernel: A = Q^T Q (Algorithm 3 step 2), split-K over rows on matrix
 // cores in the working precision, FP64 partial sums per split (FP32 sums are
@@ -25,6 +26,19 @@
 #include "kernels.h"
 
 namespace rcq {
+
+// bf16 x 8 matrix-core operand, and the exact split of an FP32 value into
+// three bf16 parts (bit patterns in the high halves): h keeps the top 8
+// significand bits, d the next 8 of the remainder, l the last 8.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& d, uint32_t& l) {
+  h = __float_as_uint(x) & 0xFFFF0000u;
+  const float r = x - __uint_as_float(h);
+  d = __float_as_uint(r) & 0xFFFF0000u;
+  l = __float_as_uint(r - __uint_as_float(d));
+}
+constexpr int kG3Rows = 32;  // Gram rows per stage = K of one bf16 matrix-core step
 
 // Copies panel b (rows 0..16b+15 x 16 columns) of the packed R array to
 // registers (staging toward LDS): thread t holds elements t, t+256, ...
@@ -67,23 +81,46 @@ __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n,
   T qa[RB][4 * NB];
   T stg[NB];
 
+  // X of the next panel is loaded one panel ahead (its latency overlaps the
+  // current panel's work; loads are not moved across the barriers).
+  // Whole workgroup inside the matrix: no per-element bounds checks.
+  const bool full = static_cast<int64_t>(blockIdx.x) * 64 * RB + 64 * RB <= m && n == 16 * NB;
+  T xn[RB][4];
+  auto load_x = [&](int b) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t row = row0 + 16 * rb;
+      if (full) {
+        const T* xb = X + row + static_cast<int64_t>(4 * lg) * ldx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xn[rb][v] = xb[static_cast<int64_t>(16 * b + v) * ldx];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * b + 4 * lg + v;
+          xn[rb][v] = (row < m && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
+        }
+      }
+    }
+  };
+  load_x(0);
   panel_fetch<T, NB>(pan, 0, stg);
   panel_store<T, NB>(pbuf[0], 0, stg);
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const T* pb = pbuf[b & 1];
-    if (b + 1 < NB) panel_fetch<T, NB>(pan, b + 1, stg);  // overlap with this panel
     A4 D[RB], E[RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int64_t row = row0 + 16 * rb;
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = 16 * b + 4 * lg + v;
-        D[rb][v] = (row < m && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
+        D[rb][v] = xn[rb][v];
         E[rb][v] = T(0);
       }
+    if (b + 1 < NB) {
+      panel_fetch<T, NB>(pan, b + 1, stg);  // overlap with this panel
+      load_x(b + 1);
     }
     // D <- X_b^T - R_{<b,b}^T Q_{<b}^T (A = -R^T block, B = Q^T block), two chains.
 #pragma unroll
@@ -140,10 +177,16 @@ __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n,
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int64_t row = row0 + 16 * rb;
+      if (full) {
+        T* qb = Q + row + static_cast<int64_t>(4 * lg) * ldq;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = 16 * b + 4 * lg + v;
-        if (row < m && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[rb][v];
+        for (int v = 0; v < 4; ++v) qb[static_cast<int64_t>(16 * b + v) * ldq] = D[rb][v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * b + 4 * lg + v;
+          if (row < m && col < n) Q[row + static_cast<int64_t>(col) * ldq] = D[rb][v];
+        }
       }
     }
     if (b + 1 < NB) {
@@ -277,6 +320,146 @@ __global__ __launch_bounds__(256) void trmm_kernel(T* Q, int64_t m, int n, int64
   }
 }
 
+// ----------------------------------------------------------------------------
+// Q = Q1 T for FP32 Q1 on bf16 matrix cores (the FP32 second solve).  Both
+// operands are split exactly into three bf16 parts (split3: T in advance by
+// make_bf3_panels, Q1 rows when loaded) and each 32-column chunk of the
+// product takes the six significant bf16 products, summed from zero on the
+// matrix cores and added to the output in FP32 with round-to-nearest vector
+// adds.  A wave keeps its 16 rows of Q1, split, in registers (96 registers
+// for n = 256), so the product works in place.  Panel b of T (output columns
+// 16b..16b+15, chunks 0..b/2) is staged in LDS, double-buffered.
+typedef unsigned int u4b_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int bf3_panel_offset(int b) {
+  // sum over b' < b of (b'/2 + 1) chunks of 3 KiB
+  return 3072 * ((b & 1) ? ((b + 1) / 2) * ((b + 1) / 2) : (b / 2) * (b / 2 + 1));
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int n, int64_t ldq,
+                                                       const unsigned char* __restrict__ pan3) {
+  constexpr int NCH = (NB + 1) / 2;
+  constexpr int PMAX = NCH * 3072;
+  constexpr int STG = (PMAX / 16 + 255) / 256;
+  __shared__ __align__(16) unsigned char pbuf[2][PMAX];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
+  // Q1 row l16 of this wave, columns 32 ch + 8 lg + e: all loads are issued
+  // first; chunk ch is split into its three bf16 planes just before output
+  // panel 2 ch, the first that needs it, so the loads of later chunks
+  // overlap the earlier panels.
+  // Loads clamp the row and column (no branches): rows past m are never
+  // stored, and columns past n meet zero rows of T.
+  float xq[NCH][8];
+  const bool full = static_cast<int64_t>(blockIdx.x) * 64 + 64 <= m && n == 32 * NCH;
+  const float* qrow = Q + (row < m ? row : m - 1);
+  if (full) {
+    // lane base at column 8 lg; the chunk/element offsets are uniform
+    const float* qb0 = qrow + static_cast<int64_t>(8 * lg) * ldq;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xq[ch][e] = qb0[static_cast<int64_t>(32 * ch + e) * ldq];
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int col = 32 * ch + 8 * lg + e;
+        xq[ch][e] = qrow[static_cast<int64_t>(col < n ? col : n - 1) * ldq];
+      }
+  }
+  u4b_t qb[NCH][3];
+  auto split_chunk = [&](int ch) {
+    uint32_t hp[8], dp[8], lp[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) split3(xq[ch][e], hp[e], dp[e], lp[e]);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      qb[ch][0][w] = __builtin_amdgcn_perm(hp[2 * w + 1], hp[2 * w], 0x07060302u);
+      qb[ch][1][w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
+      qb[ch][2][w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
+    }
+  };
+  u4b_t stg[STG];
+  auto fetch = [&](int b) {
+    const int nv = ((b / 2) + 1) * 3072 / 16;
+    const u4b_t* src = reinterpret_cast<const u4b_t*>(pan3 + bf3_panel_offset(b));
+#pragma unroll
+    for (int q = 0; q < STG; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < nv) stg[q] = src[i];
+    }
+  };
+  auto store = [&](int buf, int b) {
+    const int nv = ((b / 2) + 1) * 3072 / 16;
+    u4b_t* dst = reinterpret_cast<u4b_t*>(pbuf[buf]);
+#pragma unroll
+    for (int q = 0; q < STG; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < nv) dst[i] = stg[q];
+    }
+  };
+  fetch(0);
+  store(0, 0);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) fetch(b + 1);
+    if ((b & 1) == 0) split_chunk(b / 2);
+    const u4b_t* pa = reinterpret_cast<const u4b_t*>(pbuf[b & 1]) + lane;
+    // One chain per chunk (independent, so the matrix cores pipeline them),
+    // each from zero; products grouped by T plane: d with d, h; l with h;
+    // h with l, d, h.
+    f4 c4[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) c4[ch] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tp = 1; tp < 4; ++tp) {
+      const int tpl = tp % 3;  // planes in the order d, l, h
+      bf8 tv[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (ch <= b / 2) tv[ch] = __builtin_bit_cast(bf8, pa[(3 * ch + tpl) * 64]);
+      const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
+#pragma unroll
+      for (int iq = 0; iq < 3; ++iq)
+        if (iq < nq) {
+          // d: (d, h)->planes 1, 0;  l: plane 0;  h: planes 2, 1, 0
+          const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            if (ch <= b / 2)
+              c4[ch] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  tv[ch], __builtin_bit_cast(bf8, qb[ch][qp]), c4[ch], 0, 0, 0);
+        }
+    }
+    f4 D = c4[0];
+#pragma unroll
+    for (int ch = 1; ch < NCH; ++ch)
+      if (ch <= b / 2) D += c4[ch];
+    float* qout = Q + row;
+    if (full) {
+      float* qo = qout + static_cast<int64_t>(drow<float>(lg, 0)) * ldq;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        qo[static_cast<int64_t>(16 * b + drow<float>(lg, v) - drow<float>(lg, 0)) * ldq] = D[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + drow<float>(lg, v);
+        if (row < m && col < n) qout[static_cast<int64_t>(col) * ldq] = D[v];
+      }
+    }
+    if (b + 1 < NB) {
+      store((b + 1) & 1, b + 1);
+      __syncthreads();
+    }
+  }
+}
+
 template <typename T, bool FULL>
 static hipError_t trmm_dispatch(int nb, T* Q, int64_t m, int n, int64_t ldq, const T* pan,
                                 const T* C, int64_t ldc, hipStream_t st) {
@@ -299,9 +482,24 @@ hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const v
                        hipStream_t st) {
   if (m == 0) return hipSuccess;
   const int nb = static_cast<int>(ceil_div(n, 16));
-  if (f32)
-    return trmm_dispatch<float, false>(nb, static_cast<float*>(Q), m, n, ldq,
-                                       static_cast<const float*>(pan), nullptr, 0, st);
+  if (f32) {
+    // pan holds bf16 x 3 panels (make_bf3_panels)
+    const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+    float* q = static_cast<float*>(Q);
+    const unsigned char* p3 = static_cast<const unsigned char*>(pan);
+#define RCQ_T3_CASE(NBV)                                                \
+  case NBV:                                                             \
+    trmm_bf3_kernel<NBV><<<grid, 256, 0, st>>>(q, m, n, ldq, p3);       \
+    break;
+    switch (nb) {
+      RCQ_T3_CASE(1) RCQ_T3_CASE(2) RCQ_T3_CASE(3) RCQ_T3_CASE(4) RCQ_T3_CASE(5) RCQ_T3_CASE(6)
+      RCQ_T3_CASE(7) RCQ_T3_CASE(8) RCQ_T3_CASE(9) RCQ_T3_CASE(10) RCQ_T3_CASE(11)
+      RCQ_T3_CASE(12) RCQ_T3_CASE(13) RCQ_T3_CASE(14) RCQ_T3_CASE(15) RCQ_T3_CASE(16)
+      default: return hipErrorInvalidValue;
+    }
+#undef RCQ_T3_CASE
+    return hipGetLastError();
+  }
   return trmm_dispatch<double, false>(nb, static_cast<double*>(Q), m, n, ldq,
                                       static_cast<const double*>(pan), nullptr, 0, st);
 }
@@ -335,7 +533,7 @@ struct GramRows {
 // for a second tall matrix B (ld ldb), all blocks (used by the adjoint).
 template <typename T, int NBB, bool CROSS>
 __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) void gram_kernel(
-    const T* __restrict__ Q, int64_t m, int n, int64_t ldq, int64_t rows_per_split,
+    const T* __restrict__ Q, int64_t m, int n, int64_t ldq, int64_t rows_per_split, int npg,
     double* __restrict__ gpart, const T* __restrict__ B, int64_t ldb) {
   typedef typename Acc4<T>::type A4;
   constexpr int NP = 64 * NBB;
@@ -366,7 +564,7 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
   }
   const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
-  double* dst = gpart + static_cast<int64_t>(s) * NP * NP;
+  double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
   A4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -378,7 +576,7 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
   // Element (a, b, v) of this lane sits at dst + lane_off + constant; the
   // offset is laundered at each flush so the 64 addresses are not kept live
   // across the row loop.
-  const int64_t lane_off = (64 * bi + drow<T>(lg, 0)) + static_cast<int64_t>(64 * bj + l16) * NP;
+  const int64_t lane_off = (64 * bi + drow<T>(lg, 0)) + static_cast<int64_t>(64 * bj + l16) * npg;
 #define RCQ_GRAM_FLUSH()                                                        \
   do {                                                                          \
     int64_t lo = lane_off;                                                      \
@@ -388,7 +586,7 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
     _Pragma("unroll") for (int b = 0; b < 4; ++b)                               \
     _Pragma("unroll") for (int v = 0; v < 4; ++v) {                             \
       double* p = base + (16 * a + (drow<T>(lg, v) - drow<T>(lg, 0))) +         \
-                  static_cast<int64_t>(16 * b) * NP;                            \
+                  static_cast<int64_t>(16 * b) * npg;                           \
       const double val = static_cast<double>(acc[a][b][v]);                     \
       *p = first ? val : *p + val;                                              \
       acc[a][b][v] = T(0);                                                      \
@@ -453,16 +651,182 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
   RCQ_GRAM_FLUSH();
 #undef RCQ_GRAM_FLUSH
 }
+// ----------------------------------------------------------------------------
+// Gram A = Q^T Q for FP32 Q on bf16 matrix cores.  Every FP32 entry splits
+// exactly into three bf16 parts (split3), and
+//   q q' ~ h h' + h d' + d h' + h l' + l h' + d d'
+// drops only terms below 2^-24 |q q'| (d l', l d', l l'), so each product is
+// as accurate as an FP32 product; the six bf16 products of a pair cost less
+// than one FP32 matrix-core product.  The matrix cores sum one 32-row step
+// from zero (a long accumulation inside the bf16 matrix-core instruction
+// drifts: ||Q^T Q - I|| ~ 1e-5 was measured at 4e6 rows); steps are added in
+// FP32 with round-to-nearest vector adds and folded into the workgroup's
+// FP64 partial every kGrFlush rows, as in gram_kernel.
+// Workgroup = 4 waves = one 128 x 128 block (I, J), I <= J, of the upper
+// triangle, each wave a 64 x 64 quarter; 32 rows per stage, split once by
+// the workgroup into three LDS planes laid out as the matrix-core operands:
+// 16-byte chunks (8 rows of a column), chunk-major with a 4-column pad, so
+// that both the operand reads (16 consecutive columns) and the split's
+// writes (4 chunks of 16 columns) hit distinct banks.  Workgroup ids are
+// dealt round-robin to the 8 XCDs; consecutive ids on one XCD take the
+// blocks of one row split, so its rows are fetched from HBM once.
+constexpr int kG3Cols = 256;          // LDS columns: block I's 128 then block J's 128
+constexpr int kG3Str = kG3Cols + 4;   // chunk row stride (16-byte units)
+
+__global__ __launch_bounds__(256) void gram_bf3_kernel(const float* __restrict__ Q, int64_t m, int n,
+                                                       int64_t ldq, int64_t rows_per_split, int npg,
+                                                       int nblk2, double* __restrict__ gpart) {
+  __shared__ __align__(16) u4v_t qs[3 * 4 * kG3Str];
+  const int nbp = nblk2 * (nblk2 + 1) / 2;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int s = (slot / nbp) * 8 + xcd;
+  int bidx = slot % nbp, BI = 0, BJ = 0;
+  for (int j = 0, c = 0; j < nblk2; ++j)
+    for (int i = 0; i <= j; ++i, ++c)
+      if (c == bidx) {
+        BI = i;
+        BJ = j;
+      }
+  const bool diag = BI == BJ;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int wa = wave & 1, wb = wave >> 1;  // this wave's 64 x 64 quarter
+  // LDS column of local column c (0..255): block I's columns at 0..127,
+  // block J's at 128..255 (the same as I's for a diagonal block).
+  const int ca0 = 64 * wa, cb0 = (diag ? 0 : 128) + 64 * wb;
+  const int ncols = diag ? 128 : 256;
+  const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
+  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  bool first = true;
+  const int gi0 = 128 * BI + 64 * wa, gj0 = 128 * BJ + 64 * wb;
+  const int64_t lane_off = (gi0 + drow<float>(lg, 0)) + static_cast<int64_t>(gj0 + l16) * npg;
+  auto flush = [&]() {
+    int64_t lo = lane_off;
+    asm volatile("" : "+v"(lo));
+    double* base = dst + lo;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
+                      static_cast<int64_t>(16 * b) * npg;
+          const double val = static_cast<double>(acc[a][b][v]);
+          *p = first ? val : *p + val;
+          acc[a][b][v] = 0.f;
+          if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+    first = false;
+  };
+  // Register prefetch of the next stage: task t = (local column t / 4,
+  // rows 8 (t % 4) ..); 4 tasks per thread (1024 for 256 columns).
+  float pre[4][8];
+  const bool vec = ((ldq & 3) == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  auto gcol = [&](int c) { return (c < 128 ? 128 * BI : 128 * BJ - 128) + c; };
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int c = t >> 2, g = t & 3;
+      const int gc = gcol(c);
+      const int64_t r = r0 + 8 * g;
+      const bool live = c < ncols && gc < n;
+      const float* src = Q + static_cast<int64_t>(live ? gc : 0) * ldq + r;
+      if (live && vec && r + 8 <= r_end) {
+        const float4 f0 = reinterpret_cast<const float4*>(src)[0];
+        const float4 f1 = reinterpret_cast<const float4*>(src)[1];
+        pre[q][0] = f0.x; pre[q][1] = f0.y; pre[q][2] = f0.z; pre[q][3] = f0.w;
+        pre[q][4] = f1.x; pre[q][5] = f1.y; pre[q][6] = f1.z; pre[q][7] = f1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pre[q][e] = (live && r + e < r_end) ? src[e] : 0.f;
+      }
+    }
+  };
+  if (r_begin < r_end) fetch(r_begin);
+  int64_t since = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kG3Rows) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int c = t >> 2, g = t & 3;
+      if (c < ncols) {
+        uint32_t hp[8], dp[8], lp[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) split3(pre[q][e], hp[e], dp[e], lp[e]);
+        u4v_t hv, dv, lv;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          hv[w] = __builtin_amdgcn_perm(hp[2 * w + 1], hp[2 * w], 0x07060302u);
+          dv[w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
+          lv[w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
+        }
+        qs[(0 * 4 + g) * kG3Str + c] = hv;
+        qs[(1 * 4 + g) * kG3Str + c] = dv;
+        qs[(2 * 4 + g) * kG3Str + c] = lv;
+      }
+    }
+    __syncthreads();
+    if (r0 + kG3Rows < r_end) fetch(r0 + kG3Rows);
+    // Operands: lane (l16, lg) holds rows 8 lg .. 8 lg + 7 of a column.
+    bf8 bh[4], bd[4], bl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = cb0 + 16 * t + l16;
+      bh[t] = __builtin_bit_cast(bf8, qs[(0 * 4 + lg) * kG3Str + c]);
+      bd[t] = __builtin_bit_cast(bf8, qs[(1 * 4 + lg) * kG3Str + c]);
+      bl[t] = __builtin_bit_cast(bf8, qs[(2 * 4 + lg) * kG3Str + c]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int c = ca0 + 16 * a + l16;
+      const bf8 ah = __builtin_bit_cast(bf8, qs[(0 * 4 + lg) * kG3Str + c]);
+      const bf8 ad = __builtin_bit_cast(bf8, qs[(1 * 4 + lg) * kG3Str + c]);
+      const bf8 al = __builtin_bit_cast(bf8, qs[(2 * 4 + lg) * kG3Str + c]);
+      // Four independent chains (one per column tile), each from zero.
+      f4 c4[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bd[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], c4[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd[b], c4[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += c4[b];
+    }
+    since += kG3Rows;
+    if (since >= kGrFlush) {
+      flush();
+      since = 0;
+    }
+  }
+  flush();
+}
+
 template <typename T, bool CROSS>
 static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const GramPlan& gp,
                                 double* gpart, const T* B, int64_t ldb, hipStream_t st) {
   const unsigned grid = static_cast<unsigned>(gp.nsplit);
   auto nw = [](int b) { return CROSS ? b * b : b * (b + 1) / 2; };
   switch (gp.nbb) {
-    case 1: gram_kernel<T, 1, CROSS><<<grid, 64 * nw(1), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
-    case 2: gram_kernel<T, 2, CROSS><<<grid, 64 * nw(2), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
-    case 3: gram_kernel<T, 3, CROSS><<<grid, 64 * nw(3), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
-    case 4: gram_kernel<T, 4, CROSS><<<grid, 64 * nw(4), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gpart, B, ldb); break;
+    case 1: gram_kernel<T, 1, CROSS><<<grid, 64 * nw(1), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gp.npg, gpart, B, ldb); break;
+    case 2: gram_kernel<T, 2, CROSS><<<grid, 64 * nw(2), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gp.npg, gpart, B, ldb); break;
+    case 3: gram_kernel<T, 3, CROSS><<<grid, 64 * nw(3), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gp.npg, gpart, B, ldb); break;
+    case 4: gram_kernel<T, 4, CROSS><<<grid, 64 * nw(4), 0, st>>>(Q, m, n, ldq, gp.rows_per_split, gp.npg, gpart, B, ldb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -470,8 +834,15 @@ static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const
 
 hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq, const GramPlan& gp,
                        double* gpart, hipStream_t st) {
-  if (f32)
-    return gram_dispatch<float, false>(static_cast<const float*>(Q), m, n, ldq, gp, gpart, nullptr, 0, st);
+  if (f32) {
+    // 128 x 128 blocks of the upper triangle (npg = 64 nbb is the partial's ld)
+    const int nblk2 = static_cast<int>(ceil_div(n, 128));
+    const unsigned grid = static_cast<unsigned>(gp.nsplit * (nblk2 * (nblk2 + 1) / 2));
+    if (gp.npg < 128 * nblk2 || gp.nsplit % 8 != 0) return hipErrorInvalidValue;
+    gram_bf3_kernel<<<grid, 256, 0, st>>>(static_cast<const float*>(Q), m, n, ldq,
+                                          gp.rows_per_split, gp.npg, nblk2, gpart);
+    return hipGetLastError();
+  }
   return gram_dispatch<double, false>(static_cast<const double*>(Q), m, n, ldq, gp, gpart, nullptr, 0, st);
 }
 
