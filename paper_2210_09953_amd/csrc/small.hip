@@ -127,55 +127,81 @@ __device__ __forceinline__ double vref(const double* A, int k, int n, const doub
 }
 
 // M(p0:k, c_begin + 16 blockIdx.x + 0..15) <- (I - V T' V^T) M(...) with
-// T' = T^T (trans = 1, factorisation) or T (trans = 0, forming S).
+// T' = T^T (trans = 1, factorisation) or T (trans = 0, forming S).  One
+// workgroup of 256 threads per 16-column block: the panel's reflectors V
+// (L x 16, L = k - p0) are staged once in LDS (rows of 16, padded to 18);
+// thread (c = tid / 16, g = tid % 16) keeps M(p0 + g + 16 q, column c) for
+// all q in registers, so every global load is issued up front.  W = V^T M
+// is summed per thread over its rows and across the 16 lanes of a column
+// by a butterfly, Y = T' W is formed redundantly by those lanes, and
+// M -= V Y is applied in registers and stored.
+constexpr int kHuLd = 18;                        // LDS row stride of V (doubles)
+constexpr int kHuQ = (kMaxK + 15) / 16;          // rows per thread, maximum
+
 __global__ __launch_bounds__(256) void hh_update_kernel(const double* __restrict__ A, int k,
                                                         int n, int p0, const double* __restrict__ v0g,
                                                         const double* __restrict__ Tp, int trans,
                                                         double* __restrict__ M, int64_t ldm,
                                                         int c_begin, int c_end) {
-  __shared__ double wpart[4][kHhPanel][kHhPanel + 1];
-  __shared__ double ys[kHhPanel][kHhPanel + 1];
-  const int cb = c_begin + kHhPanel * blockIdx.x;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  extern __shared__ double vs[];  // [L][kHuLd]
   const int L = k - p0;
-  const int nsteps = (L + 3) / 4;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s = wave; s < nsteps; s += 4) {
-    const int row = p0 + 4 * s + lg;
-    double a = 0.0, b = 0.0;
-    if (row < k) {
-      a = vref(A, k, n, v0g, row, p0 + l16);
-      if (cb + l16 < c_end) b = M[row + static_cast<int64_t>(cb + l16) * ldm];
+  const int nq = (L + 15) / 16;
+  const int tid = threadIdx.x, c = tid >> 4, g = tid & 15;
+  const int col = c_begin + kHhPanel * blockIdx.x + c;
+  const bool live = col < c_end;
+  double mq[kHuQ];
+#pragma unroll
+  for (int q = 0; q < kHuQ; ++q) {
+    const int r = g + 16 * q;
+    mq[q] = (q < nq && r < L && live) ? M[(p0 + r) + static_cast<int64_t>(col) * ldm] : 0.0;
+  }
+  for (int idx = tid; idx < kHhPanel * L; idx += 256) {
+    const int vc = idx / L, i = idx % L;
+    vs[i * kHuLd + vc] = vref(A, k, n, v0g, p0 + i, p0 + vc);
+  }
+  __syncthreads();
+  double w[kHhPanel];
+#pragma unroll
+  for (int i = 0; i < kHhPanel; ++i) w[i] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kHuQ; ++q) {
+    const int r = g + 16 * q;
+    if (q < nq && r < L) {
+      const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
+#pragma unroll
+      for (int j = 0; j < kHhPanel / 2; ++j) {
+        const double2 v = vr[j];
+        w[2 * j] += v.x * mq[q];
+        w[2 * j + 1] += v.y * mq[q];
+      }
     }
-    acc = mfma16x16x4(a, b, acc);
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) wpart[wave][drow<double>(lg, v)][l16] = acc[v];
-  __syncthreads();
-  {
-    const int i = tid / 16, c = tid % 16;
-    const double w = ((wpart[0][i][c] + wpart[1][i][c]) + wpart[2][i][c]) + wpart[3][i][c];
-    wpart[0][i][c] = w;
-  }
-  __syncthreads();
-  {
-    const int i = tid / 16, c = tid % 16;
-    double s = 0.0;
-    for (int l = 0; l < kHhPanel; ++l) {
-      const double t = trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l];
-      s += t * wpart[0][l][c];
-    }
-    ys[i][c] = s;
-  }
-  __syncthreads();
-  const int c = tid % 16;
-  if (cb + c >= c_end) return;
-  for (int r = tid / 16; r < L; r += 16) {
-    const int row = p0 + r;
-    double s = 0.0;
+  for (int i = 0; i < kHhPanel; ++i)
 #pragma unroll
-    for (int i = 0; i < kHhPanel; ++i) s += vref(A, k, n, v0g, row, p0 + i) * ys[i][c];
-    M[row + static_cast<int64_t>(cb + c) * ldm] -= s;
+    for (int off = 1; off < 16; off <<= 1) w[i] += __shfl_xor(w[i], off, 16);
+  double y[kHhPanel];
+#pragma unroll
+  for (int i = 0; i < kHhPanel; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < kHhPanel; ++l)
+      t += (trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l]) * w[l];
+    y[i] = t;
+  }
+#pragma unroll
+  for (int q = 0; q < kHuQ; ++q) {
+    const int r = g + 16 * q;
+    if (q < nq && r < L && live) {
+      const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < kHhPanel / 2; ++j) {
+        const double2 v = vr[j];
+        t += v.x * y[2 * j] + v.y * y[2 * j + 1];
+      }
+      M[(p0 + r) + static_cast<int64_t>(col) * ldm] = mq[q] - t;
+    }
   }
 }
 
@@ -234,6 +260,10 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             static_cast<int>(kHhPanel * kMaxK * sizeof(double)));
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(hh_update_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(kHuLd * kMaxK * sizeof(double)));
+    if (e != hipSuccess) return e;
     attr_done = true;
   }
   const int npan = static_cast<int>(ceil_div(n, kHhPanel));
@@ -244,8 +274,8 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     const int cstart = p0 + kHhPanel;
     if (cstart < n) {
       const int nblk = static_cast<int>(ceil_div(n - cstart, kHhPanel));
-      hh_update_kernel<<<nblk, 256, 0, st>>>(A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k,
-                                             cstart, n);
+      hh_update_kernel<<<nblk, 256, kHuLd * (k - p0) * sizeof(double), st>>>(
+          A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k, cstart, n);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -256,8 +286,8 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     for (int p = npan - 1; p >= 0; --p) {
       const int p0 = p * kHhPanel;
       const int nblk = static_cast<int>(ceil_div(n - p0, kHhPanel));
-      hh_update_kernel<<<nblk, 256, 0, st>>>(A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds,
-                                             p0, n);
+      hh_update_kernel<<<nblk, 256, kHuLd * (k - p0) * sizeof(double), st>>>(
+          A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds, p0, n);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
