@@ -16,15 +16,129 @@ stream; `cpu_baseline` is the FP64 CPU oracle timed on a bounded sample of
 rows of the same matrix on this host.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8.0e12, "f64": 78.6e12, "f32": 157.3e12, "f16": 2.5e15}
+PEAK = {"hbm": 8.0e12, "f64": 78.6e12, "f32": 157.3e12, "f16": 2.5e15, "i8": 5.0e15}
+
+# Size of the plain copy whose FETCH_SIZE / WRITE_SIZE readings turn the
+# counters of the other kernels into HBM bytes (--copy-probe).
+COPY_PROBE_BYTES = 1 << 30
+CSRC = os.path.join(ROOT, "paper_2210_09953_amd", "csrc")
+SHARED_HEADERS = ("common.h", "kernels.h", "theta.h")
+
+# The kernel that does the work of each phase, by precision, and its source.
+PHASE_KERNEL = {
+    "mixed": {"sketch": "rcq::sketch_i8_kernel", "small_qr": "rcq::hh_panel_kernel",
+              "solve1": "rcq::trsm_kernel<float", "gram": "rcq::gram_bf3_kernel",
+              "cholesky": "rcq::chol_kernel", "solve2": "rcq::trmm_bf3_kernel"},
+    "f32": {"sketch": "rcq::sketch_dense_kernel", "small_qr": "rcq::hh_panel_kernel",
+            "solve1": "rcq::trsm_kernel<float", "gram": "rcq::gram_bf3_kernel",
+            "cholesky": "rcq::chol_kernel", "solve2": "rcq::trmm_bf3_kernel"},
+    "f64": {"sketch": "rcq::sketch_dense_kernel", "small_qr": "rcq::hh_panel_kernel",
+            "solve1": "rcq::trsm_kernel<double", "gram": "rcq::gram_kernel<double",
+            "cholesky": "rcq::chol_kernel", "solve2": "rcq::trmm_kernel<double"},
+}
+KERNEL_SOURCE = (("sketch_i8", "mixed.hip"), ("sketch_", "sketch.hip"), ("count_", "sketch.hip"),
+                 ("hh_", "small.hip"),
+                 ("chol_", "small.hip"), ("make_bf3", "small.hip"), ("trsm_", "tall.hip"),
+                 ("trmm_", "tall.hip"), ("gram_", "tall.hip"), ("make_panels", "tall.hip"))
+
+
+def source_hash(kernel):
+    """sha256 of the source file that defines `kernel` and the shared headers."""
+    short = kernel.split("rcq::")[-1]
+    for prefix, fname in KERNEL_SOURCE:
+        if short.startswith(prefix):
+            h = hashlib.sha256()
+            for f in (fname,) + SHARED_HEADERS:
+                with open(os.path.join(CSRC, f), "rb") as fh:
+                    h.update(fh.read())
+            return h.hexdigest()[:16]
+    return None
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+
+
+def pmc_per_kernel(run_dir, counter):
+    """{kernel: (dispatches, mean counter value)} from one rocprofv3 --pmc run."""
+    import sqlite3
+    tot, disp = {}, {}
+    for db in glob.glob(os.path.join(run_dir, "**", "*.db"), recursive=True):
+        cur = sqlite3.connect(db).cursor()
+        for name, cn, val, d in cur.execute(
+                "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+            if cn != counter:
+                continue
+            short = re.sub(r"\(.*", "", name).replace("void ", "").strip()
+            tot[short] = tot.get(short, 0.0) + val
+            disp.setdefault(short, set()).add(d)
+    return {k: (len(disp[k]), tot[k] / len(disp[k])) for k in tot}
+
+
+def summarize_pmc(workload, fetch_dir, write_dir, command):
+    """Write profiles/traffic_<workload>.md: HBM bytes per dispatch of every
+    library kernel, FETCH_SIZE and WRITE_SIZE (KiB) each scaled by what the
+    counter reads for the plain copy of COPY_PROBE_BYTES bytes."""
+    f = pmc_per_kernel(fetch_dir, "FETCH_SIZE")
+    w = pmc_per_kernel(write_dir, "WRITE_SIZE")
+    copy = "rcq::hbm_copy_kernel"
+    if copy not in f or copy not in w:
+        raise SystemExit("copy probe kernel missing from the counter runs (--copy-probe)")
+    ff = COPY_PROBE_BYTES / (f[copy][1] * 1024.0)
+    wf = COPY_PROBE_BYTES / (w[copy][1] * 1024.0)
+    rows, kern = [], {}
+    for k in sorted(set(f) & set(w)):
+        if not k.startswith("rcq::") or k == copy:
+            continue
+        b = f[k][1] * 1024.0 * ff + w[k][1] * 1024.0 * wf
+        kern[k] = {"dispatches": f[k][0], "fetch_kib": round(f[k][1], 1),
+                   "write_kib": round(w[k][1], 1), "hbm_bytes": round(b), "src": source_hash(k)}
+        rows.append(f"| `{k}` | {f[k][0]} | {f[k][1]:.1f} | {w[k][1]:.1f} | {b / 1e9:.4f} |")
+    rec = {"workload": workload, "copy_bytes": COPY_PROBE_BYTES,
+           "copy_fetch_kib": f[copy][1], "copy_write_kib": w[copy][1],
+           "fetch_factor": ff, "write_factor": wf, "kernels": kern}
+    txt = [f"# HBM traffic per dispatch, workload {workload}", "",
+           "Commands (repository root, one MI355X; one counter per run):", "",
+           "    " + command.replace("COUNTER", "FETCH_SIZE").replace("DIR", fetch_dir),
+           "    " + command.replace("COUNTER", "WRITE_SIZE").replace("DIR", write_dir),
+           "    python3 bench.py --workload " + workload + f" --summarize-pmc {fetch_dir} {write_dir}",
+           "",
+           f"Copy reference: {COPY_PROBE_BYTES} bytes read and written by `rcq::hbm_copy_kernel`;",
+           f"FETCH_SIZE read {f[copy][1]:.1f} KiB (factor {ff:.4f}), "
+           f"WRITE_SIZE read {w[copy][1]:.1f} KiB (factor {wf:.4f}).",
+           "HBM bytes = FETCH_SIZE x 1024 x fetch factor + WRITE_SIZE x 1024 x write factor.",
+           "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM GB |",
+           "|---|---:|---:|---:|---:|"] + rows + ["", "Record read by bench.py:", "",
+                                                  "    " + json.dumps(rec), ""]
+    with open(traffic_file(workload), "w") as fh:
+        fh.write("\n".join(txt))
+    print("\n".join(txt))
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel's source changed since."""
+    try:
+        with open(traffic_file(workload)) as fh:
+            line = [l for l in fh if l.strip().startswith("{")][-1]
+        rec = json.loads(line)["kernels"]
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+    for k, v in rec.items():
+        if k.startswith(kernel) and v.get("src") == source_hash(k):
+            return v["hbm_bytes"]
+    return None
 
 WORKLOADS = {
     # name: (m, n, k, kind, sigma_min, value precision, x dtype bytes)
@@ -52,7 +166,7 @@ def phase_model(phase, m, n, k, kind, prec):
     if phase == "sketch":
         if kind == "countsketch":
             return float(m * n), float(m * n * s), "hbm"
-        return 2.0 * m * k * n, float(m * n * s), ("f16" if prec == "mixed" else "f64")
+        return 2.0 * m * k * n, float(m * n * s), ("i8" if prec == "mixed" else "f64")
     if phase in ("solve1", "solve2"):
         return float(m) * n * n, 2.0 * m * n * s, mm
     if phase == "gram":
@@ -60,20 +174,28 @@ def phase_model(phase, m, n, k, kind, prec):
     return 0.0, 0.0, "f64"
 
 
-def roofline(phase, ms_per_launch, m, n, k, kind, prec):
+def phase_kernel(phase, kind, prec):
+    if phase == "sketch" and kind == "countsketch":
+        return "rcq::count_accum_kernel"
+    return PHASE_KERNEL[prec][phase]
+
+
+def roofline(phase, ms_per_launch, m, n, k, kind, prec, traffic=None):
     flops, nbytes, unit = phase_model(phase, m, n, k, kind, prec)
+    kname = phase_kernel(phase, kind, prec)
     t_mem = nbytes / PEAK["hbm"]
     t_cmp = flops / PEAK[unit] if unit != "hbm" else 0.0
     t = ms_per_launch * 1e-3
     if t_cmp > t_mem:
         a = flops / t / 1e12
         return {"bound": "mfma", "achieved": round(a, 3), "peak": PEAK[unit] / 1e12,
-                "unit": "TFLOP/s", "frac": round(a * 1e12 / PEAK[unit], 4), "traffic": None,
-                "kernel": phase, "dtype": unit, "ms_per_launch": round(ms_per_launch, 4),
+                "unit": "TFLOP/s", "frac": round(a * 1e12 / PEAK[unit], 4), "traffic": traffic,
+                "kernel": kname, "phase": phase, "dtype": unit, "ms_per_launch": round(ms_per_launch, 4),
                 "flops_per_launch": flops, "bytes_per_launch": nbytes}
     a = nbytes / t / 1e9
     return {"bound": "hbm", "achieved": round(a, 1), "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-            "frac": round(a * 1e9 / PEAK["hbm"], 4), "traffic": None, "kernel": phase,
+            "frac": round(a * 1e9 / PEAK["hbm"], 4), "traffic": traffic, "kernel": kname,
+            "phase": phase,
             "ms_per_launch": round(ms_per_launch, 4), "flops_per_launch": flops,
             "bytes_per_launch": nbytes}
 
@@ -154,7 +276,17 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain copy of 1 GiB (byte-counter reference)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs into profiles/traffic_<workload>.md")
+    ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
+                    "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg --copy-probe")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
+                      args.pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
@@ -185,7 +317,15 @@ def main():
     log(f"[bench] {prec}: {ms:.3f} ms/step {value:.1f} GB/s orth={orth:.2e} resid={res:.2e} "
         f"phases={ {p: round(v, 4) for p, v in phases.items()} }")
     dom = max(phases, key=phases.get)
-    roof = roofline(dom, phases[dom], m, n, k, W["kind"], prec)
+    traffic = measured_traffic(args.workload, phase_kernel(dom, W["kind"], prec))
+    roof = roofline(dom, phases[dom], m, n, k, W["kind"], prec, traffic)
+    if args.copy_probe:
+        # Known-size plain copy for scaling the byte counters (outside the timed region).
+        src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        rq.device_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
     R_value = R.clone()
     del Q
 
@@ -223,7 +363,7 @@ def main():
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "mixed": "f16+f32+f64"}[prec],
+        "dtype": {"f64": "f64", "f32": "f32", "mixed": "i8+bf16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "sketch": W["kind"],
                    "passes": 2, "sigma_min": W["sigma"], "x_dtype": str(xdt).split(".")[-1],

@@ -206,6 +206,14 @@ int rcholqr_backward(const void* X, int64_t m, int64_t n, int64_t ldx,
 int rcholqr_profile_enable(int on);
 int rcholqr_profile_read(double* ms);
 
+/* Plain device-to-device copy of `bytes` bytes (a multiple of 16) from src
+ * to dst (device pointers, 16-byte aligned, not overlapping) on `stream`,
+ * 16 bytes per lane.  It is the known-size reference against which hardware
+ * byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels are scaled to
+ * HBM bytes.  Returns -1/-2 for a null or misaligned src/dst, -3 if bytes is
+ * not a multiple of 16, RCHOLQR_ERR_HIP if the launch failed. */
+int rcholqr_device_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Human-readable text for a return code or status value. */
 const char* rcholqr_error_string(int code);
 

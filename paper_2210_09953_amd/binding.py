@@ -74,6 +74,8 @@ def lib():
     L.rcholqr_profile_enable.restype = i32
     L.rcholqr_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
     L.rcholqr_profile_read.restype = i32
+    L.rcholqr_device_copy.argtypes = [vp, vp, sz, vp]
+    L.rcholqr_device_copy.restype = i32
     L.rcholqr_error_string.argtypes = [i32]
     L.rcholqr_error_string.restype = ctypes.c_char_p
     _LIB = L
@@ -229,6 +231,15 @@ def profile_read():
     if n < 0:
         raise RCholQRError(n, "rcholqr_profile_read")
     return n, {p: float(ms[i]) for i, p in enumerate(PHASES)}
+
+
+def device_copy(src, dst):
+    """Plain device copy of src into dst (same byte size, 16-byte multiple)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("device_copy: src and dst byte sizes differ")
+    _check(lib().rcholqr_device_copy(_ptr(src), _ptr(dst), nb, _stream()),
+           "rcholqr_device_copy")
 
 
 def backward(X, Rs, Rp, dQ, dR=None, precision=None, dX=None, ws=None):

@@ -10,6 +10,7 @@
 //               -> R = R' R_s -> panel packing of R' -> solve in place
 //                                                                 Q = Q1 R'^{-1}
 #include <math.h>
+#include <algorithm>
 #include <string.h>
 
 #include "../../include/rcholqr.h"
@@ -62,25 +63,23 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   GramPlan& gp = L.gp;
   gp.nbb = static_cast<int>(ceil_div(n, 64));
   gp.npg = 128 * static_cast<int>(ceil_div(n, 128));  // ld of the partials: whole 128-blocks
-  // Row splits: a multiple of 8 (the XCD-aware decode of the FP32 Gram),
-  // chosen so that the FP32 Gram's grid (splits x 128-blocks, two 4-wave
-  // workgroups per CU) fills whole rounds; splits past m stay empty.
-  {
-    const int64_t nbp = ceil_div(n, 128) * (ceil_div(n, 128) + 1) / 2;
+  if (prec == kPrecF64) {
+    // Row splits for the FP64 Gram: a multiple of 8, at most 256.
     const int64_t maxs = round_up(ceil_div(m, 16), 8);
-    int64_t best = 8;
-    double best_score = -1.0;
-    for (int64_t ns = 8; ns <= 256 && ns <= maxs; ns += 8) {
-      const int64_t w = ns * nbp;
-      const double eff = static_cast<double>(w) / (512.0 * ceil_div(w, 512));
-      const double score = eff - ((w < 256) ? 0.5 : 0.0) - 1e-4 * static_cast<double>(w / 512);
-      if (score > best_score + 1e-9) {
-        best_score = score;
-        best = ns;
-      }
-    }
-    gp.rows_per_split = round_up(ceil_div(m, best), 16);
-    gp.nsplit = static_cast<int>(best);
+    const int64_t ns = maxs < 256 ? maxs : 256;
+    gp.rows_per_split = round_up(ceil_div(m, ns), 16);
+    gp.nsplit = static_cast<int>(ns);
+  } else {
+    // FP32 Gram on bf16 matrix cores: one workgroup per row split holds the
+    // whole triangle; as many splits as workgroups fit on the 256 CUs at
+    // once (fewer, waves per CU, for wider n), each of at least 256 rows.
+    const int nb64 = static_cast<int>(ceil_div(n, 64));
+    const int64_t per_cu = nb64 >= 3 ? 1 : (nb64 == 2 ? 2 : 6);
+    int64_t ns = 256 * per_cu;
+    const int64_t maxs = ceil_div(m, 256);
+    if (ns > maxs) ns = maxs < 1 ? 1 : maxs;
+    gp.rows_per_split = round_up(ceil_div(m, ns), 32);
+    gp.nsplit = static_cast<int>(ceil_div(m, gp.rows_per_split));
   }
 
   const size_t esz = (prec == kPrecF64) ? sizeof(double) : sizeof(float);
@@ -270,6 +269,17 @@ size_t batched_offset(const rcholqr_problem* probs, int i, int kind, int passes,
 
 }  // namespace
 
+namespace rcq {
+// Plain 16-byte-vector device copy: the byte-count reference for HBM counters.
+__global__ __launch_bounds__(256) void hbm_copy_kernel(const uint4* __restrict__ src,
+                                                       uint4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += stride)
+    dst[i] = src[i];
+}
+}  // namespace rcq
+
 extern "C" {
 
 int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
@@ -434,6 +444,18 @@ int rcholqr_backward(const void* X, int64_t m, int64_t n, int64_t ldx, const dou
   void* dX_rev = static_cast<char*>(dX) + static_cast<size_t>(n - 1) * lddx * esz;
   RCQ_TRY(launch_trsm(dX_rev, f32, m, ni, -lddx, pan, dX_rev, -lddx, st));
   return 0;
+}
+
+int rcholqr_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || (reinterpret_cast<uintptr_t>(src) & 15)) return -1;
+  if (!dst || (reinterpret_cast<uintptr_t>(dst) & 15)) return -2;
+  if (bytes & 15) return -3;
+  const int64_t n16 = static_cast<int64_t>(bytes / 16);
+  if (n16 == 0) return 0;
+  const int blocks = static_cast<int>(std::min<int64_t>((n16 + 255) / 256, 8192));
+  hbm_copy_kernel<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
+      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  return hipGetLastError() == hipSuccess ? 0 : RCHOLQR_ERR_HIP;
 }
 
 int rcholqr_profile_enable(int on) {

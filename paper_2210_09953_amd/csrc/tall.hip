@@ -662,83 +662,119 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
 // drifts: ||Q^T Q - I|| ~ 1e-5 was measured at 4e6 rows); steps are added in
 // FP32 with round-to-nearest vector adds and folded into the workgroup's
 // FP64 partial every kGrFlush rows, as in gram_kernel.
-// Workgroup = 4 waves = one 128 x 128 block (I, J), I <= J, of the upper
-// triangle, each wave a 64 x 64 quarter; 32 rows per stage, split once by
-// the workgroup into three LDS planes laid out as the matrix-core operands:
-// 16-byte chunks (8 rows of a column), chunk-major with a 4-column pad, so
-// that both the operand reads (16 consecutive columns) and the split's
-// writes (4 chunks of 16 columns) hit distinct banks.  Workgroup ids are
-// dealt round-robin to the 8 XCDs; consecutive ids on one XCD take the
-// blocks of one row split, so its rows are fetched from HBM once.
-constexpr int kG3Cols = 256;          // LDS columns: block I's 128 then block J's 128
-constexpr int kG3Str = kG3Cols + 4;   // chunk row stride (16-byte units)
+//
+// One workgroup owns one row range and the whole upper triangle, in 64 x 64
+// tiles: one wave per off-diagonal tile, one wave per diagonal tile (two
+// for n > 192; only the 10 upper 16 x 16 sub-tiles of a diagonal tile are
+// formed), so every row of Q is fetched and split exactly once.  For
+// n = 256: 6 + 2 = 8 waves, at most 36 sub-tile products per SIMD and stage.  Stages of 32 rows are
+// double buffered in LDS as three bf16 planes laid out as the matrix-core
+// operands: 16-byte chunks (8 rows of one column), chunk-major with a
+// 2-chunk pad, so that the operand reads (16 consecutive columns) and the
+// split's writes (2 columns x 4 row groups per 8 lanes) hit distinct banks.
+// The next stage's loads are issued before the current stage's products.
+template <int NB64>
+struct TriGram {
+  static constexpr int kOff = NB64 * (NB64 - 1) / 2;  // off-diagonal 64 x 64 tiles
+  static constexpr int kDpw = NB64 == 4 ? 2 : 1;      // diagonal tiles per wave
+  static constexpr int kWaves = kOff + (NB64 + kDpw - 1) / kDpw;
+  static constexpr int kAcc = 10 * kDpw > 16 ? 10 * kDpw : 16;
+  static constexpr int kCols = 64 * NB64;
+  static constexpr int kStr = kCols + 2;               // chunk row stride (16-byte units)
+  static constexpr int kBuf = 3 * 4 * kStr;            // chunks per stage buffer
+  static constexpr int kTasks = 4 * kCols;             // 8-row pieces per stage
+  static constexpr int kPer = (kTasks + 64 * kWaves - 1) / (64 * kWaves);
+  static constexpr size_t kLds = 2 * kBuf * 16;
+};
 
-__global__ __launch_bounds__(256) void gram_bf3_kernel(const float* __restrict__ Q, int64_t m, int n,
-                                                       int64_t ldq, int64_t rows_per_split, int npg,
-                                                       int nblk2, double* __restrict__ gpart) {
-  __shared__ __align__(16) u4v_t qs[3 * 4 * kG3Str];
-  const int nbp = nblk2 * (nblk2 + 1) / 2;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int s = (slot / nbp) * 8 + xcd;
-  int bidx = slot % nbp, BI = 0, BJ = 0;
-  for (int j = 0, c = 0; j < nblk2; ++j)
-    for (int i = 0; i <= j; ++i, ++c)
-      if (c == bidx) {
-        BI = i;
-        BJ = j;
-      }
-  const bool diag = BI == BJ;
+template <int NB64>
+__global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
+    const float* __restrict__ Q, int64_t m, int n, int64_t ldq, int64_t rows_per_split, int npg,
+    double* __restrict__ gpart) {
+  typedef TriGram<NB64> G;
+  extern __shared__ __align__(16) u4v_t qs3[];
+  const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int wa = wave & 1, wb = wave >> 1;  // this wave's 64 x 64 quarter
-  // LDS column of local column c (0..255): block I's columns at 0..127,
-  // block J's at 128..255 (the same as I's for a diagonal block).
-  const int ca0 = 64 * wa, cb0 = (diag ? 0 : 128) + 64 * wb;
-  const int ncols = diag ? 128 : 256;
+  const bool offd = wave < G::kOff;
+  // Off-diagonal wave: tile (ti, tj), ti < tj.  Diagonal wave: tiles
+  // d0 .. d0 + ndiag - 1.
+  int ti = 0, tj = 0;
+  for (int j = 1, c = 0; j < NB64; ++j)
+    for (int i = 0; i < j; ++i, ++c)
+      if (c == wave) {
+        ti = i;
+        tj = j;
+      }
+  const int d0 = G::kDpw * (wave - G::kOff);
+  const int ndiag = offd ? 0 : ((d0 + G::kDpw <= NB64) ? G::kDpw : NB64 - d0);
   const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
-  f4 acc[4][4];
+
+  // Accumulators: off-diagonal sub-tile (a, b) at 4 a + b; diagonal tile t,
+  // sub-tile (a <= b) at 10 t + (rank of (a, b) in row order).
+  f4 acc[G::kAcc];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < G::kAcc; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
   bool first = true;
-  const int gi0 = 128 * BI + 64 * wa, gj0 = 128 * BJ + 64 * wb;
-  const int64_t lane_off = (gi0 + drow<float>(lg, 0)) + static_cast<int64_t>(gj0 + l16) * npg;
   auto flush = [&]() {
-    int64_t lo = lane_off;
-    asm volatile("" : "+v"(lo));
-    double* base = dst + lo;
+    if (offd) {
+      int64_t lo = (64 * ti + drow<float>(lg, 0)) + static_cast<int64_t>(64 * tj + l16) * npg;
+      asm volatile("" : "+v"(lo));
+      double* base = dst + lo;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
-                      static_cast<int64_t>(16 * b) * npg;
-          const double val = static_cast<double>(acc[a][b][v]);
-          *p = first ? val : *p + val;
-          acc[a][b][v] = 0.f;
-          if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);
+          for (int v = 0; v < 4; ++v) {
+            double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
+                        static_cast<int64_t>(16 * b) * npg;
+            const double val = static_cast<double>(acc[4 * a + b][v]);
+            *p = first ? val : *p + val;
+            acc[4 * a + b][v] = 0.f;
+            if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+    } else {
+#pragma unroll
+      for (int t = 0; t < G::kDpw; ++t) {
+        if (t < ndiag) {
+          const int td = d0 + t;
+          int64_t lo = (64 * td + drow<float>(lg, 0)) + static_cast<int64_t>(64 * td + l16) * npg;
+          asm volatile("" : "+v"(lo));
+          double* base = dst + lo;
+          int idx = 10 * t;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = a; b < 4; ++b, ++idx)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
+                            static_cast<int64_t>(16 * b) * npg;
+                const double val = static_cast<double>(acc[idx][v]);
+                *p = first ? val : *p + val;
+                acc[idx][v] = 0.f;
+                if (v == 3) __builtin_amdgcn_sched_barrier(0);
+              }
         }
+      }
+    }
     first = false;
   };
-  // Register prefetch of the next stage: task t = (local column t / 4,
-  // rows 8 (t % 4) ..); 4 tasks per thread (1024 for 256 columns).
-  float pre[4][8];
+
+  // Loads: task t = (column t / 4, rows 8 (t % 4) ..); kPer tasks per thread.
+  float pre[G::kPer][8];
   const bool vec = ((ldq & 3) == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
-  auto gcol = [&](int c) { return (c < 128 ? 128 * BI : 128 * BJ - 128) + c; };
   auto fetch = [&](int64_t r0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = threadIdx.x + 256 * q;
+    for (int q = 0; q < G::kPer; ++q) {
+      const int t = threadIdx.x + 64 * G::kWaves * q;
       const int c = t >> 2, g = t & 3;
-      const int gc = gcol(c);
       const int64_t r = r0 + 8 * g;
-      const bool live = c < ncols && gc < n;
-      const float* src = Q + static_cast<int64_t>(live ? gc : 0) * ldq + r;
+      const bool live = t < G::kTasks && c < n;
+      const float* src = Q + static_cast<int64_t>(live ? c : 0) * ldq + r;
       if (live && vec && r + 8 <= r_end) {
         const float4 f0 = reinterpret_cast<const float4*>(src)[0];
         const float4 f1 = reinterpret_cast<const float4*>(src)[1];
@@ -750,15 +786,12 @@ __global__ __launch_bounds__(256) void gram_bf3_kernel(const float* __restrict__
       }
     }
   };
-  if (r_begin < r_end) fetch(r_begin);
-  int64_t since = 0;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kG3Rows) {
-    __syncthreads();
+  auto stage_in = [&](u4v_t* buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = threadIdx.x + 256 * q;
-      const int c = t >> 2, g = t & 3;
-      if (c < ncols) {
+    for (int q = 0; q < G::kPer; ++q) {
+      const int t = threadIdx.x + 64 * G::kWaves * q;
+      if (t < G::kTasks) {
+        const int c = t >> 2, g = t & 3;
         uint32_t hp[8], dp[8], lp[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) split3(pre[q][e], hp[e], dp[e], lp[e]);
@@ -769,45 +802,94 @@ __global__ __launch_bounds__(256) void gram_bf3_kernel(const float* __restrict__
           dv[w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
           lv[w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
         }
-        qs[(0 * 4 + g) * kG3Str + c] = hv;
-        qs[(1 * 4 + g) * kG3Str + c] = dv;
-        qs[(2 * 4 + g) * kG3Str + c] = lv;
+        buf[(0 * 4 + g) * G::kStr + c] = hv;
+        buf[(1 * 4 + g) * G::kStr + c] = dv;
+        buf[(2 * 4 + g) * G::kStr + c] = lv;
       }
     }
+  };
+  // Operands of the 16 columns starting at c0: lane (l16, lg) holds rows
+  // 8 lg .. 8 lg + 7 of column c0 + l16, in each plane.
+  auto opnd = [&](const u4v_t* buf, int p, int c0) {
+    return __builtin_bit_cast(bf8, buf[(p * 4 + lg) * G::kStr + c0 + l16]);
+  };
+  if (r_begin < r_end) {
+    fetch(r_begin);
+    stage_in(qs3);
+  }
+  __syncthreads();
+  int64_t since = 0;
+  int cur = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kG3Rows) {
+    const bool more = r0 + kG3Rows < r_end;
+    if (more) fetch(r0 + kG3Rows);
+    const u4v_t* buf = qs3 + cur * G::kBuf;
+    if (offd) {
+      bf8 bh[4], bd[4], bl[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        bh[b] = opnd(buf, 0, 64 * tj + 16 * b);
+        bd[b] = opnd(buf, 1, 64 * tj + 16 * b);
+        bl[b] = opnd(buf, 2, 64 * tj + 16 * b);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const bf8 ah = opnd(buf, 0, 64 * ti + 16 * a);
+        const bf8 ad = opnd(buf, 1, 64 * ti + 16 * a);
+        const bf8 al = opnd(buf, 2, 64 * ti + 16 * a);
+        // Four independent chains (one per column sub-tile), each from zero,
+        // smallest products first.
+        f4 c4[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bd[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], c4[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd[b], c4[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], c4[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[4 * a + b] += c4[b];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < G::kDpw; ++t) {
+        if (t < ndiag) {
+          const int c0 = 64 * (d0 + t);
+          bf8 oh[4], od[4], ol[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            oh[b] = opnd(buf, 0, c0 + 16 * b);
+            od[b] = opnd(buf, 1, c0 + 16 * b);
+            ol[b] = opnd(buf, 2, c0 + 16 * b);
+          }
+          // The 10 upper sub-tiles as 10 independent chains.
+          f4 c10[10];
+#define RCQ_G3_TRI(STMT)                                                      \
+  {                                                                           \
+    int i_ = 0;                                                               \
+    _Pragma("unroll") for (int a = 0; a < 4; ++a)                             \
+    _Pragma("unroll") for (int b = a; b < 4; ++b, ++i_) { STMT; }             \
+  }
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(od[a], od[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0))
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ol[a], oh[b], c10[i_], 0, 0, 0))
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], ol[b], c10[i_], 0, 0, 0))
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(od[a], oh[b], c10[i_], 0, 0, 0))
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], od[b], c10[i_], 0, 0, 0))
+          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], oh[b], c10[i_], 0, 0, 0))
+          RCQ_G3_TRI(acc[10 * t + i_] += c10[i_])
+#undef RCQ_G3_TRI
+        }
+      }
+    }
+    if (more) stage_in(qs3 + (cur ^ 1) * G::kBuf);
     __syncthreads();
-    if (r0 + kG3Rows < r_end) fetch(r0 + kG3Rows);
-    // Operands: lane (l16, lg) holds rows 8 lg .. 8 lg + 7 of a column.
-    bf8 bh[4], bd[4], bl[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = cb0 + 16 * t + l16;
-      bh[t] = __builtin_bit_cast(bf8, qs[(0 * 4 + lg) * kG3Str + c]);
-      bd[t] = __builtin_bit_cast(bf8, qs[(1 * 4 + lg) * kG3Str + c]);
-      bl[t] = __builtin_bit_cast(bf8, qs[(2 * 4 + lg) * kG3Str + c]);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int c = ca0 + 16 * a + l16;
-      const bf8 ah = __builtin_bit_cast(bf8, qs[(0 * 4 + lg) * kG3Str + c]);
-      const bf8 ad = __builtin_bit_cast(bf8, qs[(1 * 4 + lg) * kG3Str + c]);
-      const bf8 al = __builtin_bit_cast(bf8, qs[(2 * 4 + lg) * kG3Str + c]);
-      // Four independent chains (one per column tile), each from zero.
-      f4 c4[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bd[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], c4[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd[b], c4[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += c4[b];
-    }
+    cur ^= 1;
     since += kG3Rows;
     if (since >= kGrFlush) {
       flush();
@@ -835,12 +917,24 @@ static hipError_t gram_dispatch(const T* Q, int64_t m, int n, int64_t ldq, const
 hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq, const GramPlan& gp,
                        double* gpart, hipStream_t st) {
   if (f32) {
-    // 128 x 128 blocks of the upper triangle (npg = 64 nbb is the partial's ld)
-    const int nblk2 = static_cast<int>(ceil_div(n, 128));
-    const unsigned grid = static_cast<unsigned>(gp.nsplit * (nblk2 * (nblk2 + 1) / 2));
-    if (gp.npg < 128 * nblk2 || gp.nsplit % 8 != 0) return hipErrorInvalidValue;
-    gram_bf3_kernel<<<grid, 256, 0, st>>>(static_cast<const float*>(Q), m, n, ldq,
-                                          gp.rows_per_split, gp.npg, nblk2, gpart);
+    const int nb64 = static_cast<int>(ceil_div(n, 64));
+    if (gp.npg < 64 * nb64) return hipErrorInvalidValue;
+    const float* Qf = static_cast<const float*>(Q);
+#define RCQ_G3_CASE(NB)                                                                      \
+  case NB: {                                                                                 \
+    const hipError_t e = hipFuncSetAttribute(                                                \
+        reinterpret_cast<const void*>(&gram_bf3_kernel<NB>),                                 \
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(TriGram<NB>::kLds));    \
+    if (e != hipSuccess) return e;                                                           \
+    gram_bf3_kernel<NB><<<gp.nsplit, 64 * TriGram<NB>::kWaves, TriGram<NB>::kLds, st>>>(    \
+        Qf, m, n, ldq, gp.rows_per_split, gp.npg, gpart);                                    \
+    break;                                                                                   \
+  }
+    switch (nb64) {
+      RCQ_G3_CASE(1) RCQ_G3_CASE(2) RCQ_G3_CASE(3) RCQ_G3_CASE(4)
+      default: return hipErrorInvalidValue;
+    }
+#undef RCQ_G3_CASE
     return hipGetLastError();
   }
   return gram_dispatch<double, false>(static_cast<const double*>(Q), m, n, ldq, gp, gpart, nullptr, 0, st);

@@ -70,3 +70,14 @@ def test_batched_argument_errors_without_gpu():
     assert L.rcholqr_factor_batched(probs, 3, 7, 2, rq.MIXED, vp, 1 << 30, None) == -3
     probs[2].k = 96
     assert L.rcholqr_factor_batched(probs, 3, rq.RADEMACHER, 2, rq.MIXED, vp, 64, None) == -7
+
+
+def test_device_copy_argument_errors_without_gpu():
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    vp = ctypes.c_void_p
+    assert L.rcholqr_device_copy(vp(0), vp(256), 16, None) == -1
+    assert L.rcholqr_device_copy(vp(8), vp(256), 16, None) == -1
+    assert L.rcholqr_device_copy(vp(256), vp(264), 16, None) == -2
+    assert L.rcholqr_device_copy(vp(256), vp(512), 15, None) == -3
+    assert L.rcholqr_device_copy(vp(256), vp(512), 0, None) == 0

@@ -287,3 +287,12 @@ def test_mixed_two_pass(rq, orc, m, n, k, sig):
     assert orth <= 1e-6
     assert res <= 1e-5
     assert dR <= 1e-4 and dQ <= 1e-3
+
+
+def test_device_copy_is_exact(rq):
+    import torch
+    src = torch.randint(0, 256, (3 << 20,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    rq.device_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
