@@ -27,7 +27,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8.0e12, "f64": 78.6e12, "f32": 157.3e12, "f16": 2.5e15, "i8": 5.0e15}
+PEAK = {"hbm": 8.0e12, "f64": 78.6e12, "f32": 157.3e12, "f16": 2.5e15, "i8": 5.0e15,
+        "bf16x3": 2.5e15 / 6}
 
 # Size of the plain copy whose FETCH_SIZE / WRITE_SIZE readings turn the
 # counters of the other kernels into HBM bytes (--copy-probe).
@@ -38,10 +39,10 @@ SHARED_HEADERS = ("common.h", "kernels.h", "theta.h")
 # The kernel that does the work of each phase, by precision, and its source.
 PHASE_KERNEL = {
     "mixed": {"sketch": "rcq::sketch_i8_kernel", "small_qr": "rcq::hh_panel_kernel",
-              "solve1": "rcq::trsm_kernel<float", "gram": "rcq::gram_bf3_kernel",
+              "solve1": "rcq::trsm_bf3_kernel", "gram": "rcq::gram_bf3_kernel",
               "cholesky": "rcq::chol_kernel", "solve2": "rcq::trmm_bf3_kernel"},
     "f32": {"sketch": "rcq::sketch_dense_kernel", "small_qr": "rcq::hh_panel_kernel",
-            "solve1": "rcq::trsm_kernel<float", "gram": "rcq::gram_bf3_kernel",
+            "solve1": "rcq::trsm_bf3_kernel", "gram": "rcq::gram_bf3_kernel",
             "cholesky": "rcq::chol_kernel", "solve2": "rcq::trmm_bf3_kernel"},
     "f64": {"sketch": "rcq::sketch_dense_kernel", "small_qr": "rcq::hh_panel_kernel",
             "solve1": "rcq::trsm_kernel<double", "gram": "rcq::gram_kernel<double",
@@ -160,9 +161,13 @@ def log(msg):
 
 
 def phase_model(phase, m, n, k, kind, prec):
-    """Algorithmic work of one phase: (flops, bytes, matrix-core dtype)."""
+    """Algorithmic work of one phase: (flops, HBM bytes, matrix-core dtype).
+
+    FP32 data (f32, mixed) goes through the tall phases on bf16 matrix cores
+    with three-way splits: six bf16 products per FP32-accurate product, so
+    their compute peak is the bf16 peak / 6 ("bf16x3")."""
     s = 8 if prec == "f64" else 4
-    mm = {"f64": "f64", "f32": "f32", "mixed": "f32"}[prec]
+    mm = "f64" if prec == "f64" else "bf16x3"
     if phase == "sketch":
         if kind == "countsketch":
             return float(m * n), float(m * n * s), "hbm"
@@ -170,7 +175,7 @@ def phase_model(phase, m, n, k, kind, prec):
     if phase in ("solve1", "solve2"):
         return float(m) * n * n, 2.0 * m * n * s, mm
     if phase == "gram":
-        return float(m) * n * (n + 1), float(m * n * s), "f64"
+        return float(m) * n * (n + 1), float(m * n * s), mm
     return 0.0, 0.0, "f64"
 
 

@@ -88,6 +88,13 @@ inline int64_t dense_panel_elems(int n) {
   return 256 * nb * nb;
 }
 
+// Byte offset of subpanel b in the FP32 solve's bf16 x 3 panels: subpanel
+// b' holds (b'+1)/2 chunks of 3072 bytes and a 1536-byte diagonal inverse.
+__host__ __device__ inline int64_t trsm_bf3_panel_offset(int b) {
+  return 3072 * static_cast<int64_t>(b / 2) * ((b + 1) / 2) + 1536 * static_cast<int64_t>(b);
+}
+inline int64_t trsm_bf3_panel_bytes(int n) { return trsm_bf3_panel_offset((n + 15) / 16); }
+
 inline int64_t panel_elems(int n) {
   const int64_t nb = (n + 15) / 16;
   return 256 * nb * (nb + 1) / 2;

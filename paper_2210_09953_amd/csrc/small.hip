@@ -474,11 +474,89 @@ __global__ void make_panels_kernel(const double* __restrict__ R, int64_t ldr, in
   pan[idx] = static_cast<T>(v);
 }
 
+// Operand panels of an upper triangular R (n x n, ld ldr) for the FP32 solve
+// trsm_bf3_kernel.  Subpanel b (output columns 16b..16b+15) holds
+//  - (b+1)/2 update chunks: chunk p covers Q columns 32p..32p+31 in the
+//    order in which the solved values sit in registers: K = 8 lg + e is
+//    column 32p + 4lg + e for e < 4 and 32p + 16 + 4lg + (e - 4) for e >= 4.
+//    Lane (lg, l16) holds -R(col(K), 16b + l16) where col(K) < 16b (else 0),
+//    FP32 split exactly into three bf16 planes: 3 planes x 64 lanes x 16 B;
+//  - the inverse Tb of the 16 x 16 diagonal block (FP64 substitution, then
+//    FP32, split): lane (lg, l16) holds Tb(4 lg + e, l16), e < 4: 3 planes x
+//    64 lanes x 8 B.
+// Columns past n are zero (their solved values are zero).  One 64-thread
+// block per subpanel.
+__device__ __forceinline__ void split3_bits(double v, uint32_t& h, uint32_t& d, uint32_t& l) {
+  const float x = static_cast<float>(v);
+  h = __float_as_uint(x) & 0xFFFF0000u;
+  const float r = x - __uint_as_float(h);
+  d = __float_as_uint(r) & 0xFFFF0000u;
+  l = __float_as_uint(r - __uint_as_float(d));
+}
+
+__global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* __restrict__ R,
+                                                                  int64_t ldr, int n,
+                                                                  unsigned char* __restrict__ pan3) {
+  __shared__ double tb[16][17];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int c0 = 16 * b;
+  if (lane < 16) {
+    // column j = lane of Tb by back substitution (upper triangular)
+    const int j = lane;
+    for (int i = 15; i >= 0; --i) {
+      double t = 0.0;
+      if (i <= j && c0 + j < n) {
+        if (i == j) {
+          t = 1.0 / R[(c0 + j) + static_cast<int64_t>(c0 + j) * ldr];
+        } else {
+          double s = 0.0;
+          for (int l = i + 1; l <= j; ++l) s += R[(c0 + i) + static_cast<int64_t>(c0 + l) * ldr] * tb[l][j];
+          t = -s / R[(c0 + i) + static_cast<int64_t>(c0 + i) * ldr];
+        }
+      }
+      tb[i][j] = t;
+    }
+  }
+  __syncthreads();
+  const int nc = (b + 1) / 2;
+  unsigned char* base = pan3 + trsm_bf3_panel_offset(b);
+  const int col = c0 + l16;
+  for (int p = 0; p < nc; ++p) {
+    uint32_t hp[8], dp[8], lp[8];
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * p + (e < 4 ? 4 * lg + e : 16 + 4 * lg + (e - 4));
+      const double v = (k < c0 && col < n) ? -R[k + static_cast<int64_t>(col) * ldr] : 0.0;
+      split3_bits(v, hp[e], dp[e], lp[e]);
+    }
+    unsigned char* dst = base + 3072 * p;
+    for (int w = 0; w < 4; ++w) {
+      reinterpret_cast<uint32_t*>(dst + 16 * lane)[w] = (hp[2 * w] >> 16) | (hp[2 * w + 1] & 0xFFFF0000u);
+      reinterpret_cast<uint32_t*>(dst + 1024 + 16 * lane)[w] = (dp[2 * w] >> 16) | (dp[2 * w + 1] & 0xFFFF0000u);
+      reinterpret_cast<uint32_t*>(dst + 2048 + 16 * lane)[w] = (lp[2 * w] >> 16) | (lp[2 * w + 1] & 0xFFFF0000u);
+    }
+  }
+  uint32_t hp[4], dp[4], lp[4];
+  for (int e = 0; e < 4; ++e) split3_bits(tb[4 * lg + e][l16], hp[e], dp[e], lp[e]);
+  unsigned char* dd = base + 3072 * nc;
+  for (int w = 0; w < 2; ++w) {
+    reinterpret_cast<uint32_t*>(dd + 8 * lane)[w] = (hp[2 * w] >> 16) | (hp[2 * w + 1] & 0xFFFF0000u);
+    reinterpret_cast<uint32_t*>(dd + 512 + 8 * lane)[w] = (dp[2 * w] >> 16) | (dp[2 * w + 1] & 0xFFFF0000u);
+    reinterpret_cast<uint32_t*>(dd + 1024 + 8 * lane)[w] = (lp[2 * w] >> 16) | (lp[2 * w + 1] & 0xFFFF0000u);
+  }
+}
+
 hipError_t launch_make_panels(const double* R, int64_t ldr, int n, bool f32, void* pan,
                               hipStream_t st, bool negate) {
   const int64_t total = panel_elems(n);
   const unsigned grid = static_cast<unsigned>(ceil_div(total, 256));
   const double sg = negate ? -1.0 : 1.0;
+  if (f32 && negate) {
+    // FP32 solve: bf16 x 3 operand panels with inverted diagonal blocks
+    make_trsm_bf3_panels_kernel<<<static_cast<unsigned>(ceil_div(n, 16)), 64, 0, st>>>(
+        R, ldr, n, static_cast<unsigned char*>(pan));
+    return hipGetLastError();
+  }
   if (f32)
     make_panels_kernel<float><<<grid, 256, 0, st>>>(R, ldr, n, static_cast<float*>(pan), total, sg);
   else

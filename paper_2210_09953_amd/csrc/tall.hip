@@ -214,17 +214,6 @@ static hipError_t trsm_dispatch(int nb, const T* X, int64_t m, int n, int64_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
-                       void* Q, int64_t ldq, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  const int nb = static_cast<int>(ceil_div(n, 16));
-  if (f32)
-    return trsm_dispatch<float>(nb, static_cast<const float*>(X), m, n, ldx,
-                                static_cast<const float*>(pan), static_cast<float*>(Q), ldq, st);
-  return trsm_dispatch<double>(nb, static_cast<const double*>(X), m, n, ldx,
-                               static_cast<const double*>(pan), static_cast<double*>(Q), ldq, st);
-}
-
 // ----------------------------------------------------------------------------
 // Q = Q1 T for an upper triangular T (T = R'^{-1}, Algorithm 3 step 4 as a
 // product: R' comes from the Cholesky factor of the Gram of a well
@@ -458,6 +447,204 @@ __global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int 
       __syncthreads();
     }
   }
+}
+
+// ----------------------------------------------------------------------------
+// Q = X R^{-1} for FP32 X on bf16 matrix cores (the FP32 and mixed solves).
+// Blocked forward substitution over 16-column subpanels: subpanel b first
+// takes the update D = X_b - Q_{<b} R_{<b,b} (the same sums as the row-wise
+// substitution, regrouped), then is multiplied by the inverse Tb of its
+// 16 x 16 diagonal block (formed in FP64 by make_trsm_bf3_panels_kernel).
+// Both products split their FP32 operands exactly into three bf16 parts and
+// take the six significant products (as in trmm_bf3_kernel), so each is as
+// accurate as an FP32 product.  The transposed setup (panel columns x rows)
+// makes the solved block, as the 16x16 matrix cores return it, directly the
+// operand of the later updates: a wave keeps its 16 rows of Q split in
+// registers (two subpanels per 32-wide chunk, in the column order the panels
+// are packed in), so X is read once and Q written once, with no LDS round
+// trip.  Subpanel b's operands are staged in LDS, double buffered.  Works in
+// place (Q == X: a wave reads all of its rows before it writes).
+typedef short s4b_t __attribute__((ext_vector_type(4)));
+
+template <int NB>
+__global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m, int n,
+                                                       int64_t ldx,
+                                                       const unsigned char* __restrict__ pan3,
+                                                       float* Q, int64_t ldq) {
+  constexpr int NCH = (NB + 1) / 2;
+  constexpr int PMAX = (NB / 2) * 3072 + 1536;
+  constexpr int STG = (PMAX / 16 + 255) / 256;
+  __shared__ __align__(16) unsigned char pbuf[2][PMAX];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
+  const bool full = static_cast<int64_t>(blockIdx.x) * 64 + 64 <= m && n == 16 * NB;
+  // X row of this lane at columns 16 b + 4 lg + v: the layout of the solved
+  // values.  Loads clamp row and column (rows past m are never stored;
+  // columns past n meet zero panel entries).
+  float xd[NB][4];
+  const float* xrow = X + (row < m ? row : m - 1);
+  if (full) {
+    const float* xb = xrow + static_cast<int64_t>(4 * lg) * ldx;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xd[b][v] = xb[static_cast<int64_t>(16 * b + v) * ldx];
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + 4 * lg + v;
+        xd[b][v] = xrow[static_cast<int64_t>(col < n ? col : n - 1) * ldx];
+      }
+  }
+  u4b_t qb[NCH][3];
+  u4b_t stg[STG];
+  auto psize = [](int b) { return static_cast<int>(((b + 1) / 2) * 3072 + 1536); };
+  auto fetch = [&](int b) {
+    const int nv = psize(b) / 16;
+    const u4b_t* src = reinterpret_cast<const u4b_t*>(pan3 + trsm_bf3_panel_offset(b));
+#pragma unroll
+    for (int q = 0; q < STG; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < nv) stg[q] = src[i];
+    }
+  };
+  auto store = [&](int buf, int b) {
+    const int nv = psize(b) / 16;
+    u4b_t* dst = reinterpret_cast<u4b_t*>(pbuf[buf]);
+#pragma unroll
+    for (int q = 0; q < STG; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < nv) dst[i] = stg[q];
+    }
+  };
+  // bf16 planes of four FP32 values, two per 32-bit word (element 0 low).
+  auto split4 = [](const f4& x, uint32_t (&h)[2], uint32_t (&d)[2], uint32_t (&l)[2]) {
+    uint32_t hp[4], dp[4], lp[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split3(x[e], hp[e], dp[e], lp[e]);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      h[w] = __builtin_amdgcn_perm(hp[2 * w + 1], hp[2 * w], 0x07060302u);
+      d[w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
+      l[w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
+    }
+  };
+  auto as_s4 = [](const uint32_t (&w)[2]) {
+    const uint2 u = make_uint2(w[0], w[1]);
+    return __builtin_bit_cast(s4b_t, u);
+  };
+  fetch(0);
+  store(0, 0);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) fetch(b + 1);
+    const int nc = (b + 1) / 2;
+    const u4b_t* pa = reinterpret_cast<const u4b_t*>(pbuf[b & 1]) + lane;
+    f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
+    if (nc > 0) {
+      // One chain per chunk, each from zero; products grouped by R plane:
+      // d with d, h; l with h; h with l, d, h.
+      f4 c4[NCH];
+#pragma unroll
+      for (int p = 0; p < NCH; ++p) c4[p] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int tp = 1; tp < 4; ++tp) {
+        const int tpl = tp % 3;  // planes in the order d, l, h
+        bf8 tv[NCH];
+#pragma unroll
+        for (int p = 0; p < NCH; ++p)
+          if (p < nc) tv[p] = __builtin_bit_cast(bf8, pa[(3 * p + tpl) * 64]);
+        const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
+#pragma unroll
+        for (int iq = 0; iq < 3; ++iq)
+          if (iq < nq) {
+            const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
+#pragma unroll
+            for (int p = 0; p < NCH; ++p)
+              if (p < nc)
+                c4[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    tv[p], __builtin_bit_cast(bf8, qb[p][qp]), c4[p], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int p = 0; p < NCH; ++p)
+        if (p < nc) D += c4[p];
+    }
+    // Diagonal block: Q_b = Tb^T D on 16x16x16 matrix cores; D as returned
+    // is the B operand (K = 4 lg + v).
+    uint32_t dh[2], dd[2], dl[2];
+    split4(D, dh, dd, dl);
+    const uint2* pd = reinterpret_cast<const uint2*>(pbuf[b & 1] + 3072 * nc) + lane;
+    const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
+    const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
+    const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
+    f4 E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(tl, as_s4(dh), E, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dl), E, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
+    float* qout = Q + row;
+    if (full) {
+      float* qo = qout + static_cast<int64_t>(4 * lg) * ldq;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qo[static_cast<int64_t>(16 * b + v) * ldq] = E[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * b + 4 * lg + v;
+        if (row < m && col < n) qout[static_cast<int64_t>(col) * ldq] = E[v];
+      }
+    }
+    // Keep Q_b split for the later updates: words 0-1 of chunk b/2 for even
+    // b (words 2-3 zero until b + 1 is solved), words 2-3 for odd b.
+    uint32_t eh[2], ed[2], el[2];
+    split4(E, eh, ed, el);
+    if ((b & 1) == 0) {
+      qb[b / 2][0] = u4b_t{eh[0], eh[1], 0u, 0u};
+      qb[b / 2][1] = u4b_t{ed[0], ed[1], 0u, 0u};
+      qb[b / 2][2] = u4b_t{el[0], el[1], 0u, 0u};
+    } else {
+      qb[b / 2][0][2] = eh[0]; qb[b / 2][0][3] = eh[1];
+      qb[b / 2][1][2] = ed[0]; qb[b / 2][1][3] = ed[1];
+      qb[b / 2][2][2] = el[0]; qb[b / 2][2][3] = el[1];
+    }
+    if (b + 1 < NB) {
+      store((b + 1) & 1, b + 1);
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
+                       void* Q, int64_t ldq, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  if (f32) {
+    // pan holds bf16 x 3 subpanels (make_trsm_bf3_panels_kernel)
+    const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+    const float* x = static_cast<const float*>(X);
+    float* q = static_cast<float*>(Q);
+    const unsigned char* p3 = static_cast<const unsigned char*>(pan);
+#define RCQ_S3_CASE(NBV)                                                \
+  case NBV:                                                             \
+    trsm_bf3_kernel<NBV><<<grid, 256, 0, st>>>(x, m, n, ldx, p3, q, ldq); \
+    break;
+    switch (nb) {
+      RCQ_S3_CASE(1) RCQ_S3_CASE(2) RCQ_S3_CASE(3) RCQ_S3_CASE(4) RCQ_S3_CASE(5) RCQ_S3_CASE(6)
+      RCQ_S3_CASE(7) RCQ_S3_CASE(8) RCQ_S3_CASE(9) RCQ_S3_CASE(10) RCQ_S3_CASE(11)
+      RCQ_S3_CASE(12) RCQ_S3_CASE(13) RCQ_S3_CASE(14) RCQ_S3_CASE(15) RCQ_S3_CASE(16)
+      default: return hipErrorInvalidValue;
+    }
+#undef RCQ_S3_CASE
+    return hipGetLastError();
+  }
+  return trsm_dispatch<double>(nb, static_cast<const double*>(X), m, n, ldx,
+                               static_cast<const double*>(pan), static_cast<double*>(Q), ldq, st);
 }
 
 template <typename T, bool FULL>
