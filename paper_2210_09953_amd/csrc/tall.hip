@@ -22,6 +22,8 @@
 // cores in the working precision, FP64 partial sums per split (FP32 sums are
 // folded into FP64 every 2048 rows); per-split partials are reduced in a
 // fixed order by gram_reduce_kernel.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -309,6 +311,60 @@ __global__ __launch_bounds__(256) void trmm_kernel(T* Q, int64_t m, int n, int64
   }
 }
 
+// Direct global -> LDS operand staging for the tall bf16 x 3 kernels.  A
+// panel of `bytes` bytes is copied as 1 KiB wave-instructions (16 bytes per
+// lane) dealt round-robin to the kTallWaves waves of the workgroup; every wave issues
+// the same number of instructions (the surplus ones read the panel's first
+// KiB into a 1 KiB sink), so the wait counts below are compile-time facts.
+// Waves per workgroup of the tall bf16 x 3 kernels (16 rows each): one
+// staged copy of the operand panels serves 16 kTallWaves rows.
+constexpr int kTallWaves = 8;
+__host__ __device__ constexpr int dma_kib(int bytes) { return (bytes + 1023) / 1024; }
+__host__ __device__ constexpr int dma_per_wave(int bytes) {
+  return (dma_kib(bytes) + kTallWaves - 1) / kTallWaves;
+}
+
+__device__ __forceinline__ void dma_panel(const unsigned char* __restrict__ src, int bytes,
+                                          unsigned char* slot, unsigned char* sink, int wave,
+                                          int lane) {
+  const int w = dma_kib(bytes);
+#pragma unroll
+  for (int i = 0; i < dma_per_wave(bytes); ++i) {
+    const int j = wave + kTallWaves * i;
+    const bool live = j < w;
+    const unsigned char* g = src + (live ? 1024 * j : 0) + 16 * lane;
+    unsigned char* l = live ? slot + 1024 * j : sink;
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(N).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): a loop
+// whose index is a compile-time constant in the body.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Workgroup barrier without a memory fence (the fence would wait for every
+// outstanding load, including the staging of later panels); LDS visibility
+// comes from the explicit vmcnt / lgkmcnt waits before it.
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ----------------------------------------------------------------------------
 // Q = Q1 T for FP32 Q1 on bf16 matrix cores (the FP32 second solve).  Both
 // operands are split exactly into three bf16 parts (split3: T in advance by
@@ -317,7 +373,8 @@ __global__ __launch_bounds__(256) void trmm_kernel(T* Q, int64_t m, int n, int64
 // matrix cores and added to the output in FP32 with round-to-nearest vector
 // adds.  A wave keeps its 16 rows of Q1, split, in registers (96 registers
 // for n = 256), so the product works in place.  Panel b of T (output columns
-// 16b..16b+15, chunks 0..b/2) is staged in LDS, double-buffered.
+// 16b..16b+15, chunks 0..b/2) is staged in LDS two panels ahead by direct
+// global -> LDS loads.
 typedef unsigned int u4b_t __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr int bf3_panel_offset(int b) {
@@ -325,16 +382,20 @@ __host__ __device__ constexpr int bf3_panel_offset(int b) {
   return 3072 * ((b & 1) ? ((b + 1) / 2) * ((b + 1) / 2) : (b / 2) * (b / 2 + 1));
 }
 
+// Bytes of panel b of T (chunks 0..b/2 of 3 KiB).
+__host__ __device__ constexpr int trmm_bf3_psize(int b) { return (b / 2 + 1) * 3072; }
+
 template <int NB>
-__global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int n, int64_t ldq,
+__global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int64_t m, int n, int64_t ldq,
                                                        const unsigned char* __restrict__ pan3) {
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = NCH * 3072;
-  constexpr int STG = (PMAX / 16 + 255) / 256;
-  __shared__ __align__(16) unsigned char pbuf[2][PMAX];
+  constexpr int SLOT = dma_kib(PMAX) * 1024;
+  // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
+  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
   // Q1 row l16 of this wave, columns 32 ch + 8 lg + e: all loads are issued
   // first; chunk ch is split into its three bf16 planes just before output
   // panel 2 ch, the first that needs it, so the loads of later chunks
@@ -342,7 +403,7 @@ __global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int 
   // Loads clamp the row and column (no branches): rows past m are never
   // stored, and columns past n meet zero rows of T.
   float xq[NCH][8];
-  const bool full = static_cast<int64_t>(blockIdx.x) * 64 + 64 <= m && n == 32 * NCH;
+  const bool full = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + 16 * kTallWaves <= m && n == 32 * NCH;
   const float* qrow = Q + (row < m ? row : m - 1);
   if (full) {
     // lane base at column 8 lg; the chunk/element offsets are uniform
@@ -372,33 +433,28 @@ __global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int 
       qb[ch][2][w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
     }
   };
-  u4b_t stg[STG];
-  auto fetch = [&](int b) {
-    const int nv = ((b / 2) + 1) * 3072 / 16;
-    const u4b_t* src = reinterpret_cast<const u4b_t*>(pan3 + bf3_panel_offset(b));
-#pragma unroll
-    for (int q = 0; q < STG; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i < nv) stg[q] = src[i];
-    }
+  auto stage = [&](int b) {
+    dma_panel(pan3 + bf3_panel_offset(b), trmm_bf3_psize(b), ring + SLOT * (b % 3), ring + 3 * SLOT, wave,
+              lane);
   };
-  auto store = [&](int buf, int b) {
-    const int nv = ((b / 2) + 1) * 3072 / 16;
-    u4b_t* dst = reinterpret_cast<u4b_t*>(pbuf[buf]);
-#pragma unroll
-    for (int q = 0; q < STG; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i < nv) dst[i] = stg[q];
+  stage(0);
+  if (NB > 1) stage(1);
+  static_for<NB>([&](auto bc) {
+    constexpr int b = decltype(bc)::value;
+    // Panel b has landed once the memory operations issued after its
+    // staging are all that remain (see trsm_bf3_kernel).
+    if (full) {
+      constexpr int later = (b == 0) ? (NB > 1 ? dma_per_wave(trmm_bf3_psize(1)) : 0)
+                          : (b == 1) ? (NB > 2 ? dma_per_wave(trmm_bf3_psize(2)) : 0) + 4
+                                     : 8 + (b + 1 < NB ? dma_per_wave(trmm_bf3_psize(b + 1)) : 0);
+      wait_vmcnt<later>();
+    } else {
+      wait_vmcnt<0>();
     }
-  };
-  fetch(0);
-  store(0, 0);
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    if (b + 1 < NB) fetch(b + 1);
+    wg_barrier();
+    if (b + 2 < NB) stage(b + 2);
     if ((b & 1) == 0) split_chunk(b / 2);
-    const u4b_t* pa = reinterpret_cast<const u4b_t*>(pbuf[b & 1]) + lane;
+    const u4b_t* pa = reinterpret_cast<const u4b_t*>(ring + SLOT * (b % 3)) + lane;
     // One chain per chunk (independent, so the matrix cores pipeline them),
     // each from zero; products grouped by T plane: d with d, h; l with h;
     // h with l, d, h.
@@ -442,11 +498,7 @@ __global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int 
         if (row < m && col < n) qout[static_cast<int64_t>(col) * ldq] = D[v];
       }
     }
-    if (b + 1 < NB) {
-      store((b + 1) & 1, b + 1);
-      __syncthreads();
-    }
-  }
+  });
 }
 
 // ----------------------------------------------------------------------------
@@ -462,23 +514,28 @@ __global__ __launch_bounds__(256) void trmm_bf3_kernel(float* Q, int64_t m, int 
 // operand of the later updates: a wave keeps its 16 rows of Q split in
 // registers (two subpanels per 32-wide chunk, in the column order the panels
 // are packed in), so X is read once and Q written once, with no LDS round
-// trip.  Subpanel b's operands are staged in LDS, double buffered.  Works in
-// place (Q == X: a wave reads all of its rows before it writes).
+// trip.  Subpanel b's operands are staged in LDS two subpanels ahead by
+// direct global -> LDS loads.  Works in place (Q == X: a wave reads all of
+// its rows before it writes).
 typedef short s4b_t __attribute__((ext_vector_type(4)));
 
+// Bytes of subpanel b of the solve's panels ((b+1)/2 chunks, diagonal inverse).
+__host__ __device__ constexpr int trsm_bf3_psize(int b) { return ((b + 1) / 2) * 3072 + 1536; }
+
 template <int NB>
-__global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m, int n,
+__global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* X, int64_t m, int n,
                                                        int64_t ldx,
                                                        const unsigned char* __restrict__ pan3,
                                                        float* Q, int64_t ldq) {
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = (NB / 2) * 3072 + 1536;
-  constexpr int STG = (PMAX / 16 + 255) / 256;
-  __shared__ __align__(16) unsigned char pbuf[2][PMAX];
+  constexpr int SLOT = dma_kib(PMAX) * 1024;
+  // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
+  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16 + l16;
-  const bool full = static_cast<int64_t>(blockIdx.x) * 64 + 64 <= m && n == 16 * NB;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
+  const bool full = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + 16 * kTallWaves <= m && n == 16 * NB;
   // X row of this lane at columns 16 b + 4 lg + v: the layout of the solved
   // values.  Loads clamp row and column (rows past m are never stored;
   // columns past n meet zero panel entries).
@@ -500,25 +557,9 @@ __global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m
       }
   }
   u4b_t qb[NCH][3];
-  u4b_t stg[STG];
-  auto psize = [](int b) { return static_cast<int>(((b + 1) / 2) * 3072 + 1536); };
-  auto fetch = [&](int b) {
-    const int nv = psize(b) / 16;
-    const u4b_t* src = reinterpret_cast<const u4b_t*>(pan3 + trsm_bf3_panel_offset(b));
-#pragma unroll
-    for (int q = 0; q < STG; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i < nv) stg[q] = src[i];
-    }
-  };
-  auto store = [&](int buf, int b) {
-    const int nv = psize(b) / 16;
-    u4b_t* dst = reinterpret_cast<u4b_t*>(pbuf[buf]);
-#pragma unroll
-    for (int q = 0; q < STG; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i < nv) dst[i] = stg[q];
-    }
+  auto stage = [&](int b) {
+    dma_panel(pan3 + trsm_bf3_panel_offset(b), trsm_bf3_psize(b), ring + SLOT * (b % 3), ring + 3 * SLOT,
+              wave, lane);
   };
   // bf16 planes of four FP32 values, two per 32-bit word (element 0 low).
   auto split4 = [](const f4& x, uint32_t (&h)[2], uint32_t (&d)[2], uint32_t (&l)[2]) {
@@ -536,14 +577,27 @@ __global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m
     const uint2 u = make_uint2(w[0], w[1]);
     return __builtin_bit_cast(s4b_t, u);
   };
-  fetch(0);
-  store(0, 0);
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    if (b + 1 < NB) fetch(b + 1);
+  stage(0);
+  if (NB > 1) stage(1);
+  static_for<NB>([&](auto bc) {
+    constexpr int b = decltype(bc)::value;
+    // Panel b has landed once the memory operations issued after its
+    // staging are all that remain: panel b+1's staging and the 4 stores of
+    // each of the previous two subpanels (whole-workgroup tiles only; a
+    // ragged tile may skip stores and waits for everything).
+    if (full) {
+      constexpr int later = (b == 0) ? (NB > 1 ? dma_per_wave(trsm_bf3_psize(1)) : 0)
+                          : (b == 1) ? (NB > 2 ? dma_per_wave(trsm_bf3_psize(2)) : 0) + 4
+                                     : 8 + (b + 1 < NB ? dma_per_wave(trsm_bf3_psize(b + 1)) : 0);
+      wait_vmcnt<later>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    wg_barrier();
+    if (b + 2 < NB) stage(b + 2);
     const int nc = (b + 1) / 2;
-    const u4b_t* pa = reinterpret_cast<const u4b_t*>(pbuf[b & 1]) + lane;
+    const unsigned char* slot = ring + SLOT * (b % 3);
+    const u4b_t* pa = reinterpret_cast<const u4b_t*>(slot) + lane;
     f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
     if (nc > 0) {
       // One chain per chunk, each from zero; products grouped by R plane:
@@ -578,7 +632,7 @@ __global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m
     // is the B operand (K = 4 lg + v).
     uint32_t dh[2], dd[2], dl[2];
     split4(D, dh, dd, dl);
-    const uint2* pd = reinterpret_cast<const uint2*>(pbuf[b & 1] + 3072 * nc) + lane;
+    const uint2* pd = reinterpret_cast<const uint2*>(slot + 3072 * nc) + lane;
     const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
     const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
     const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
@@ -613,11 +667,7 @@ __global__ __launch_bounds__(256) void trsm_bf3_kernel(const float* X, int64_t m
       qb[b / 2][1][2] = ed[0]; qb[b / 2][1][3] = ed[1];
       qb[b / 2][2][2] = el[0]; qb[b / 2][2][3] = el[1];
     }
-    if (b + 1 < NB) {
-      store((b + 1) & 1, b + 1);
-      __syncthreads();
-    }
-  }
+  });
 }
 
 hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
@@ -626,13 +676,13 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32) {
     // pan holds bf16 x 3 subpanels (make_trsm_bf3_panels_kernel)
-    const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+    const unsigned grid = static_cast<unsigned>(ceil_div(m, 16 * kTallWaves));
     const float* x = static_cast<const float*>(X);
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
-#define RCQ_S3_CASE(NBV)                                                \
-  case NBV:                                                             \
-    trsm_bf3_kernel<NBV><<<grid, 256, 0, st>>>(x, m, n, ldx, p3, q, ldq); \
+#define RCQ_S3_CASE(NBV)                                                                \
+  case NBV:                                                                             \
+    trsm_bf3_kernel<NBV><<<grid, 64 * kTallWaves, 0, st>>>(x, m, n, ldx, p3, q, ldq);   \
     break;
     switch (nb) {
       RCQ_S3_CASE(1) RCQ_S3_CASE(2) RCQ_S3_CASE(3) RCQ_S3_CASE(4) RCQ_S3_CASE(5) RCQ_S3_CASE(6)
@@ -671,12 +721,12 @@ hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const v
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32) {
     // pan holds bf16 x 3 panels (make_bf3_panels)
-    const unsigned grid = static_cast<unsigned>(ceil_div(m, 64));
+    const unsigned grid = static_cast<unsigned>(ceil_div(m, 16 * kTallWaves));
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
-#define RCQ_T3_CASE(NBV)                                                \
-  case NBV:                                                             \
-    trmm_bf3_kernel<NBV><<<grid, 256, 0, st>>>(q, m, n, ldq, p3);       \
+#define RCQ_T3_CASE(NBV)                                                           \
+  case NBV:                                                                        \
+    trmm_bf3_kernel<NBV><<<grid, 64 * kTallWaves, 0, st>>>(q, m, n, ldq, p3);      \
     break;
     switch (nb) {
       RCQ_T3_CASE(1) RCQ_T3_CASE(2) RCQ_T3_CASE(3) RCQ_T3_CASE(4) RCQ_T3_CASE(5) RCQ_T3_CASE(6)
