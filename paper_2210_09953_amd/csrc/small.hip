@@ -20,69 +20,87 @@ namespace rcq {
 // exit columns p0..p0+15 hold R above the diagonal (diagonal = alpha) and
 // the tail of each reflector v below it; v's leading entry goes to v0[],
 // 2/(v^T v) to beta[], and the panel's 16 x 16 T to Tp.
+// One wave per panel column, its rows (lane + 64 q) in registers.  Step j:
+// the waves right of j apply reflector j (read from LDS) to their column,
+// and wave j + 1 then forms reflector j + 1 from its updated column and
+// publishes it in LDS: one barrier per reflector.
+// RPL = rows per lane (L <= 64 RPL).
+template <int RPL>
 __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, int k, int n,
                                                         int p0, double* __restrict__ v0g,
                                                         double* __restrict__ betag,
                                                         double* __restrict__ Tp) {
-  extern __shared__ double pan[];  // [16][L], column-major
-  __shared__ double sc[3];
-  __shared__ double v0s[kHhPanel], bs[kHhPanel];
+  extern __shared__ double vsh[];  // [16][L]: reflector j = vsh[j L + r] (0 above row j)
+  __shared__ double sc[kHhPanel][3];
   __shared__ double y[kHhPanel][kHhPanel];
   __shared__ double tT[kHhPanel][kHhPanel + 1];
   const int L = k - p0;
   const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-
-  for (int idx = tid; idx < kHhPanel * L; idx += blockDim.x) {
-    const int c = idx / L, i = idx % L;
-    pan[idx] = (c < nbp) ? A[(p0 + i) + static_cast<int64_t>(p0 + c) * k] : 0.0;
+  const bool own = wave < nbp;
+  double xr[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    xr[q] = (own && r < L) ? A[(p0 + r) + static_cast<int64_t>(p0 + wave) * k] : 0.0;
   }
+  // Wave j: reflector from its column (rows >= j), diagonal becomes alpha.
+  auto reflect = [&](int j) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r > j && r < L) t += xr[q] * xr[q];
+    }
+    t = wave_sum(t);
+    const double x0 = __shfl(xr[0], j, 64);  // j < 16: row j is lane j, q = 0
+    const double nrm = sqrt(x0 * x0 + t);
+    const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+    const double v0 = x0 - alpha;
+    const double vtv = v0 * v0 + t;
+    const double beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r < L) vsh[j * L + r] = (r < j) ? 0.0 : ((r == j) ? v0 : xr[q]);
+    }
+    if (lane == j) xr[0] = alpha;
+    if (lane == 0) {
+      sc[j][0] = alpha;
+      sc[j][1] = v0;
+      sc[j][2] = beta;
+    }
+  };
+  if (wave == 0 && nbp > 0) reflect(0);
   __syncthreads();
-
   for (int j = 0; j < nbp; ++j) {
-    const double* vj = pan + j * L;
-    if (wave == 0) {
-      double t = 0.0;
-      for (int i = j + 1 + lane; i < L; i += 64) t += vj[i] * vj[i];
-      t = wave_sum(t);
-      if (lane == 0) {
-        const double x0 = vj[j];
-        const double nrm = sqrt(x0 * x0 + t);
-        const double alpha = (x0 >= 0.0) ? -nrm : nrm;
-        const double v0 = x0 - alpha;
-        const double vtv = v0 * v0 + t;
-        sc[0] = alpha;
-        sc[1] = v0;
-        sc[2] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+    if (wave > j && own) {
+      const double* vj = vsh + j * L;
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r < L) w += vj[r] * xr[q];
       }
-    }
-    __syncthreads();
-    const double alpha = sc[0], v0 = sc[1], beta = sc[2];
-    if (wave > j && wave < nbp) {
-      double* pc = pan + wave * L;
-      double w = (lane == 0) ? v0 * pc[j] : 0.0;
-      for (int i = j + 1 + lane; i < L; i += 64) w += vj[i] * pc[i];
       w = wave_sum(w);
-      const double f = beta * w;
-      if (lane == 0) pc[j] -= f * v0;
-      for (int i = j + 1 + lane; i < L; i += 64) pc[i] -= f * vj[i];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      pan[j * L + j] = alpha;
-      v0s[j] = v0;
-      bs[j] = beta;
+      const double f = sc[j][2] * w;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r < L) xr[q] -= f * vj[r];
+      }
+      if (wave == j + 1) reflect(j + 1);
     }
     __syncthreads();
   }
-  // y[a][b] = v_a^T v_b for a < b (v_b is zero above row b).
+  // y[a][b] = v_a^T v_b for a < b.
   for (int pr = wave; pr < kHhPanel * kHhPanel; pr += 16) {
     const int a = pr / kHhPanel, b = pr % kHhPanel;
     if (a >= b || b >= nbp) continue;
-    const double* va = pan + a * L;
-    const double* vb = pan + b * L;
-    double s = (lane == 0) ? va[b] * v0s[b] : 0.0;
-    for (int i = b + 1 + lane; i < L; i += 64) s += va[i] * vb[i];
+    const double* va = vsh + a * L;
+    const double* vb = vsh + b * L;
+    double s = 0.0;
+    for (int i = b + lane; i < L; i += 64) s += va[i] * vb[i];
     s = wave_sum(s);
     if (lane == 0) y[a][b] = s;
   }
@@ -98,9 +116,9 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
         if (a < j) {
           double acc = 0.0;
           for (int l = a; l < j; ++l) acc += tT[a][l] * y[l][j];
-          tv = -bs[j] * acc;
+          tv = -sc[j][2] * acc;
         } else if (a == j) {
-          tv = bs[j];
+          tv = sc[j][2];
         }
       }
       if (a < kHhPanel) tT[a][j] = tv;
@@ -110,63 +128,66 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
       for (int b = 0; b < kHhPanel; ++b) Tp[a + kHhPanel * b] = tT[a][b];
   }
   if (tid < nbp) {
-    v0g[p0 + tid] = v0s[tid];
-    betag[p0 + tid] = bs[tid];
+    v0g[p0 + tid] = sc[tid][1];
+    betag[p0 + tid] = sc[tid][2];
   }
-  for (int idx = tid; idx < nbp * L; idx += blockDim.x) {
-    const int c = idx / L, i = idx % L;
-    A[(p0 + i) + static_cast<int64_t>(p0 + c) * k] = pan[idx];
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r < L) A[(p0 + r) + static_cast<int64_t>(p0 + wave) * k] = xr[q];
+    }
   }
-}
-
-// Reflector entry V(row, col) of panel columns (row, col relative to A).
-__device__ __forceinline__ double vref(const double* A, int k, int n, const double* v0g, int row,
-                                       int col) {
-  if (col >= n) return 0.0;
-  return (row == col) ? v0g[col] : ((row > col) ? A[row + static_cast<int64_t>(col) * k] : 0.0);
 }
 
 // M(p0:k, c_begin + 16 blockIdx.x + 0..15) <- (I - V T' V^T) M(...) with
 // T' = T^T (trans = 1, factorisation) or T (trans = 0, forming S).  One
-// workgroup of 256 threads per 16-column block: the panel's reflectors V
-// (L x 16, L = k - p0) are staged once in LDS (rows of 16, padded to 18);
-// thread (c = tid / 16, g = tid % 16) keeps M(p0 + g + 16 q, column c) for
-// all q in registers, so every global load is issued up front.  W = V^T M
-// is summed per thread over its rows and across the 16 lanes of a column
-// by a butterfly, Y = T' W is formed redundantly by those lanes, and
-// M -= V Y is applied in registers and stored.
-constexpr int kHuLd = 18;                        // LDS row stride of V (doubles)
-constexpr int kHuQ = (kMaxK + 15) / 16;          // rows per thread, maximum
+// workgroup of 16 waves per 16-column block, wave c for column c: it loads
+// its column's rows (lane + 64 q) and reflector column c's rows into
+// registers up front, the reflectors V (L x 16, L = k - p0) go to LDS (rows
+// of 16, padded to 18), W = V^T M is summed per lane and across the wave,
+// Y = T' W is formed redundantly by the lanes, and M -= V Y is applied in
+// registers and stored.
+constexpr int kHuLd = 18;  // LDS row stride of V (doubles)
 
-__global__ __launch_bounds__(256) void hh_update_kernel(const double* __restrict__ A, int k,
-                                                        int n, int p0, const double* __restrict__ v0g,
-                                                        const double* __restrict__ Tp, int trans,
-                                                        double* __restrict__ M, int64_t ldm,
-                                                        int c_begin, int c_end) {
+template <int RPL>
+__global__ __launch_bounds__(1024) void hh_update_kernel(const double* __restrict__ A, int k,
+                                                         int n, int p0, const double* __restrict__ v0g,
+                                                         const double* __restrict__ Tp, int trans,
+                                                         double* __restrict__ M, int64_t ldm,
+                                                         int c_begin, int c_end) {
   extern __shared__ double vs[];  // [L][kHuLd]
+  __shared__ double ts[kHhPanel * kHhPanel];  // T' (row i, column l) at ts[16 i + l]
   const int L = k - p0;
-  const int nq = (L + 15) / 16;
-  const int tid = threadIdx.x, c = tid >> 4, g = tid & 15;
+  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x < kHhPanel * kHhPanel) {
+    const int i = threadIdx.x >> 4, l = threadIdx.x & 15;
+    ts[threadIdx.x] = trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l];
+  }
   const int col = c_begin + kHhPanel * blockIdx.x + c;
   const bool live = col < c_end;
-  double mq[kHuQ];
+  const bool vlive = p0 + c < n;
+  const double v0c = vlive ? v0g[p0 + c] : 0.0;
+  double mq[RPL], vq[RPL];
 #pragma unroll
-  for (int q = 0; q < kHuQ; ++q) {
-    const int r = g + 16 * q;
-    mq[q] = (q < nq && r < L && live) ? M[(p0 + r) + static_cast<int64_t>(col) * ldm] : 0.0;
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    mq[q] = (r < L && live) ? M[(p0 + r) + static_cast<int64_t>(col) * ldm] : 0.0;
+    vq[q] = (r < L && vlive && r > c) ? A[(p0 + r) + static_cast<int64_t>(p0 + c) * k] : 0.0;
   }
-  for (int idx = tid; idx < kHhPanel * L; idx += 256) {
-    const int vc = idx / L, i = idx % L;
-    vs[i * kHuLd + vc] = vref(A, k, n, v0g, p0 + i, p0 + vc);
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    if (r < L) vs[r * kHuLd + c] = (r == c) ? v0c : vq[q];
   }
   __syncthreads();
   double w[kHhPanel];
 #pragma unroll
   for (int i = 0; i < kHhPanel; ++i) w[i] = 0.0;
 #pragma unroll
-  for (int q = 0; q < kHuQ; ++q) {
-    const int r = g + 16 * q;
-    if (q < nq && r < L) {
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    if (r < L) {
       const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
 #pragma unroll
       for (int j = 0; j < kHhPanel / 2; ++j) {
@@ -177,22 +198,19 @@ __global__ __launch_bounds__(256) void hh_update_kernel(const double* __restrict
     }
   }
 #pragma unroll
-  for (int i = 0; i < kHhPanel; ++i)
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) w[i] += __shfl_xor(w[i], off, 16);
+  for (int i = 0; i < kHhPanel; ++i) w[i] = wave_sum(w[i]);
   double y[kHhPanel];
 #pragma unroll
   for (int i = 0; i < kHhPanel; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int l = 0; l < kHhPanel; ++l)
-      t += (trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l]) * w[l];
+    for (int l = 0; l < kHhPanel; ++l) t += ts[kHhPanel * i + l] * w[l];
     y[i] = t;
   }
 #pragma unroll
-  for (int q = 0; q < kHuQ; ++q) {
-    const int r = g + 16 * q;
-    if (q < nq && r < L && live) {
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    if (r < L && live) {
       const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
       double t = 0.0;
 #pragma unroll
@@ -256,26 +274,53 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
   const size_t shm = static_cast<size_t>(kHhPanel) * k * sizeof(double);
   static bool attr_done = false;
   if (!attr_done) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(hh_panel_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(kHhPanel * kMaxK * sizeof(double)));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(hh_update_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(kHuLd * kMaxK * sizeof(double)));
-    if (e != hipSuccess) return e;
+    const void* pk[] = {reinterpret_cast<const void*>(hh_panel_kernel<4>),
+                        reinterpret_cast<const void*>(hh_panel_kernel<8>),
+                        reinterpret_cast<const void*>(hh_panel_kernel<12>),
+                        reinterpret_cast<const void*>(hh_panel_kernel<16>)};
+    const void* uk[] = {reinterpret_cast<const void*>(hh_update_kernel<4>),
+                        reinterpret_cast<const void*>(hh_update_kernel<8>),
+                        reinterpret_cast<const void*>(hh_update_kernel<12>),
+                        reinterpret_cast<const void*>(hh_update_kernel<16>)};
+    for (int i = 0; i < 4; ++i) {
+      e = hipFuncSetAttribute(pk[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(kHhPanel * kMaxK * sizeof(double)));
+      if (e != hipSuccess) return e;
+      e = hipFuncSetAttribute(uk[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(kHuLd * kMaxK * sizeof(double)));
+      if (e != hipSuccess) return e;
+    }
     attr_done = true;
   }
   const int npan = static_cast<int>(ceil_div(n, kHhPanel));
+  // Rows per lane of the one-wave-per-column kernels, from the panel height.
+#define RCQ_HH_RPL(L, STMT)                            \
+  do {                                                 \
+    const int rows_ = (L);                             \
+    if (rows_ <= 256) {                                \
+      constexpr int RPL = 4;                           \
+      STMT;                                            \
+    } else if (rows_ <= 512) {                         \
+      constexpr int RPL = 8;                           \
+      STMT;                                            \
+    } else if (rows_ <= 768) {                         \
+      constexpr int RPL = 12;                          \
+      STMT;                                            \
+    } else {                                           \
+      constexpr int RPL = 16;                          \
+      STMT;                                            \
+    }                                                  \
+  } while (0)
   for (int p = 0; p < npan; ++p) {
     const int p0 = p * kHhPanel;
-    hh_panel_kernel<<<1, 1024, shm, st>>>(A, k, n, p0, V0, beta, T + p * kHhPanel * kHhPanel);
+    RCQ_HH_RPL(k - p0, (hh_panel_kernel<RPL><<<1, 1024, shm, st>>>(
+                           A, k, n, p0, V0, beta, T + p * kHhPanel * kHhPanel)));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int cstart = p0 + kHhPanel;
     if (cstart < n) {
       const int nblk = static_cast<int>(ceil_div(n - cstart, kHhPanel));
-      hh_update_kernel<<<nblk, 256, kHuLd * (k - p0) * sizeof(double), st>>>(
-          A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k, cstart, n);
+      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL><<<nblk, 1024, kHuLd * (k - p0) * sizeof(double), st>>>(
+                             A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k, cstart, n)));
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -286,11 +331,12 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     for (int p = npan - 1; p >= 0; --p) {
       const int p0 = p * kHhPanel;
       const int nblk = static_cast<int>(ceil_div(n - p0, kHhPanel));
-      hh_update_kernel<<<nblk, 256, kHuLd * (k - p0) * sizeof(double), st>>>(
-          A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds, p0, n);
+      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL><<<nblk, 1024, kHuLd * (k - p0) * sizeof(double), st>>>(
+                             A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds, p0, n)));
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
+#undef RCQ_HH_RPL
   hh_finalize_kernel<<<1, 256, 0, st>>>(A, k, n, Rs, R, ldr, S, lds, status);
   return hipGetLastError();
 }
