@@ -83,4 +83,22 @@ __device__ __forceinline__ void set_status(int* status, int code) {
 __host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
+// sum_{s < ns} p[s * stride] added in order of s (the fixed order that makes
+// the split-K reductions reproducible), with the loads of 16 terms issued
+// together.
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ p, int ns,
+                                              int64_t stride) {
+  double sum = 0.0;
+  int s = 0;
+  for (; s + 16 <= ns; s += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[static_cast<int64_t>(s + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += v[u];
+  }
+  for (; s < ns; ++s) sum += p[static_cast<int64_t>(s) * stride];
+  return sum;
+}
+
 }  // namespace rcq

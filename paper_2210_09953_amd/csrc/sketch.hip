@@ -143,9 +143,7 @@ __global__ void sketch_reduce_kernel(const double* __restrict__ part, int nsplit
   const int i = static_cast<int>(idx % k), c = static_cast<int>(idx / k);
   const int64_t stride = static_cast<int64_t>(npad) * kpad;
   const double* p = part + static_cast<int64_t>(c) * kpad + i;
-  double sum = 0.0;
-  for (int s = 0; s < nsplit; ++s) sum += p[s * stride];
-  P[i + c * ldp] = scale * sum;
+  P[i + c * ldp] = scale * ordered_sum(p, nsplit, stride);
 }
 
 // ----------------------------------------------------------------------------

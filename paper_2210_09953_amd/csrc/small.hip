@@ -231,40 +231,47 @@ __global__ void set_identity_kernel(double* S, int64_t lds, int k, int n) {
 }
 
 // Sign fix and status.  Rs (n x n, ld n) = D triu(A); R (optional, ld ldr)
-// gets the same; S columns (optional) scaled by D.  Writes the status word:
-// 2 if any R entry is not finite (non-finite input), 1 if a diagonal is 0.
+// gets the same; S columns (optional) scaled by D.  Status: 2 if any R entry
+// is not finite (non-finite input), 1 if a diagonal is 0; every block adds
+// its finding with an integer atomic max into the status word, which
+// reset_status_kernel zeroes before the factorisation.  Blocks 0..nb_r-1
+// cover R, the rest cover S.
+__global__ void reset_status_kernel(int* status) { *status = 0; }
+
 __global__ __launch_bounds__(256) void hh_finalize_kernel(const double* __restrict__ A, int k,
                                                           int n, double* __restrict__ Rs,
                                                           double* __restrict__ R, int64_t ldr,
                                                           double* __restrict__ S, int64_t lds,
-                                                          int* __restrict__ status) {
-  __shared__ int bad_nonfinite, bad_rank;
-  if (threadIdx.x == 0) {
-    bad_nonfinite = 0;
-    bad_rank = 0;
-  }
+                                                          int nb_r, int* __restrict__ status) {
+  __shared__ int worst;
+  if (threadIdx.x == 0) worst = 0;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int r = idx % n, c = idx / n;
-    double v = 0.0;
-    if (r <= c) {
-      const double d = (A[r + static_cast<int64_t>(r) * k] < 0.0) ? -1.0 : 1.0;
-      v = d * A[r + static_cast<int64_t>(c) * k];
-      if (!isfinite(v)) atomicOr(&bad_nonfinite, 1);
-      if (r == c && !(v > 0.0)) atomicOr(&bad_rank, 1);
+  int code = 0;
+  if (static_cast<int>(blockIdx.x) < nb_r) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n * n) {
+      const int r = idx % n, c = idx / n;
+      double v = 0.0;
+      if (r <= c) {
+        const double d = (A[r + static_cast<int64_t>(r) * k] < 0.0) ? -1.0 : 1.0;
+        v = d * A[r + static_cast<int64_t>(c) * k];
+        if (!isfinite(v)) code = 2;
+        else if (r == c && !(v > 0.0)) code = 1;
+      }
+      Rs[r + c * n] = v;
+      if (R) R[r + c * ldr] = v;
     }
-    Rs[r + c * n] = v;
-    if (R) R[r + c * ldr] = v;
-  }
-  if (S) {
-    for (int64_t idx = threadIdx.x; idx < static_cast<int64_t>(k) * n; idx += blockDim.x) {
+  } else if (S) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x - nb_r) * 256 + threadIdx.x;
+    if (idx < static_cast<int64_t>(k) * n) {
       const int i = static_cast<int>(idx % k), c = static_cast<int>(idx / k);
       const double d = (A[c + static_cast<int64_t>(c) * k] < 0.0) ? -1.0 : 1.0;
       S[i + c * lds] *= d;
     }
   }
+  if (code) atomicMax(&worst, code);
   __syncthreads();
-  if (threadIdx.x == 0) *status = bad_nonfinite ? 2 : (bad_rank ? 1 : 0);
+  if (threadIdx.x == 0 && worst) atomicMax(status, worst);
 }
 
 hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta, double* T,
@@ -292,6 +299,8 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     }
     attr_done = true;
   }
+  reset_status_kernel<<<1, 1, 0, st>>>(status);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int npan = static_cast<int>(ceil_div(n, kHhPanel));
   // Rows per lane of the one-wave-per-column kernels, from the panel height.
 #define RCQ_HH_RPL(L, STMT)                            \
@@ -337,7 +346,9 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     }
   }
 #undef RCQ_HH_RPL
-  hh_finalize_kernel<<<1, 256, 0, st>>>(A, k, n, Rs, R, ldr, S, lds, status);
+  const int nb_r = static_cast<int>(ceil_div(n * n, 256));
+  const int nb_s = S ? static_cast<int>(ceil_div(static_cast<int64_t>(k) * n, 256)) : 0;
+  hh_finalize_kernel<<<nb_r + nb_s, 256, 0, st>>>(A, k, n, Rs, R, ldr, S, lds, nb_r, status);
   return hipGetLastError();
 }
 
@@ -459,21 +470,35 @@ hipError_t launch_cholesky(double* G, int n, int ldg, int* status, hipStream_t s
 }
 
 // C = A B for upper triangular A, B (strict lower part of C set to 0).
-__global__ void triu_product_kernel(const double* __restrict__ A, int64_t lda,
-                                    const double* __restrict__ B, int64_t ldb,
-                                    double* __restrict__ C, int64_t ldc, int n) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  const int r = idx % n, c = idx / n;
+__global__ __launch_bounds__(256) void triu_product_kernel(const double* __restrict__ A,
+                                                           int64_t lda,
+                                                           const double* __restrict__ B,
+                                                           int64_t ldb, double* __restrict__ C,
+                                                           int64_t ldc, int n) {
+  // C(:, c) = triu(A) B(:, c) for upper triangular A, B; block c, thread r.
+  __shared__ double bc[kMaxN];
+  const int c = blockIdx.x, r = threadIdx.x;
+  if (r < n) bc[r] = (r <= c) ? B[r + static_cast<int64_t>(c) * ldb] : 0.0;
+  __syncthreads();
+  if (r >= n) return;
   double s = 0.0;
-  for (int l = r; l <= c; ++l) s += A[r + l * lda] * B[l + c * ldb];
-  C[r + c * ldc] = (r <= c) ? s : 0.0;
+  if (r <= c) {
+    int l = r;
+    for (; l + 8 <= c + 1; l += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = A[r + static_cast<int64_t>(l + u) * lda];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u] * bc[l + u];
+    }
+    for (; l <= c; ++l) s += A[r + static_cast<int64_t>(l) * lda] * bc[l];
+  }
+  C[r + static_cast<int64_t>(c) * ldc] = s;
 }
 
 hipError_t launch_triu_product(const double* A, int64_t lda, const double* B, int64_t ldb,
                                double* C, int64_t ldc, int n, hipStream_t st) {
-  triu_product_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, st>>>(A, lda, B, ldb,
-                                                                                    C, ldc, n);
+  triu_product_kernel<<<static_cast<unsigned>(n), 256, 0, st>>>(A, lda, B, ldb, C, ldc, n);
   return hipGetLastError();
 }
 
@@ -681,8 +706,7 @@ __global__ void gram_reduce_kernel(const double* __restrict__ gpart, int nsplit,
   if (r > c) return;
   const int64_t stride = static_cast<int64_t>(npg) * npg;
   const double* p = gpart + r + static_cast<int64_t>(c) * npg;
-  double s = 0.0;
-  for (int q = 0; q < nsplit; ++q) s += p[q * stride];
+  const double s = ordered_sum(p, nsplit, stride);
   G[r + c * npg] = s;
 }
 
@@ -701,8 +725,7 @@ __global__ void gram_reduce_full_kernel(const double* __restrict__ gpart, int ns
   const int r = idx % n, c = idx / n;
   const int64_t stride = static_cast<int64_t>(npg) * npg;
   const double* p = gpart + r + static_cast<int64_t>(c) * npg;
-  double s = 0.0;
-  for (int q = 0; q < nsplit; ++q) s += p[q * stride];
+  const double s = ordered_sum(p, nsplit, stride);
   G[r + c * npg] = s;
 }
 
