@@ -110,8 +110,8 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
   if (tid < 2 * Cg) colexp[tid] = kQUnset;
   if (tid == 0) *badflag = 0;
 
-  // Quantiser state: NSL task slots per thread.  Task (column cl, lane g of
-  // the column's G lanes) covers the 4-row groups G v + g (v < 4) of the
+  // Quantiser state: NSL task slots per thread.  Task (column group cg,
+  // lane g of the column's G lanes) covers the 4-row groups G v + g (v < 4) of the
   // stage, so that each load instruction reads 16 G contiguous bytes of a
   // column.  A task's column is fixed, so its scale exponent sq persists
   // across stages.  Columns past n read column n - 1 (their sums are never
@@ -124,7 +124,11 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
   for (int sl = 0; sl < NSL; ++sl) {
     sq[sl] = kQUnset;
     const int task = tid + sl * nthr;
-    qcol[sl] = task / G;
+    // The four column groups of a wave take columns 4 apart (a 4 x 4
+    // transpose within each 16 columns), so that their digit writes fall
+    // in distinct LDS banks.
+    const int cg = task / G;
+    qcol[sl] = (G == 16) ? ((cg & ~15) | ((cg & 3) << 2) | ((cg >> 2) & 3)) : cg;
     qg[sl] = task % G;
     const int c = (c0 + qcol[sl] < n) ? c0 + qcol[sl] : n - 1;
     qsrc[sl] = X + static_cast<int64_t>(c) * ldx + 4 * qg[sl];
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
     const int sc = sq[sl];
     const bool grow = (mx > 0.f) & ((sc == kQUnset) | (ex >= 22 - sc));
     sq[sl] = grow ? sn : sc;
-    colexp[buf * Cg + qcol[sl]] = sq[sl];
+    if (qg[sl] == 0) colexp[buf * Cg + qcol[sl]] = sq[sl];
     return pow2f(sq[sl] == kQUnset ? 0 : sq[sl]);
   };
   // Quantiser, second part: rows 4 (G v + g) .. + 3 of slot sl into the three
