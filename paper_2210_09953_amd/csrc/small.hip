@@ -33,7 +33,6 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   extern __shared__ double vsh[];  // [16][L]: reflector j = vsh[j L + r] (0 above row j)
   __shared__ double sc[kHhPanel][3];
   __shared__ double y[kHhPanel][kHhPanel];
-  __shared__ double tT[kHhPanel][kHhPanel + 1];
   const int L = k - p0;
   const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -93,39 +92,42 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
     }
     __syncthreads();
   }
-  // y[a][b] = v_a^T v_b for a < b.
+  // y[a][b] = v_a^T v_b for a < b (zero elsewhere).
   for (int pr = wave; pr < kHhPanel * kHhPanel; pr += 16) {
     const int a = pr / kHhPanel, b = pr % kHhPanel;
-    if (a >= b || b >= nbp) continue;
+    if (a >= b || b >= nbp) {
+      if (lane == 0) y[a][b] = 0.0;
+      continue;
+    }
     const double* va = vsh + a * L;
     const double* vb = vsh + b * L;
-    double s = 0.0;
-    for (int i = b + lane; i < L; i += 64) s += va[i] * vb[i];
-    s = wave_sum(s);
-    if (lane == 0) y[a][b] = s;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r >= b && r < L) sum += va[r] * vb[r];
+    }
+    sum = wave_sum(sum);
+    if (lane == 0) y[a][b] = sum;
   }
   __syncthreads();
-  // T upper (compact WY of the panel): T[j][j] = beta_j and
-  // T[0:j, j] = -beta_j T[0:j, 0:j] (V_{0:j}^T v_j); column j needs the
-  // previous columns only, so one wave builds it in LDS, lane a = row a.
-  if (wave == 0) {
-    const int a = lane;
-    for (int j = 0; j < kHhPanel; ++j) {
-      double tv = 0.0;
-      if (j < nbp) {
-        if (a < j) {
-          double acc = 0.0;
-          for (int l = a; l < j; ++l) acc += tT[a][l] * y[l][j];
-          tv = -sc[j][2] * acc;
-        } else if (a == j) {
-          tv = sc[j][2];
-        }
-      }
-      if (a < kHhPanel) tT[a][j] = tv;
-      wave_sync();
+  // T upper (compact WY of the panel): T^{-1} = diag(1 / beta) + strict
+  // upper part of V^T V, so column j of T follows by back substitution:
+  // T(j, j) = beta_j, T(i, j) = -beta_i sum_{i < l <= j} y(i, l) T(l, j).
+  // Lane j of wave 0 forms column j (entries below it stay zero).
+  if (wave == 0 && lane < kHhPanel) {
+    const int j = lane;
+    double t[kHhPanel];
+#pragma unroll
+    for (int i = kHhPanel - 1; i >= 0; --i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = i + 1; l < kHhPanel; ++l) acc += y[i][l] * t[l];
+      const double bi = (i < nbp) ? sc[i][2] : 0.0;
+      t[i] = (j >= nbp || i > j) ? 0.0 : ((i == j) ? bi : -bi * acc);
     }
-    if (a < kHhPanel)
-      for (int b = 0; b < kHhPanel; ++b) Tp[a + kHhPanel * b] = tT[a][b];
+#pragma unroll
+    for (int i = 0; i < kHhPanel; ++i) Tp[i + kHhPanel * j] = t[i];
   }
   if (tid < nbp) {
     v0g[p0 + tid] = sc[tid][1];
