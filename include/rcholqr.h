@@ -52,11 +52,14 @@ enum rcholqr_sketch_kind {
 
 /* Working precision of the dominant (tall) operations.
  *   F64:   X, Q FP64; sketch on FP64 matrix cores.
- *   F32:   X, Q FP32; sketch accumulated in FP64, solves and Gram in FP32.
- *   MIXED: X, Q FP32; Rademacher sketch on FP16 matrix cores (X split into
- *          FP16 hi + lo with per-tile power-of-two column scaling, +-1
- *          exact, FP32 accumulation flushed to FP64), solves and Gram in
- *          FP32.  Requires RCHOLQR_RADEMACHER.
+ *   F32:   X, Q FP32; sketch accumulated in FP64; solves and Gram with
+ *          FP32 accuracy on bf16 matrix cores (each FP32 operand split
+ *          exactly into three bf16 parts, six products kept).
+ *   MIXED: X, Q FP32; Rademacher sketch computed exactly on int8 matrix
+ *          cores (each column of X rounded to a 24-bit fixed-point value
+ *          under a power-of-two scale, three byte planes times the +-1
+ *          entries, integer sums folded into FP64); solves and Gram as F32.
+ *          Requires RCHOLQR_RADEMACHER.
  * In every precision the small k x n QR, the Cholesky factorisation and
  * the R' R_s product run in FP64 on the GPU (Section 5: minor operations
  * in higher precision). */
