@@ -356,118 +356,169 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
 
 // ----------------------------------------------------------------------------
 // Cholesky, upper, in place on G (ld ldg); only the upper triangle is read
-// and written.  Blocked right-looking in 32-column panels: one wave factors
-// the 32 x 32 diagonal block in LDS, threads solve the panel's rows to the
-// right (multiplying by the pivots' reciprocals), and the trailing update
-// G -= Rp^T Rp runs on FP64 matrix cores in 16 x 16 tiles.  Status
-// 1000 + j at the first pivot that is not positive and finite (only if the
-// status word is still 0).
-constexpr int kChB = 32;
+// and written.  Right-looking in 16-column panels with the whole upper
+// triangle held in registers as 16 x 16 tiles (tile (i, j), i <= j, belongs
+// to wave (tile index) % 8 of one 512-thread workgroup):
+//   1. wave 0 factors the diagonal tile in LDS (no barriers inside a wave)
+//      and forms W = R_PP^{-1} by back substitution, one lane per column;
+//   2. the owners of row P's tiles form R_Pj = W^T G_Pj on FP64 matrix cores
+//      (a tile's accumulator layout is the B operand's) and publish them;
+//   3. the owners of the trailing tiles subtract R_Pi^T R_Pj on matrix cores.
+// Status 1000 + j at the first pivot that is not positive and finite (only
+// if the status word is still 0).
+constexpr int kChTiles = (kMaxN / 16) * (kMaxN / 16 + 1) / 2;  // 136
+constexpr int kChWaves = 8;
+constexpr int kChPerWave = (kChTiles + kChWaves - 1) / kChWaves;  // 17
 
-__global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int n, int ldg,
+__global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict__ G, int n, int ldg,
                                                     int* __restrict__ status) {
-  __shared__ double dg[kChB][kChB + 1];
-  __shared__ double rinv[kChB];
-  __shared__ double rp[kChB][kMaxN + 1];
+  __shared__ double dgb[16][17];        // diagonal tile being factored
+  __shared__ double wl[16][17];         // W = R_PP^{-1}
+  __shared__ double rp[16][kMaxN + 1];  // row panel R_P,: (16 x n)
   __shared__ int fail;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, lg = lane >> 4;
+  const int nt = (n + 15) / 16;
+  const int ntile = nt * (nt + 1) / 2;
   if (tid == 0) fail = 0;
-  for (int c0 = 0; c0 < n; c0 += kChB) {
-    const int w = (n - c0 < kChB) ? n - c0 : kChB;
-    for (int idx = tid; idx < kChB * kChB; idx += blockDim.x) {
-      const int i = idx % kChB, c = idx / kChB;
-      double v;
-      if (i < w && c < w)
-        v = (i <= c) ? G[(c0 + i) + static_cast<int64_t>(c0 + c) * ldg] : 0.0;
-      else
-        v = (i == c) ? 1.0 : 0.0;
-      dg[i][c] = v;
+  // tile index -> (i, j), column-major over the upper triangle
+  auto decode = [](int t, int& ti, int& tj) {
+    tj = 0;
+    while (t > tj) {
+      t -= tj + 1;
+      ++tj;
     }
+    ti = t;
+  };
+  d4 acc[kChPerWave];
+#pragma unroll
+  for (int u = 0; u < kChPerWave; ++u) {
+    const int t = wave + kChWaves * u;
+    int ti, tj;
+    decode(t, ti, tj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
+      double x = 0.0;
+      if (t < ntile) {
+        if (r < n && c < n)
+          x = (r <= c) ? G[r + static_cast<int64_t>(c) * ldg] : 0.0;
+        else
+          x = (r == c) ? 1.0 : 0.0;
+      }
+      acc[u][v] = x;
+    }
+  }
+  for (int P = 0; P < nt; ++P) {
+    // 1. the diagonal tile to LDS (its owner), then wave 0 factors it.
+    const int tdiag = P * (P + 1) / 2 + P;
+#pragma unroll
+    for (int u = 0; u < kChPerWave; ++u)
+      if (wave + kChWaves * u == tdiag)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dgb[drow<double>(lg, v)][l16] = acc[u][v];
     __syncthreads();
     if (wave == 0) {
-      const int c = lane;  // lanes 0..31 own columns of the block
-#pragma unroll
-      for (int j = 0; j < kChB; ++j) {
-        const double d = dg[j][j];
+      // lane holds elements (i = lane & 15, c = (lane >> 4) + 4 q), q < 4
+      const int i = lane & 15;
+      for (int j = 0; j < 16; ++j) {
+        const double d = dgb[j][j];
         const bool ok = (d > 0.0) && isfinite(d);
         const double r = ok ? sqrt(d) : 1.0;
         const double ri = 1.0 / r;
-        if (!ok && lane == 0 && fail == 0 && j < w) fail = c0 + j + 1;
-        double rjc = 0.0;
-        if (c < kChB && c > j) {
-          rjc = dg[j][c] * ri;
-          dg[j][c] = rjc;
-        }
-        if (lane == j) {
-          dg[j][j] = r;
-          rinv[j] = ri;
-        }
-        wave_sync();
-        if (c < kChB && c > j) {
+        if (!ok && lane == 0 && fail == 0 && 16 * P + j < n) fail = 16 * P + j + 1;
+        // row j: scale to the right of the pivot
 #pragma unroll
-          for (int i = j + 1; i < kChB; ++i)
-            if (i <= c) dg[i][c] -= dg[j][i] * rjc;
+        for (int q = 0; q < 4; ++q) {
+          const int c = (lane >> 4) + 4 * q;
+          if (i == j && c > j) dgb[j][c] *= ri;
+        }
+        if (lane == 0) dgb[j][j] = r;
+        wave_sync();
+        // trailing part of the tile: (i, c) with j < i <= c
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = (lane >> 4) + 4 * q;
+          if (i > j && i <= c) dgb[i][c] -= dgb[j][i] * dgb[j][c];
         }
         wave_sync();
+      }
+      // W = R^{-1}, column c = lane (< 16): W(c, c) = 1 / R(c, c),
+      // W(a, c) = -(sum_{a < l <= c} R(a, l) W(l, c)) / R(a, a).
+      if (lane < 16) {
+        const int c = lane;
+        for (int a = 15; a >= 0; --a) {
+          double acc2 = 0.0;
+          for (int l = a + 1; l <= c; ++l) acc2 += dgb[a][l] * wl[l][c];
+          const double inv = 1.0 / dgb[a][a];
+          wl[a][c] = (a > c) ? 0.0 : ((a == c) ? inv : -acc2 * inv);
+        }
       }
     }
     __syncthreads();
     if (fail) break;
-    for (int idx = tid; idx < w * w; idx += blockDim.x) {
-      const int i = idx % w, c = idx / w;
-      if (i <= c) G[(c0 + i) + static_cast<int64_t>(c0 + c) * ldg] = dg[i][c];
-    }
-    const int nt = n - c0 - w;
-    if (tid < nt) {  // one thread per column to the right: Rp = Rd^{-T} G_panel
-      const int c = c0 + w + tid;
-      for (int i = 0; i < kChB; ++i) {
-        double sv = (i < w) ? G[(c0 + i) + static_cast<int64_t>(c) * ldg] : 0.0;
-        for (int l = 0; l < i; ++l) sv -= dg[l][i] * rp[l][tid];
-        sv *= rinv[i];
-        rp[i][tid] = sv;
-        if (i < w) G[(c0 + i) + static_cast<int64_t>(c) * ldg] = sv;
-      }
-    }
-    __syncthreads();
-    // Trailing update on 16 x 16 tiles (ti <= tj) of the remaining nt columns.
-    const int ntt = (nt + 15) / 16;
-    const int ntiles = ntt * (ntt + 1) / 2;
-    for (int tile = wave; tile < ntiles; tile += 16) {
-      int ti = 0, tj = 0, cnt = tile;
-      while (cnt > tj) {  // decode upper-triangular tile index (row ti, column tj)
-        cnt -= tj + 1;
-        ++tj;
-      }
-      ti = cnt;
-      d4 acc;
+    // 2. row P: diagonal tile <- R_PP; R_Pj = W^T G_Pj for j > P.
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
-        acc[v] = (i < nt && c < nt) ? G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] : 0.0;
-      }
+    for (int u = 0; u < kChPerWave; ++u) {
+      const int t = wave + kChWaves * u;
+      if (t >= ntile) continue;
+      int ti, tj;
+      decode(t, ti, tj);
+      if (ti != P) continue;
+      if (tj == P) {
 #pragma unroll
-      for (int ks = 0; ks < kChB / 4; ++ks) {
-        const int kk = 4 * ks + lg;
-        const int ci = 16 * ti + l16, cj = 16 * tj + l16;
-        const double a = (ci < nt) ? -rp[kk][ci] : 0.0;
-        const double b = (cj < nt) ? rp[kk][cj] : 0.0;
-        acc = mfma16x16x4(a, b, acc);
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int rr = drow<double>(lg, v);
+          acc[u][v] = (rr <= l16) ? dgb[rr][l16] : 0.0;
+        }
+      } else {
+        d4 y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
-        if (i < nt && c < nt && i <= c) G[(c0 + w + i) + static_cast<int64_t>(c0 + w + c) * ldg] = acc[v];
+        for (int sk = 0; sk < 4; ++sk)  // A(M = l16, K = 4 sk + lg) = W(4 sk + lg, l16)
+          y = mfma16x16x4(wl[4 * sk + lg][l16], acc[u][sk], y);
+        acc[u] = y;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rp[drow<double>(lg, v)][16 * tj + l16] = y[v];
       }
     }
     __syncthreads();
+    // 3. trailing tiles (i, j), P < i <= j: G_ij -= R_Pi^T R_Pj.
+#pragma unroll
+    for (int u = 0; u < kChPerWave; ++u) {
+      const int t = wave + kChWaves * u;
+      if (t >= ntile) continue;
+      int ti, tj;
+      decode(t, ti, tj);
+      if (ti <= P) continue;
+#pragma unroll
+      for (int sk = 0; sk < 4; ++sk) {
+        const double a = -rp[4 * sk + lg][16 * ti + l16];  // A(M = l16, K) = R_Pi(K, l16)
+        const double bb = rp[4 * sk + lg][16 * tj + l16];  // B(K, N = l16) = R_Pj(K, l16)
+        acc[u] = mfma16x16x4(a, bb, acc[u]);
+      }
+    }
+    // the next panel's first barrier orders these updates before its reads
   }
   __syncthreads();
+  if (!fail) {
+#pragma unroll
+    for (int u = 0; u < kChPerWave; ++u) {
+      const int t = wave + kChWaves * u;
+      if (t >= ntile) continue;
+      int ti, tj;
+      decode(t, ti, tj);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
+        if (r < n && c < n && r <= c) G[r + static_cast<int64_t>(c) * ldg] = acc[u][v];
+      }
+    }
+  }
   if (tid == 0 && fail) atomicCAS(status, 0, 1000 + fail - 1);
 }
 
 hipError_t launch_cholesky(double* G, int n, int ldg, int* status, hipStream_t st) {
-  chol_kernel<<<1, 1024, 0, st>>>(G, n, ldg, status);
+  chol_kernel<<<1, 64 * kChWaves, 0, st>>>(G, n, ldg, status);
   return hipGetLastError();
 }
 
