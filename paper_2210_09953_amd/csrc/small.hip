@@ -359,8 +359,9 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
 // and written.  Right-looking in 16-column panels with the whole upper
 // triangle held in registers as 16 x 16 tiles (tile (i, j), i <= j, belongs
 // to wave (tile index) % 8 of one 512-thread workgroup):
-//   1. wave 0 factors the diagonal tile in LDS (no barriers inside a wave)
-//      and forms W = R_PP^{-1} by back substitution, one lane per column;
+//   1. one wave factors the diagonal tile in registers (a lane per column,
+//      pivots and rows shared by lane reads) and, by the same elimination
+//      on the identity, forms W^T = R_PP^{-T};
 //   2. the owners of row P's tiles form R_Pj = W^T G_Pj on FP64 matrix cores
 //      (a tile's accumulator layout is the B operand's) and publish them;
 //   3. the owners of the trailing tiles subtract R_Pi^T R_Pj on matrix cores.
@@ -373,7 +374,7 @@ constexpr int kChPerWave = (kChTiles + kChWaves - 1) / kChWaves;  // 17
 __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict__ G, int n, int ldg,
                                                     int* __restrict__ status) {
   __shared__ double dgb[16][17];        // diagonal tile being factored
-  __shared__ double wl[16][17];         // W = R_PP^{-1}
+  __shared__ double wl[16][17];         // W^T, W = R_PP^{-1}
   __shared__ double rp[16][kMaxN + 1];  // row panel R_P,: (16 x n)
   __shared__ int fail;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -418,41 +419,44 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
 #pragma unroll
         for (int v = 0; v < 4; ++v) dgb[drow<double>(lg, v)][l16] = acc[u][v];
     __syncthreads();
-    if (wave == 0) {
-      // lane holds elements (i = lane & 15, c = (lane >> 4) + 4 q), q < 4
-      const int i = lane & 15;
+    if (wave == 0 && lane < 32) {
+      // Lanes 0..15 hold column c = lane of the tile, lanes 16..31 column
+      // c = lane - 16 of the identity, 16 values each in registers.  The
+      // elimination that turns the tile into R (row j scaled by 1 / r_jj,
+      // rows below it reduced) turns the identity into R^{-T} = W^T; the
+      // pivot and row j reach every lane by lane reads.
+      const bool apart = lane < 16;
+      const int c = lane & 15;
+      double col[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) col[i] = apart ? dgb[i][c] : ((i == c) ? 1.0 : 0.0);
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double d = dgb[j][j];
+        const double d = read_lane(col[j], j);
         const bool ok = (d > 0.0) && isfinite(d);
         const double r = ok ? sqrt(d) : 1.0;
         const double ri = 1.0 / r;
         if (!ok && lane == 0 && fail == 0 && 16 * P + j < n) fail = 16 * P + j + 1;
-        // row j: scale to the right of the pivot
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = (lane >> 4) + 4 * q;
-          if (i == j && c > j) dgb[j][c] *= ri;
+        // row j: R(j, c) = A(j, c) / r for c > j; the identity part is scaled whole
+        if (apart) {
+          if (c == j) col[j] = r;
+          else if (c > j) col[j] *= ri;
+        } else {
+          col[j] *= ri;
         }
-        if (lane == 0) dgb[j][j] = r;
-        wave_sync();
-        // trailing part of the tile: (i, c) with j < i <= c
+        // rows i > j: A(i, c) -= R(j, i) R(j, c) (c >= i in the tile part)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = (lane >> 4) + 4 * q;
-          if (i > j && i <= c) dgb[i][c] -= dgb[j][i] * dgb[j][c];
+        for (int i = j + 1; i < 16; ++i) {
+          const double rji = read_lane(col[j], i);  // R(j, i) sits in lane i
+          if (!apart || i <= c) col[i] -= rji * col[j];
         }
-        wave_sync();
       }
-      // W = R^{-1}, column c = lane (< 16): W(c, c) = 1 / R(c, c),
-      // W(a, c) = -(sum_{a < l <= c} R(a, l) W(l, c)) / R(a, a).
-      if (lane < 16) {
-        const int c = lane;
-        for (int a = 15; a >= 0; --a) {
-          double acc2 = 0.0;
-          for (int l = a + 1; l <= c; ++l) acc2 += dgb[a][l] * wl[l][c];
-          const double inv = 1.0 / dgb[a][a];
-          wl[a][c] = (a > c) ? 0.0 : ((a == c) ? inv : -acc2 * inv);
-        }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (apart)
+          dgb[i][c] = (i <= c) ? col[i] : 0.0;
+        else
+          wl[i][c] = col[i];  // W^T(i, c)
       }
     }
     __syncthreads();
@@ -474,8 +478,8 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
       } else {
         d4 y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int sk = 0; sk < 4; ++sk)  // A(M = l16, K = 4 sk + lg) = W(4 sk + lg, l16)
-          y = mfma16x16x4(wl[4 * sk + lg][l16], acc[u][sk], y);
+        for (int sk = 0; sk < 4; ++sk)  // A(M = l16, K = 4 sk + lg) = W^T(l16, 4 sk + lg)
+          y = mfma16x16x4(wl[l16][4 * sk + lg], acc[u][sk], y);
         acc[u] = y;
 #pragma unroll
         for (int v = 0; v < 4; ++v) rp[drow<double>(lg, v)][16 * tj + l16] = y[v];
