@@ -280,7 +280,7 @@ def main():
     ap.add_argument("--workload", default="mixed-4m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain copy of 1 GiB (byte-counter reference)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
