@@ -50,14 +50,17 @@ __global__ void theta_debug_kernel(int kind, int k, uint64_t seed, int64_t i0, i
 constexpr int kSkRows = 16;  // rows of X per LDS stage
 
 template <typename TX, int NB>
-__global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict__ X, int64_t m,
+__global__ __launch_bounds__(256, 2) void sketch_dense_kernel(const TX* __restrict__ X, int64_t m,
                                                            int n, int64_t ldx, int kind,
                                                            uint64_t seed, int ktiles,
                                                            int64_t rows_per_split, int kpad,
                                                            double* __restrict__ part) {
   constexpr int NP = NB * 16;
-  __shared__ double xs[kSkRows][NP + 1];
-  __shared__ double zs[4][kSkRows][16];
+  // Stages of 16 rows, double buffered: while the matrix cores work on
+  // stage i, the X loads of stage i + 2 are in flight in registers and stage
+  // i + 1 (its X and this wave's Theta block) is already in LDS.
+  __shared__ double xs[2][kSkRows][NP + 1];
+  __shared__ double zs[2][4][kSkRows][16];
 
   // XCD-aware decode: workgroup ids are dealt round-robin to the 8 XCDs;
   // consecutive ids on one XCD walk the Theta tiles of one row range.
@@ -78,17 +81,23 @@ __global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict_
   Words rw{0u, 0u, 0u, 0u};  // Rademacher words of this lane's Theta row
   int64_t rblk = -1;
 
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kSkRows) {
-    __syncthreads();
-    // Stage X(r0:r0+16, 0:NP) in LDS, row-major, zero-padded.
-    for (int idx = threadIdx.x; idx < kSkRows * NP; idx += 256) {
-      const int jj = idx % kSkRows, c = idx / kSkRows;
-      const int64_t row = r0 + jj;
-      double v = 0.0;
-      if (row < r_end && c < n) v = static_cast<double>(X[row + static_cast<int64_t>(c) * ldx]);
-      xs[jj][c] = v;
+  // X prefetch: element e of thread t is row t % 16, column t / 16 + 16 e.
+  const int pjj = threadIdx.x & 15, pc0 = threadIdx.x >> 4;
+  TX pre[NB];
+  auto fetch = [&](int64_t r0) {
+    const int64_t row = r0 + pjj;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int c = pc0 + 16 * e;
+      pre[e] = (row < r_end && c < n) ? X[row + static_cast<int64_t>(c) * ldx] : TX(0);
     }
-    // Theta(ibase:ibase+16, r0:r0+16) for this wave.
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) xs[buf][pjj][pc0 + 16 * e] = static_cast<double>(pre[e]);
+  };
+  // Theta(ibase:ibase+16, r0:r0+16) for this wave.
+  auto gen = [&](int64_t r0, int buf) {
     if (kind == kGaussian) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -97,8 +106,8 @@ __global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict_
         const int64_t row = r0 + jj;
         double z0 = 0.0, z1 = 0.0;
         if (row < r_end) gauss_pair(seed, row, static_cast<uint32_t>((ibase >> 1) + ip), z0, z1);
-        zs[wave][jj][2 * ip] = z0;
-        zs[wave][jj][2 * ip + 1] = z1;
+        zs[buf][wave][jj][2 * ip] = z0;
+        zs[buf][wave][jj][2 * ip + 1] = z1;
       }
     } else {
       // Lane: Theta row ibase + (lane & 15), rows jj0..jj0+3 of the stage.
@@ -114,16 +123,33 @@ __global__ __launch_bounds__(256) void sketch_dense_kernel(const TX* __restrict_
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = r0 + jj0 + e;
-        zs[wave][jj0 + e][ii] = (row < r_end) ? (radem_bit(rw, o + e) ? -1.0 : 1.0) : 0.0;
+        zs[buf][wave][jj0 + e][ii] = (row < r_end) ? (radem_bit(rw, o + e) ? -1.0 : 1.0) : 0.0;
       }
     }
-    __syncthreads();
+  };
+  if (r_begin < r_end) {
+    fetch(r_begin);
+    put(0);
+    gen(r_begin, 0);
+    if (r_begin + kSkRows < r_end) fetch(r_begin + kSkRows);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kSkRows) {
 #pragma unroll
     for (int ks = 0; ks < kSkRows / 4; ++ks) {
-      const double a = zs[wave][4 * ks + lg][l16];
+      const double a = zs[cur][wave][4 * ks + lg][l16];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = mfma16x16x4(a, xs[4 * ks + lg][16 * b + l16], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma16x16x4(a, xs[cur][4 * ks + lg][16 * b + l16], acc[b]);
     }
+    const int64_t r1 = r0 + kSkRows;
+    if (r1 < r_end) {
+      put(cur ^ 1);
+      gen(r1, cur ^ 1);
+      if (r1 + kSkRows < r_end) fetch(r1 + kSkRows);
+    }
+    __syncthreads();
+    cur ^= 1;
   }
   // Partial layout: part[s][c][i], ld = kpad, for c < NP.
   double* dst = part + static_cast<int64_t>(s) * NP * kpad;
