@@ -33,6 +33,7 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   extern __shared__ double vsh[];  // [16][L]: reflector j = vsh[j L + r] (0 above row j)
   __shared__ double sc[kHhPanel][3];
   __shared__ double y[kHhPanel][kHhPanel];
+  __shared__ double ypart[8][kHhPanel][kHhPanel + 1];
   const int L = k - p0;
   const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -45,14 +46,14 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   }
   // Wave j: reflector from its column (rows >= j), diagonal becomes alpha.
   auto reflect = [&](int j) {
-    double t = 0.0;
+    double tq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + 64 * q;
-      if (r > j && r < L) t += xr[q] * xr[q];
+      if (r > j && r < L) tq[q & 3] += xr[q] * xr[q];
     }
-    t = wave_sum(t);
-    const double x0 = __shfl(xr[0], j, 64);  // j < 16: row j is lane j, q = 0
+    const double t = wave_sum((tq[0] + tq[1]) + (tq[2] + tq[3]));
+    const double x0 = read_lane(xr[0], j);  // j < 16: row j is lane j, q = 0
     const double nrm = sqrt(x0 * x0 + t);
     const double alpha = (x0 >= 0.0) ? -nrm : nrm;
     const double v0 = x0 - alpha;
@@ -75,40 +76,54 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   for (int j = 0; j < nbp; ++j) {
     if (wave > j && own) {
       const double* vj = vsh + j * L;
-      double w = 0.0;
+      double wq[4] = {0.0, 0.0, 0.0, 0.0};
+      double vr[RPL];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         const int r = lane + 64 * q;
-        if (r < L) w += vj[r] * xr[q];
+        vr[q] = (r < L) ? vj[r] : 0.0;
+        wq[q & 3] += vr[q] * xr[q];
       }
-      w = wave_sum(w);
+      const double w = wave_sum((wq[0] + wq[1]) + (wq[2] + wq[3]));
       const double f = sc[j][2] * w;
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int r = lane + 64 * q;
-        if (r < L) xr[q] -= f * vj[r];
-      }
+      for (int q = 0; q < RPL; ++q) xr[q] -= f * vr[q];
       if (wave == j + 1) reflect(j + 1);
     }
     __syncthreads();
   }
-  // y[a][b] = v_a^T v_b for a < b (zero elsewhere).
-  for (int pr = wave; pr < kHhPanel * kHhPanel; pr += 16) {
-    const int a = pr / kHhPanel, b = pr % kHhPanel;
-    if (a >= b || b >= nbp) {
-      if (lane == 0) y[a][b] = 0.0;
-      continue;
+  // y = V^T V (strict upper part used) on FP64 matrix cores: wave w sums the
+  // rows of its chunk (A(a, r) = V(r, a), B(r, b) = V(r, b)); partials are
+  // added in a fixed order (w + 8 into w, then w = 0..7).
+  {
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int chunk = ((L + 63) / 64) * 4;  // rows per wave, a multiple of 4
+    const int rb = wave * chunk;
+    d4 yp = d4{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = rb; r0 < rb + chunk; r0 += 4) {
+      const int r = r0 + lg;
+      const double av = (r < L && l16 < nbp) ? vsh[l16 * L + r] : 0.0;
+      yp = mfma16x16x4(av, av, yp);
     }
-    const double* va = vsh + a * L;
-    const double* vb = vsh + b * L;
-    double sum = 0.0;
+    // waves 8..15 hand their partials to waves 0..7 (LDS for 8 partials)
+    if (wave >= 8)
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const int r = lane + 64 * q;
-      if (r >= b && r < L) sum += va[r] * vb[r];
-    }
-    sum = wave_sum(sum);
-    if (lane == 0) y[a][b] = sum;
+      for (int v = 0; v < 4; ++v) ypart[wave - 8][drow<double>(lg, v)][l16] = yp[v];
+    __syncthreads();
+    if (wave < 8)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yp[v] += ypart[wave][drow<double>(lg, v)][l16];
+    __syncthreads();
+    if (wave < 8)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ypart[wave][drow<double>(lg, v)][l16] = yp[v];
+  }
+  __syncthreads();
+  if (tid < kHhPanel * kHhPanel) {
+    const int a = tid >> 4, b = tid & 15;
+    double sum = 0.0;
+    for (int w = 0; w < 8; ++w) sum += ypart[w][a][b];
+    y[a][b] = (a < b && b < nbp) ? sum : 0.0;
   }
   __syncthreads();
   // T upper (compact WY of the panel): T^{-1} = diag(1 / beta) + strict
@@ -120,9 +135,10 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
     double t[kHhPanel];
 #pragma unroll
     for (int i = kHhPanel - 1; i >= 0; --i) {
-      double acc = 0.0;
+      double ac[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int l = i + 1; l < kHhPanel; ++l) acc += y[i][l] * t[l];
+      for (int l = i + 1; l < kHhPanel; ++l) ac[l & 3] += y[i][l] * t[l];
+      const double acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
       const double bi = (i < nbp) ? sc[i][2] : 0.0;
       t[i] = (j >= nbp || i > j) ? 0.0 : ((i == j) ? bi : -bi * acc);
     }

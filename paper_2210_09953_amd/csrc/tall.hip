@@ -831,9 +831,10 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
     }                                                                           \
     first = false;                                                              \
   } while (0)
-  // FP32: register prefetch of the next stage (kGrRows x NP values over
-  // NW*64 threads).  FP64 (accumulators twice as large): direct staging.
-  constexpr bool kPre = sizeof(T) == 4 && !CROSS;
+  // Register prefetch of the next stage (kGrRows x NP values over NW*64
+  // threads): its loads overlap this stage's products.  FP64 with ten
+  // waves (three per SIMD) has no registers to spare and stages directly.
+  constexpr bool kPre = !CROSS && (sizeof(T) == 4 || NBB <= 3);
   constexpr int PER = kPre ? (kGrRows * NP + NW * 64 - 1) / (NW * 64) : 1;
   T pre[PER];
   auto fetch = [&](int64_t r0) {
