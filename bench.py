@@ -324,6 +324,12 @@ def main():
     dom = max(phases, key=phases.get)
     traffic = measured_traffic(args.workload, phase_kernel(dom, W["kind"], prec))
     roof = roofline(dom, phases[dom], m, n, k, W["kind"], prec, traffic)
+    # The same model for every tall phase (context for the dominant one).
+    phase_roof = {}
+    for ph in ("sketch", "solve1", "gram", "solve2"):
+        r = roofline(ph, phases[ph], m, n, k, W["kind"], prec,
+                     measured_traffic(args.workload, phase_kernel(ph, W["kind"], prec)))
+        phase_roof[ph] = {key: r[key] for key in ("bound", "achieved", "unit", "frac", "traffic")}
     if args.copy_probe:
         # Known-size plain copy for scaling the byte counters (outside the timed region).
         src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
@@ -376,6 +382,7 @@ def main():
         "orth": orth, "resid": res,
         "phases_ms": {p: round(v, 4) for p, v in phases.items()},
         "roofline": roof,
+        "phase_rooflines": phase_roof,
         "fp64": fp64,
         "cpu_baseline": cpu,
     }
