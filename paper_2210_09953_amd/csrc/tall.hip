@@ -338,6 +338,12 @@ __device__ __forceinline__ void dma_panel(const unsigned char* __restrict__ src,
   }
 }
 
+// One 16-byte direct global -> LDS load per lane: lane L's bytes land at
+// slot + 16 L.
+__device__ __forceinline__ void dma16(const void* src, void* slot) {
+  __builtin_amdgcn_global_load_lds(src, slot, 16, 0, 0);
+}
+
 // s_waitcnt vmcnt(N).
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -385,44 +391,58 @@ __host__ __device__ constexpr int bf3_panel_offset(int b) {
 // Bytes of panel b of T (chunks 0..b/2 of 3 KiB).
 __host__ __device__ constexpr int trmm_bf3_psize(int b) { return (b / 2 + 1) * 3072; }
 
-template <int NB>
+// FULL and blk0 as for trsm_bf3_kernel (n = 32 NCH when FULL).
+template <int NB, bool FULL>
 __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int64_t m, int n, int64_t ldq,
-                                                       const unsigned char* __restrict__ pan3) {
+                                                       const unsigned char* __restrict__ pan3,
+                                                       int64_t blk0) {
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = NCH * 3072;
   constexpr int SLOT = dma_kib(PMAX) * 1024;
   // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
-  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024];
+  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024 + (FULL ? 2 * 2048 * kTallWaves : 0)];
+  auto xslot = [&](int ch) -> float* {
+    return reinterpret_cast<float*>(ring + 3 * SLOT + 1024 + (ch % 2) * 2048 * kTallWaves + 2048 * (threadIdx.x >> 6));
+  };
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
-  // Q1 row l16 of this wave, columns 32 ch + 8 lg + e: all loads are issued
-  // first; chunk ch is split into its three bf16 planes just before output
-  // panel 2 ch, the first that needs it, so the loads of later chunks
-  // overlap the earlier panels.
-  // Loads clamp the row and column (no branches): rows past m are never
-  // stored, and columns past n meet zero rows of T.
+  const int64_t row = (blk0 + blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
+  // Q1 row l16 of this wave, columns 32 ch + 8 lg + e.  Chunk ch is loaded
+  // with the staging of output panel 2 ch, the first that needs it (two
+  // panels ahead), and split into its three bf16 planes just before that
+  // panel; the loads overlap the earlier panels.  Loads clamp the row and
+  // column (no branches): rows past m are never stored, and columns past n
+  // meet zero rows of T.  In place: panel b overwrites columns 16b..16b+15
+  // of rows that this lane has already loaded.
   float xq[NCH][8];
-  const bool full = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + 16 * kTallWaves <= m && n == 32 * NCH;
+  constexpr bool full = FULL;
   const float* qrow = Q + (row < m ? row : m - 1);
-  if (full) {
-    // lane base at column 8 lg; the chunk/element offsets are uniform
-    const float* qb0 = qrow + static_cast<int64_t>(8 * lg) * ldq;
+  // Whole tiles stage chunk ch in LDS by two direct loads per wave: load i,
+  // lane L = 16 e' + 4 g + q brings rows 4q..4q+3 of column 32 ch + 8 g +
+  // 4 i + e', so that the reads of element e (float 256 (e / 4) + 64 (e % 4)
+  // + 16 lg + l16) fall in distinct banks.
+  const float* qtile = Q + (row - l16) + 4 * (lane & 3) +
+                       static_cast<int64_t>(8 * ((lane >> 2) & 3) + (lane >> 4)) * ldq;
+  auto load_chunk = [&](int ch) {
+    if (full) {
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) xq[ch][e] = qb0[static_cast<int64_t>(32 * ch + e) * ldq];
-  } else {
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
+      for (int i = 0; i < 2; ++i)
+        dma16(qtile + static_cast<int64_t>(32 * ch + 4 * i) * ldq, xslot(ch) + 256 * i);
+    } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int col = 32 * ch + 8 * lg + e;
         xq[ch][e] = qrow[static_cast<int64_t>(col < n ? col : n - 1) * ldq];
       }
-  }
+    }
+  };
   u4b_t qb[NCH][3];
   auto split_chunk = [&](int ch) {
+    if (full) {
+      const float* xl = xslot(ch) + 16 * lg + l16;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xq[ch][e] = xl[256 * (e / 4) + 64 * (e % 4)];
+    }
     uint32_t hp[8], dp[8], lp[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) split3(xq[ch][e], hp[e], dp[e], lp[e]);
@@ -438,21 +458,28 @@ __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int
               lane);
   };
   stage(0);
+  load_chunk(0);
   if (NB > 1) stage(1);
   static_for<NB>([&](auto bc) {
     constexpr int b = decltype(bc)::value;
-    // Panel b has landed once the memory operations issued after its
-    // staging are all that remain (see trsm_bf3_kernel).
+    // Panel b (and, for even b, chunk b/2) has landed once the memory
+    // operations issued after them are all that remain: 4 stores per
+    // earlier panel, and per later panel its staging plus, for even panels,
+    // the 2 loads of its chunk (see trsm_bf3_kernel).
     if (full) {
-      constexpr int later = (b == 0) ? (NB > 1 ? dma_per_wave(trmm_bf3_psize(1)) : 0)
-                          : (b == 1) ? (NB > 2 ? dma_per_wave(trmm_bf3_psize(2)) : 0) + 4
-                                     : 8 + (b + 1 < NB ? dma_per_wave(trmm_bf3_psize(b + 1)) : 0);
+      constexpr int d1 = (b + 1 < NB) ? dma_per_wave(trmm_bf3_psize(b + 1)) +
+                                            (((b + 1) % 2 == 0) ? 2 : 0)
+                                      : 0;
+      constexpr int later = (b == 0) ? d1 : (b == 1) ? d1 + 4 : d1 + 8;
       wait_vmcnt<later>();
     } else {
       wait_vmcnt<0>();
     }
     wg_barrier();
-    if (b + 2 < NB) stage(b + 2);
+    if (b + 2 < NB) {
+      stage(b + 2);
+      if ((b & 1) == 0) load_chunk(b / 2 + 1);
+    }
     if ((b & 1) == 0) split_chunk(b / 2);
     const u4b_t* pa = reinterpret_cast<const u4b_t*>(ring + SLOT * (b % 3)) + lane;
     // One chain per chunk (independent, so the matrix cores pipeline them),
@@ -522,40 +549,49 @@ typedef short s4b_t __attribute__((ext_vector_type(4)));
 // Bytes of subpanel b of the solve's panels ((b+1)/2 chunks, diagonal inverse).
 __host__ __device__ constexpr int trsm_bf3_psize(int b) { return ((b + 1) / 2) * 3072 + 1536; }
 
-template <int NB>
+// FULL: every workgroup covers 16 kTallWaves rows below m and n = 16 NB (no
+// bounds checks, so the wait counts are exact); otherwise rows and columns
+// are checked.  Workgroup i covers the tile blk0 + i.
+template <int NB, bool FULL>
 __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* X, int64_t m, int n,
                                                        int64_t ldx,
                                                        const unsigned char* __restrict__ pan3,
-                                                       float* Q, int64_t ldq) {
+                                                       float* Q, int64_t ldq, int64_t blk0) {
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = (NB / 2) * 3072 + 1536;
   constexpr int SLOT = dma_kib(PMAX) * 1024;
   // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
-  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024];
+  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024 + (FULL ? 3 * 1024 * kTallWaves : 0)];
+  auto xslot = [&](int b) -> float* {
+    return reinterpret_cast<float*>(ring + 3 * SLOT + 1024 + (b % 3) * 1024 * kTallWaves + 1024 * (threadIdx.x >> 6));
+  };
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
-  const bool full = static_cast<int64_t>(blockIdx.x) * 16 * kTallWaves + 16 * kTallWaves <= m && n == 16 * NB;
+  const int64_t row = (blk0 + blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
+  constexpr bool full = FULL;
   // X row of this lane at columns 16 b + 4 lg + v: the layout of the solved
-  // values.  Loads clamp row and column (rows past m are never stored;
+  // values.  Subpanel b is loaded with the staging of its panel, two
+  // subpanels ahead, so the loads overlap the earlier subpanels.  Whole
+  // tiles stage it in LDS by one direct load per wave: lane L = 16 v + 4 g
+  // + q brings rows 4q..4q+3 of column 16 b + 4 g + v, so that the reads
+  // (float 64 v + 16 lg + l16) fall in distinct banks.  Ragged tiles load
+  // registers, clamping row and column (rows past m are never stored;
   // columns past n meet zero panel entries).
   float xd[NB][4];
   const float* xrow = X + (row < m ? row : m - 1);
-  if (full) {
-    const float* xb = xrow + static_cast<int64_t>(4 * lg) * ldx;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) xd[b][v] = xb[static_cast<int64_t>(16 * b + v) * ldx];
-  } else {
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
+  const float* xtile = X + (row - l16) + 4 * (lane & 3) +
+                       static_cast<int64_t>(4 * ((lane >> 2) & 3) + (lane >> 4)) * ldx;
+  auto load_x = [&](int b) {
+    if (full) {
+      dma16(xtile + static_cast<int64_t>(16 * b) * ldx, xslot(b));
+    } else {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = 16 * b + 4 * lg + v;
         xd[b][v] = xrow[static_cast<int64_t>(col < n ? col : n - 1) * ldx];
       }
-  }
+    }
+  };
   u4b_t qb[NCH][3];
   auto stage = [&](int b) {
     dma_panel(pan3 + trsm_bf3_panel_offset(b), trsm_bf3_psize(b), ring + SLOT * (b % 3), ring + 3 * SLOT,
@@ -578,26 +614,38 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
     return __builtin_bit_cast(s4b_t, u);
   };
   stage(0);
-  if (NB > 1) stage(1);
+  load_x(0);
+  if (NB > 1) {
+    stage(1);
+    load_x(1);
+  }
   static_for<NB>([&](auto bc) {
     constexpr int b = decltype(bc)::value;
-    // Panel b has landed once the memory operations issued after its
-    // staging are all that remain: panel b+1's staging and the 4 stores of
-    // each of the previous two subpanels (whole-workgroup tiles only; a
-    // ragged tile may skip stores and waits for everything).
+    // Subpanel b's panel and X values have landed once the memory
+    // operations issued after them are all that remain: 4 stores per
+    // earlier subpanel and 4 loads plus the staging per later one, in issue
+    // order (whole-workgroup tiles only; a ragged tile may skip stores and
+    // waits for everything).
     if (full) {
-      constexpr int later = (b == 0) ? (NB > 1 ? dma_per_wave(trsm_bf3_psize(1)) : 0)
-                          : (b == 1) ? (NB > 2 ? dma_per_wave(trsm_bf3_psize(2)) : 0) + 4
-                                     : 8 + (b + 1 < NB ? dma_per_wave(trsm_bf3_psize(b + 1)) : 0);
+      constexpr int d1 = (b + 1 < NB) ? dma_per_wave(trsm_bf3_psize(b + 1)) + 1 : 0;
+      constexpr int later = (b == 0) ? d1 : (b == 1) ? d1 + 4 : d1 + 8;
       wait_vmcnt<later>();
     } else {
       wait_vmcnt<0>();
     }
     wg_barrier();
-    if (b + 2 < NB) stage(b + 2);
+    if (b + 2 < NB) {
+      stage(b + 2);
+      load_x(b + 2);
+    }
     const int nc = (b + 1) / 2;
     const unsigned char* slot = ring + SLOT * (b % 3);
     const u4b_t* pa = reinterpret_cast<const u4b_t*>(slot) + lane;
+    if (full) {
+      const float* xl = xslot(b) + 16 * lg + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xd[b][v] = xl[64 * v];
+    }
     f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
     if (nc > 0) {
       // One chain per chunk, each from zero; products grouped by R plane:
@@ -676,13 +724,23 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32) {
     // pan holds bf16 x 3 subpanels (make_trsm_bf3_panels_kernel)
-    const unsigned grid = static_cast<unsigned>(ceil_div(m, 16 * kTallWaves));
+    // Whole tiles on the unchecked instance (which stages X by 16-byte
+    // direct loads: X 16-byte aligned, ldx a multiple of 4), the ragged rest
+    // (or every tile, when n is not a multiple of 16) on the checked one.
+    const int64_t tiles = ceil_div(m, 16 * kTallWaves);
+    const bool aligned = (ldx % 4) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+    const int64_t nfull = (n % 16 == 0 && aligned) ? m / (16 * kTallWaves) : 0;
     const float* x = static_cast<const float*>(X);
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
-#define RCQ_S3_CASE(NBV)                                                                \
-  case NBV:                                                                             \
-    trsm_bf3_kernel<NBV><<<grid, 64 * kTallWaves, 0, st>>>(x, m, n, ldx, p3, q, ldq);   \
+#define RCQ_S3_CASE(NBV)                                                                   \
+  case NBV:                                                                                \
+    if (nfull > 0)                                                                         \
+      trsm_bf3_kernel<NBV, true><<<static_cast<unsigned>(nfull), 64 * kTallWaves, 0, st>>>( \
+          x, m, n, ldx, p3, q, ldq, 0);                                                    \
+    if (tiles > nfull)                                                                     \
+      trsm_bf3_kernel<NBV, false><<<static_cast<unsigned>(tiles - nfull), 64 * kTallWaves, \
+                                    0, st>>>(x, m, n, ldx, p3, q, ldq, nfull);             \
     break;
     switch (nb) {
       RCQ_S3_CASE(1) RCQ_S3_CASE(2) RCQ_S3_CASE(3) RCQ_S3_CASE(4) RCQ_S3_CASE(5) RCQ_S3_CASE(6)
@@ -721,12 +779,22 @@ hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const v
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32) {
     // pan holds bf16 x 3 panels (make_bf3_panels)
-    const unsigned grid = static_cast<unsigned>(ceil_div(m, 16 * kTallWaves));
+    // Whole tiles on the unchecked instance (n a multiple of 32; Q staged by
+    // 16-byte direct loads: 16-byte aligned, ldq a multiple of 4), the rest
+    // on the checked one.
+    const int64_t tiles = ceil_div(m, 16 * kTallWaves);
+    const bool aligned = (ldq % 4) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+    const int64_t nfull = (n % 32 == 0 && aligned) ? m / (16 * kTallWaves) : 0;
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
-#define RCQ_T3_CASE(NBV)                                                           \
-  case NBV:                                                                        \
-    trmm_bf3_kernel<NBV><<<grid, 64 * kTallWaves, 0, st>>>(q, m, n, ldq, p3);      \
+#define RCQ_T3_CASE(NBV)                                                                   \
+  case NBV:                                                                                \
+    if (nfull > 0)                                                                         \
+      trmm_bf3_kernel<NBV, true><<<static_cast<unsigned>(nfull), 64 * kTallWaves, 0, st>>>( \
+          q, m, n, ldq, p3, 0);                                                            \
+    if (tiles > nfull)                                                                     \
+      trmm_bf3_kernel<NBV, false><<<static_cast<unsigned>(tiles - nfull), 64 * kTallWaves, \
+                                    0, st>>>(q, m, n, ldq, p3, nfull);                     \
     break;
     switch (nb) {
       RCQ_T3_CASE(1) RCQ_T3_CASE(2) RCQ_T3_CASE(3) RCQ_T3_CASE(4) RCQ_T3_CASE(5) RCQ_T3_CASE(6)

@@ -117,6 +117,33 @@ def test_trsm_in_place_f32(rq, orc):
     assert np.linalg.norm(Qn - Qr) <= 8 * U32 * n * np.linalg.cond(R) * np.linalg.norm(Qr)
 
 
+@pytest.mark.parametrize("m,n", [(128 * 40 + 37, 96), (128 * 24, 256)])
+def test_trsm_f32_whole_tiles(rq, orc, m, n):
+    """FP32 solve with whole 128-row tiles (staged through LDS) and a ragged
+    tail; a padded leading dimension, a misaligned copy (checked kernel) and
+    the in-place call give the same bits."""
+    import torch
+    rng = np.random.default_rng(m)
+    X = np.asfortranarray(rng.standard_normal((m, n))).astype(np.float32)
+    R = np.triu(rng.standard_normal((n, n))) + 8 * np.eye(n)
+    Xg = _gpu(X)
+    Rg = _gpu(R)
+    Q = rq.trsm(Xg, Rg)
+    Qr = orc.trsm_rows(X.astype(np.float64), R)
+    Qn = _np(Q).astype(np.float64)
+    assert np.linalg.norm(Qn - Qr) <= 8 * U32 * n * np.linalg.cond(R) * np.linalg.norm(Qr)
+    pad = torch.empty((n, m + 4), dtype=torch.float32, device="cuda")[:, :m].t()
+    pad.copy_(Xg)
+    mis = torch.empty(m * n + 1, dtype=torch.float32, device="cuda")[1:].view(n, m).t()
+    mis.copy_(Xg)
+    assert mis.data_ptr() % 16 != 0
+    Xi = Xg.clone()
+    rq.trsm(Xi, Rg, Q=Xi)
+    for other in (rq.trsm(pad, Rg), rq.trsm(mis, Rg), Xi):
+        torch.cuda.synchronize()
+        assert torch.equal(other, Q)
+
+
 # ----------------------------------------------------------------------------- factor
 def test_config_a_one_pass_parity(rq, orc):
     """m=10000, n=50, k=150, sigma 1 -> 1e-8, Gaussian, FP64, one pass."""
