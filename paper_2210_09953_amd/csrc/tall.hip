@@ -338,6 +338,20 @@ __device__ __forceinline__ void dma_panel(const unsigned char* __restrict__ src,
   }
 }
 
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cus[dev] = c;
+  }
+  return cus[dev];
+}
+
 // One 16-byte direct global -> LDS load per lane: lane L's bytes land at
 // slot + 16 L.
 __device__ __forceinline__ void dma16(const void* src, void* slot) {
@@ -391,7 +405,7 @@ __host__ __device__ constexpr int bf3_panel_offset(int b) {
 // Bytes of panel b of T (chunks 0..b/2 of 3 KiB).
 __host__ __device__ constexpr int trmm_bf3_psize(int b) { return (b / 2 + 1) * 3072; }
 
-// FULL and blk0 as for trsm_bf3_kernel (n = 32 NCH when FULL).
+// FULL, persistence and blk0 as for trsm_bf3_kernel (FULL: n = 32 NCH).
 template <int NB, bool FULL>
 __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int64_t m, int n, int64_t ldq,
                                                        const unsigned char* __restrict__ pan3,
@@ -399,47 +413,57 @@ __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = NCH * 3072;
   constexpr int SLOT = dma_kib(PMAX) * 1024;
-  // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
-  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024 + (FULL ? 2 * 2048 * kTallWaves : 0)];
-  auto xslot = [&](int ch) -> float* {
-    return reinterpret_cast<float*>(ring + 3 * SLOT + 1024 + (ch % 2) * 2048 * kTallWaves + 2048 * (threadIdx.x >> 6));
+  constexpr bool persist = FULL && NB % 4 == 0;
+  constexpr int NSL = persist ? 4 : 3;
+  constexpr int64_t kTile = 16 * kTallWaves;
+  // NSL panel slots (panel b in slot b % NSL, staged two panels ahead), a
+  // sink, and (whole tiles) two chunk slots of 2 KiB per wave
+  __shared__ __align__(1024) unsigned char ring[NSL * SLOT + 1024 + (FULL ? 2 * 2048 * kTallWaves : 0)];
+  auto xslot = [&](int sl) -> float* {
+    return reinterpret_cast<float*>(ring + NSL * SLOT + 1024 + sl * 2048 * kTallWaves +
+                                    2048 * (threadIdx.x >> 6));
   };
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = (blk0 + blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
+  const int64_t ntiles = persist ? m / kTile : 0;
+  int64_t tile = blk0 + blockIdx.x;
   // Q1 row l16 of this wave, columns 32 ch + 8 lg + e.  Chunk ch is loaded
   // with the staging of output panel 2 ch, the first that needs it (two
   // panels ahead), and split into its three bf16 planes just before that
-  // panel; the loads overlap the earlier panels.  Loads clamp the row and
-  // column (no branches): rows past m are never stored, and columns past n
-  // meet zero rows of T.  In place: panel b overwrites columns 16b..16b+15
-  // of rows that this lane has already loaded.
+  // panel; the loads overlap the earlier panels.  Ragged tiles load
+  // registers, clamping the row and column: rows past m are never stored,
+  // and columns past n meet zero rows of T.  In place: panel b overwrites
+  // columns 16b..16b+15 of rows that this lane has already loaded.
   float xq[NCH][8];
   constexpr bool full = FULL;
-  const float* qrow = Q + (row < m ? row : m - 1);
+  // Strides and the panel base laundered per tile (as in trsm_bf3_kernel).
+  int64_t ldqv = ldq;
+  const unsigned char* panv = pan3;
   // Whole tiles stage chunk ch in LDS by two direct loads per wave: load i,
   // lane L = 16 e' + 4 g + q brings rows 4q..4q+3 of column 32 ch + 8 g +
   // 4 i + e', so that the reads of element e (float 256 (e / 4) + 64 (e % 4)
   // + 16 lg + l16) fall in distinct banks.
-  const float* qtile = Q + (row - l16) + 4 * (lane & 3) +
-                       static_cast<int64_t>(8 * ((lane >> 2) & 3) + (lane >> 4)) * ldq;
-  auto load_chunk = [&](int ch) {
+  const int qcol = 8 * ((lane >> 2) & 3) + (lane >> 4);
+  auto load_chunk = [&](int64_t t, int ch) {
     if (full) {
+      const float* qt = Q + t * kTile + wave * 16 + 4 * (lane & 3);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        dma16(qtile + static_cast<int64_t>(32 * ch + 4 * i) * ldq, xslot(ch) + 256 * i);
+        dma16(qt + static_cast<int64_t>(32 * ch + 4 * i + qcol) * ldqv, xslot(ch % 2) + 256 * i);
     } else {
+      const int64_t r = t * kTile + wave * 16 + l16;
+      const float* qrow = Q + (r < m ? r : m - 1);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int col = 32 * ch + 8 * lg + e;
-        xq[ch][e] = qrow[static_cast<int64_t>(col < n ? col : n - 1) * ldq];
+        xq[ch][e] = qrow[static_cast<int64_t>(col < n ? col : n - 1) * ldqv];
       }
     }
   };
   u4b_t qb[NCH][3];
   auto split_chunk = [&](int ch) {
     if (full) {
-      const float* xl = xslot(ch) + 16 * lg + l16;
+      const float* xl = xslot(ch % 2) + 16 * lg + l16;
 #pragma unroll
       for (int e = 0; e < 8; ++e) xq[ch][e] = xl[256 * (e / 4) + 64 * (e % 4)];
     }
@@ -453,79 +477,103 @@ __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int
       qb[ch][2][w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
     }
   };
-  auto stage = [&](int b) {
-    dma_panel(pan3 + bf3_panel_offset(b), trmm_bf3_psize(b), ring + SLOT * (b % 3), ring + 3 * SLOT, wave,
-              lane);
+  auto stage = [&](int b, int sl) {
+    dma_panel(panv + bf3_panel_offset(b), trmm_bf3_psize(b), ring + SLOT * sl, ring + NSL * SLOT,
+              wave, lane);
   };
-  stage(0);
-  load_chunk(0);
-  if (NB > 1) stage(1);
-  static_for<NB>([&](auto bc) {
-    constexpr int b = decltype(bc)::value;
-    // Panel b (and, for even b, chunk b/2) has landed once the memory
-    // operations issued after them are all that remain: 4 stores per
-    // earlier panel, and per later panel its staging plus, for even panels,
-    // the 2 loads of its chunk (see trsm_bf3_kernel).
-    if (full) {
-      constexpr int d1 = (b + 1 < NB) ? dma_per_wave(trmm_bf3_psize(b + 1)) +
-                                            (((b + 1) % 2 == 0) ? 2 : 0)
-                                      : 0;
-      constexpr int later = (b == 0) ? d1 : (b == 1) ? d1 + 4 : d1 + 8;
-      wait_vmcnt<later>();
-    } else {
-      wait_vmcnt<0>();
-    }
-    wg_barrier();
-    if (b + 2 < NB) {
-      stage(b + 2);
-      if ((b & 1) == 0) load_chunk(b / 2 + 1);
-    }
-    if ((b & 1) == 0) split_chunk(b / 2);
-    const u4b_t* pa = reinterpret_cast<const u4b_t*>(ring + SLOT * (b % 3)) + lane;
-    // One chain per chunk (independent, so the matrix cores pipeline them),
-    // each from zero; products grouped by T plane: d with d, h; l with h;
-    // h with l, d, h.
-    f4 c4[NCH];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) c4[ch] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int tp = 1; tp < 4; ++tp) {
-      const int tpl = tp % 3;  // planes in the order d, l, h
-      bf8 tv[NCH];
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch)
-        if (ch <= b / 2) tv[ch] = __builtin_bit_cast(bf8, pa[(3 * ch + tpl) * 64]);
-      const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
-#pragma unroll
-      for (int iq = 0; iq < 3; ++iq)
-        if (iq < nq) {
-          // d: (d, h)->planes 1, 0;  l: plane 0;  h: planes 2, 1, 0
-          const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
-#pragma unroll
-          for (int ch = 0; ch < NCH; ++ch)
-            if (ch <= b / 2)
-              c4[ch] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  tv[ch], __builtin_bit_cast(bf8, qb[ch][qp]), c4[ch], 0, 0, 0);
+  stage(0, 0);
+  load_chunk(tile, 0);
+  if (NB > 1) stage(1, 1);
+  bool first = true;
+  while (true) {
+    asm volatile("" : "+s"(ldqv), "+s"(panv));
+    const int64_t row = tile * kTile + wave * 16 + l16;
+    const int64_t next = tile + gridDim.x;
+    const bool has_next = persist && next < ntiles;
+    static_for<NB>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      // Panel b (and, for even b, chunk b/2) has landed once the memory
+      // operations issued after them are all that remain: 4 stores per
+      // earlier panel, and per later panel its staging plus, for even
+      // panels, the 2 loads of its chunk (see trsm_bf3_kernel).
+      if (full) {
+        constexpr bool staged = (b + 1 < NB) || persist;  // at panel b - 1
+        constexpr int d1 = staged ? dma_per_wave(trmm_bf3_psize((b + 1) % NB)) +
+                                        (((b + 1) % 2 == 0) ? 2 : 0)
+                                  : 0;
+        if (b >= 2) {
+          wait_vmcnt<d1 + 8>();
+        } else if (first) {
+          wait_vmcnt<(b == 0) ? d1 : d1 + 4>();
+        } else {
+          wait_vmcnt<d1 + 8>();
         }
-    }
-    f4 D = c4[0];
-#pragma unroll
-    for (int ch = 1; ch < NCH; ++ch)
-      if (ch <= b / 2) D += c4[ch];
-    float* qout = Q + row;
-    if (full) {
-      float* qo = qout + static_cast<int64_t>(drow<float>(lg, 0)) * ldq;
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        qo[static_cast<int64_t>(16 * b + drow<float>(lg, v) - drow<float>(lg, 0)) * ldq] = D[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = 16 * b + drow<float>(lg, v);
-        if (row < m && col < n) qout[static_cast<int64_t>(col) * ldq] = D[v];
+      } else {
+        wait_vmcnt<0>();
       }
-    }
-  });
+      wg_barrier();
+      if (b + 2 < NB) {
+        stage(b + 2, (b + 2) % NSL);
+        if ((b & 1) == 0) load_chunk(tile, b / 2 + 1);
+      } else if (persist) {
+        stage(b + 2 - NB, (b + 2) % NSL);
+        if ((b & 1) == 0) load_chunk(has_next ? next : tile, 0);
+      }
+      // Every staging load of this panel precedes its stores (wait counts).
+      asm volatile("" ::: "memory");
+      if ((b & 1) == 0) split_chunk(b / 2);
+      const u4b_t* pa = reinterpret_cast<const u4b_t*>(ring + SLOT * (b % NSL)) + lane;
+      // One chain per chunk (independent, so the matrix cores pipeline them),
+      // each from zero; products grouped by T plane: d with d, h; l with h;
+      // h with l, d, h.
+      f4 c4[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) c4[ch] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int tp = 1; tp < 4; ++tp) {
+        const int tpl = tp % 3;  // planes in the order d, l, h
+        bf8 tv[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+          if (ch <= b / 2) tv[ch] = __builtin_bit_cast(bf8, pa[(3 * ch + tpl) * 64]);
+        const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
+#pragma unroll
+        for (int iq = 0; iq < 3; ++iq)
+          if (iq < nq) {
+            // d: (d, h)->planes 1, 0;  l: plane 0;  h: planes 2, 1, 0
+            const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+              if (ch <= b / 2)
+                c4[ch] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    tv[ch], __builtin_bit_cast(bf8, qb[ch][qp]), c4[ch], 0, 0, 0);
+          }
+      }
+      f4 D = c4[0];
+#pragma unroll
+      for (int ch = 1; ch < NCH; ++ch)
+        if (ch <= b / 2) D += c4[ch];
+      float* qout = Q + row;
+      if (full) {
+        float* qo = qout + static_cast<int64_t>(drow<float>(lg, 0)) * ldqv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          qo[static_cast<int64_t>(16 * b + drow<float>(lg, v) - drow<float>(lg, 0)) * ldqv] = D[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * b + drow<float>(lg, v);
+          if (row < m && col < n) qout[static_cast<int64_t>(col) * ldqv] = D[v];
+        }
+      }
+    });
+    if (!has_next) break;
+    tile = next;
+    first = false;
+  }
+  // The last tile's two extra stagings must land before the workgroup's LDS
+  // is released.
+  if (persist) wait_vmcnt<0>();
 }
 
 // ----------------------------------------------------------------------------
@@ -549,9 +597,13 @@ typedef short s4b_t __attribute__((ext_vector_type(4)));
 // Bytes of subpanel b of the solve's panels ((b+1)/2 chunks, diagonal inverse).
 __host__ __device__ constexpr int trsm_bf3_psize(int b) { return ((b + 1) / 2) * 3072 + 1536; }
 
-// FULL: every workgroup covers 16 kTallWaves rows below m and n = 16 NB (no
-// bounds checks, so the wait counts are exact); otherwise rows and columns
-// are checked.  Workgroup i covers the tile blk0 + i.
+// FULL: whole tiles of 16 kTallWaves rows below m, n = 16 NB, NB >= 4 (no
+// bounds checks, so the wait counts are exact).  When NB % 4 == 0 the panel
+// ring has four slots, a tile's panels fill whole ring cycles, and each
+// workgroup loops over tiles blockIdx.x, + gridDim.x, ...: the next tile's
+// first two panels (and X subpanels) are staged during the last two of the
+// current one.  Otherwise a workgroup solves tile blk0 + blockIdx.x, with
+// bounds checks unless FULL.
 template <int NB, bool FULL>
 __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* X, int64_t m, int n,
                                                        int64_t ldx,
@@ -560,14 +612,20 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = (NB / 2) * 3072 + 1536;
   constexpr int SLOT = dma_kib(PMAX) * 1024;
-  // three panel slots (panel b in slot b % 3, staged two panels ahead) and a sink
-  __shared__ __align__(1024) unsigned char ring[3 * SLOT + 1024 + (FULL ? 3 * 1024 * kTallWaves : 0)];
-  auto xslot = [&](int b) -> float* {
-    return reinterpret_cast<float*>(ring + 3 * SLOT + 1024 + (b % 3) * 1024 * kTallWaves + 1024 * (threadIdx.x >> 6));
+  constexpr bool persist = FULL && NB % 4 == 0;
+  constexpr int NSL = persist ? 4 : 3;
+  constexpr int64_t kTile = 16 * kTallWaves;
+  // NSL panel slots (panel b in slot b % NSL, staged two panels ahead), a
+  // sink, and (whole tiles) NSL X slots of 1 KiB per wave
+  __shared__ __align__(1024) unsigned char ring[NSL * SLOT + 1024 + (FULL ? NSL * 1024 * kTallWaves : 0)];
+  auto xslot = [&](int sl) -> float* {
+    return reinterpret_cast<float*>(ring + NSL * SLOT + 1024 + sl * 1024 * kTallWaves +
+                                    1024 * (threadIdx.x >> 6));
   };
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int64_t row = (blk0 + blockIdx.x) * 16 * kTallWaves + wave * 16 + l16;
+  const int64_t ntiles = persist ? m / kTile : 0;
+  int64_t tile = blk0 + blockIdx.x;
   constexpr bool full = FULL;
   // X row of this lane at columns 16 b + 4 lg + v: the layout of the solved
   // values.  Subpanel b is loaded with the staging of its panel, two
@@ -578,24 +636,30 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
   // registers, clamping row and column (rows past m are never stored;
   // columns past n meet zero panel entries).
   float xd[NB][4];
-  const float* xrow = X + (row < m ? row : m - 1);
-  const float* xtile = X + (row - l16) + 4 * (lane & 3) +
-                       static_cast<int64_t>(4 * ((lane >> 2) & 3) + (lane >> 4)) * ldx;
-  auto load_x = [&](int b) {
+  // Strides and the panel base as loop-carried copies: laundered at the top
+  // of every tile, so that the compiler recomputes the per-panel offsets
+  // instead of holding all of them in registers across the tile loop.
+  int64_t ldxv = ldx, ldqv = ldq;
+  const unsigned char* panv = pan3;
+  const int xcol = 4 * ((lane >> 2) & 3) + (lane >> 4);
+  auto load_x = [&](int64_t t, int b, int sl) {
     if (full) {
-      dma16(xtile + static_cast<int64_t>(16 * b) * ldx, xslot(b));
+      dma16(X + t * kTile + wave * 16 + 4 * (lane & 3) + static_cast<int64_t>(16 * b + xcol) * ldxv,
+            xslot(sl));
     } else {
+      const int64_t r = t * kTile + wave * 16 + l16;
+      const float* xrow = X + (r < m ? r : m - 1);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = 16 * b + 4 * lg + v;
-        xd[b][v] = xrow[static_cast<int64_t>(col < n ? col : n - 1) * ldx];
+        xd[b][v] = xrow[static_cast<int64_t>(col < n ? col : n - 1) * ldxv];
       }
     }
   };
   u4b_t qb[NCH][3];
-  auto stage = [&](int b) {
-    dma_panel(pan3 + trsm_bf3_panel_offset(b), trsm_bf3_psize(b), ring + SLOT * (b % 3), ring + 3 * SLOT,
-              wave, lane);
+  auto stage = [&](int b, int sl) {
+    dma_panel(panv + trsm_bf3_panel_offset(b), trsm_bf3_psize(b), ring + SLOT * sl,
+              ring + NSL * SLOT, wave, lane);
   };
   // bf16 planes of four FP32 values, two per 32-bit word (element 0 low).
   auto split4 = [](const f4& x, uint32_t (&h)[2], uint32_t (&d)[2], uint32_t (&l)[2]) {
@@ -613,109 +677,136 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
     const uint2 u = make_uint2(w[0], w[1]);
     return __builtin_bit_cast(s4b_t, u);
   };
-  stage(0);
-  load_x(0);
+  stage(0, 0);
+  load_x(tile, 0, 0);
   if (NB > 1) {
-    stage(1);
-    load_x(1);
+    stage(1, 1);
+    load_x(tile, 1, 1);
   }
-  static_for<NB>([&](auto bc) {
-    constexpr int b = decltype(bc)::value;
-    // Subpanel b's panel and X values have landed once the memory
-    // operations issued after them are all that remain: 4 stores per
-    // earlier subpanel and 4 loads plus the staging per later one, in issue
-    // order (whole-workgroup tiles only; a ragged tile may skip stores and
-    // waits for everything).
-    if (full) {
-      constexpr int d1 = (b + 1 < NB) ? dma_per_wave(trsm_bf3_psize(b + 1)) + 1 : 0;
-      constexpr int later = (b == 0) ? d1 : (b == 1) ? d1 + 4 : d1 + 8;
-      wait_vmcnt<later>();
-    } else {
-      wait_vmcnt<0>();
-    }
-    wg_barrier();
-    if (b + 2 < NB) {
-      stage(b + 2);
-      load_x(b + 2);
-    }
-    const int nc = (b + 1) / 2;
-    const unsigned char* slot = ring + SLOT * (b % 3);
-    const u4b_t* pa = reinterpret_cast<const u4b_t*>(slot) + lane;
-    if (full) {
-      const float* xl = xslot(b) + 16 * lg + l16;
+  bool first = true;
+  while (true) {
+    asm volatile("" : "+s"(ldxv), "+s"(ldqv), "+s"(panv));
+    const int64_t row = tile * kTile + wave * 16 + l16;
+    const int64_t next = tile + gridDim.x;
+    const bool has_next = persist && next < ntiles;
+    static_for<NB>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      // Subpanel b's panel and X values have landed once the memory
+      // operations issued after them are all that remain, in issue order:
+      // 4 stores per earlier subpanel, and per later one its staging and
+      // one X load (whole tiles only; a ragged tile may skip stores and
+      // waits for everything).  Persistent workgroups stage two panels
+      // past the end of every tile (the next tile's first two, or a
+      // harmless repeat of this tile's on the last one).
+      if (full) {
+        constexpr bool staged = (b + 1 < NB) || persist;  // at subpanel b - 1
+        constexpr int d1 = staged ? dma_per_wave(trsm_bf3_psize((b + 1) % NB)) + 1 : 0;
+        if (b >= 2) {
+          wait_vmcnt<d1 + 8>();
+        } else if (first) {
+          wait_vmcnt<(b == 0) ? d1 : d1 + 4>();
+        } else {
+          wait_vmcnt<d1 + 8>();
+        }
+      } else {
+        wait_vmcnt<0>();
+      }
+      wg_barrier();
+      if (b + 2 < NB) {
+        stage(b + 2, (b + 2) % NSL);
+        load_x(tile, b + 2, (b + 2) % NSL);
+      } else if (persist) {
+        stage(b + 2 - NB, (b + 2) % NSL);
+        load_x(has_next ? next : tile, b + 2 - NB, (b + 2) % NSL);
+      }
+      // The wait counts take every staging load of this subpanel to precede
+      // its stores: keep the compiler from interleaving them.
+      asm volatile("" ::: "memory");
+      const int nc = (b + 1) / 2;
+      const unsigned char* slot = ring + SLOT * (b % NSL);
+      const u4b_t* pa = reinterpret_cast<const u4b_t*>(slot) + lane;
+      if (full) {
+        const float* xl = xslot(b % NSL) + 16 * lg + l16;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xd[b][v] = xl[64 * v];
-    }
-    f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
-    if (nc > 0) {
-      // One chain per chunk, each from zero; products grouped by R plane:
-      // d with d, h; l with h; h with l, d, h.
-      f4 c4[NCH];
+        for (int v = 0; v < 4; ++v) xd[b][v] = xl[64 * v];
+      }
+      f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
+      if (nc > 0) {
+        // One chain per chunk, each from zero; products grouped by R plane:
+        // d with d, h; l with h; h with l, d, h.
+        f4 c4[NCH];
 #pragma unroll
-      for (int p = 0; p < NCH; ++p) c4[p] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p < NCH; ++p) c4[p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int tp = 1; tp < 4; ++tp) {
-        const int tpl = tp % 3;  // planes in the order d, l, h
-        bf8 tv[NCH];
+        for (int tp = 1; tp < 4; ++tp) {
+          const int tpl = tp % 3;  // planes in the order d, l, h
+          bf8 tv[NCH];
+#pragma unroll
+          for (int p = 0; p < NCH; ++p)
+            if (p < nc) tv[p] = __builtin_bit_cast(bf8, pa[(3 * p + tpl) * 64]);
+          const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
+#pragma unroll
+          for (int iq = 0; iq < 3; ++iq)
+            if (iq < nq) {
+              const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
+#pragma unroll
+              for (int p = 0; p < NCH; ++p)
+                if (p < nc)
+                  c4[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                      tv[p], __builtin_bit_cast(bf8, qb[p][qp]), c4[p], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int p = 0; p < NCH; ++p)
-          if (p < nc) tv[p] = __builtin_bit_cast(bf8, pa[(3 * p + tpl) * 64]);
-        const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
-#pragma unroll
-        for (int iq = 0; iq < 3; ++iq)
-          if (iq < nq) {
-            const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
-#pragma unroll
-            for (int p = 0; p < NCH; ++p)
-              if (p < nc)
-                c4[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    tv[p], __builtin_bit_cast(bf8, qb[p][qp]), c4[p], 0, 0, 0);
-          }
+          if (p < nc) D += c4[p];
       }
+      // Diagonal block: Q_b = Tb^T D on 16x16x16 matrix cores; D as returned
+      // is the B operand (K = 4 lg + v).
+      uint32_t dh[2], dd[2], dl[2];
+      split4(D, dh, dd, dl);
+      const uint2* pd = reinterpret_cast<const uint2*>(slot + 3072 * nc) + lane;
+      const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
+      const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
+      const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
+      f4 E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(tl, as_s4(dh), E, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dl), E, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
+      float* qout = Q + row;
+      if (full) {
+        float* qo = qout + static_cast<int64_t>(4 * lg) * ldqv;
 #pragma unroll
-      for (int p = 0; p < NCH; ++p)
-        if (p < nc) D += c4[p];
-    }
-    // Diagonal block: Q_b = Tb^T D on 16x16x16 matrix cores; D as returned
-    // is the B operand (K = 4 lg + v).
-    uint32_t dh[2], dd[2], dl[2];
-    split4(D, dh, dd, dl);
-    const uint2* pd = reinterpret_cast<const uint2*>(slot + 3072 * nc) + lane;
-    const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
-    const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
-    const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
-    f4 E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(tl, as_s4(dh), E, 0, 0, 0);
-    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dl), E, 0, 0, 0);
-    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
-    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
-    E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
-    float* qout = Q + row;
-    if (full) {
-      float* qo = qout + static_cast<int64_t>(4 * lg) * ldq;
+        for (int v = 0; v < 4; ++v) qo[static_cast<int64_t>(16 * b + v) * ldqv] = E[v];
+      } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qo[static_cast<int64_t>(16 * b + v) * ldq] = E[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = 16 * b + 4 * lg + v;
-        if (row < m && col < n) qout[static_cast<int64_t>(col) * ldq] = E[v];
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * b + 4 * lg + v;
+          if (row < m && col < n) qout[static_cast<int64_t>(col) * ldqv] = E[v];
+        }
       }
-    }
-    // Keep Q_b split for the later updates: words 0-1 of chunk b/2 for even
-    // b (words 2-3 zero until b + 1 is solved), words 2-3 for odd b.
-    uint32_t eh[2], ed[2], el[2];
-    split4(E, eh, ed, el);
-    if ((b & 1) == 0) {
-      qb[b / 2][0] = u4b_t{eh[0], eh[1], 0u, 0u};
-      qb[b / 2][1] = u4b_t{ed[0], ed[1], 0u, 0u};
-      qb[b / 2][2] = u4b_t{el[0], el[1], 0u, 0u};
-    } else {
-      qb[b / 2][0][2] = eh[0]; qb[b / 2][0][3] = eh[1];
-      qb[b / 2][1][2] = ed[0]; qb[b / 2][1][3] = ed[1];
-      qb[b / 2][2][2] = el[0]; qb[b / 2][2][3] = el[1];
-    }
-  });
+      // Keep Q_b split for the later updates: words 0-1 of chunk b/2 for even
+      // b (words 2-3 zero until b + 1 is solved), words 2-3 for odd b.
+      uint32_t eh[2], ed[2], el[2];
+      split4(E, eh, ed, el);
+      if ((b & 1) == 0) {
+        qb[b / 2][0] = u4b_t{eh[0], eh[1], 0u, 0u};
+        qb[b / 2][1] = u4b_t{ed[0], ed[1], 0u, 0u};
+        qb[b / 2][2] = u4b_t{el[0], el[1], 0u, 0u};
+      } else {
+        qb[b / 2][0][2] = eh[0]; qb[b / 2][0][3] = eh[1];
+        qb[b / 2][1][2] = ed[0]; qb[b / 2][1][3] = ed[1];
+        qb[b / 2][2][2] = el[0]; qb[b / 2][2][3] = el[1];
+      }
+    });
+    if (!has_next) break;
+    tile = next;
+    first = false;
+  }
+  // The last tile's two extra stagings must land before the workgroup's LDS
+  // is released.
+  if (persist) wait_vmcnt<0>();
 }
 
 hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
@@ -727,16 +818,19 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
     // Whole tiles on the unchecked instance (which stages X by 16-byte
     // direct loads: X 16-byte aligned, ldx a multiple of 4), the ragged rest
     // (or every tile, when n is not a multiple of 16) on the checked one.
+    // With nb % 4 == 0 the whole tiles are shared out to one persistent
+    // workgroup per compute unit.
     const int64_t tiles = ceil_div(m, 16 * kTallWaves);
     const bool aligned = (ldx % 4) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
-    const int64_t nfull = (n % 16 == 0 && aligned) ? m / (16 * kTallWaves) : 0;
+    const int64_t nfull = (n % 16 == 0 && nb >= 4 && aligned) ? m / (16 * kTallWaves) : 0;
+    const int64_t gfull = (nb % 4 == 0) ? std::min<int64_t>(nfull, device_cus()) : nfull;
     const float* x = static_cast<const float*>(X);
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
 #define RCQ_S3_CASE(NBV)                                                                   \
   case NBV:                                                                                \
     if (nfull > 0)                                                                         \
-      trsm_bf3_kernel<NBV, true><<<static_cast<unsigned>(nfull), 64 * kTallWaves, 0, st>>>( \
+      trsm_bf3_kernel<NBV, true><<<static_cast<unsigned>(gfull), 64 * kTallWaves, 0, st>>>( \
           x, m, n, ldx, p3, q, ldq, 0);                                                    \
     if (tiles > nfull)                                                                     \
       trsm_bf3_kernel<NBV, false><<<static_cast<unsigned>(tiles - nfull), 64 * kTallWaves, \
@@ -779,18 +873,20 @@ hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const v
   const int nb = static_cast<int>(ceil_div(n, 16));
   if (f32) {
     // pan holds bf16 x 3 panels (make_bf3_panels)
-    // Whole tiles on the unchecked instance (n a multiple of 32; Q staged by
-    // 16-byte direct loads: 16-byte aligned, ldq a multiple of 4), the rest
+    // Whole tiles on the unchecked instance (n a multiple of 32, n >= 64; Q
+    // staged by 16-byte direct loads: 16-byte aligned, ldq a multiple of 4;
+    // one persistent workgroup per compute unit when nb % 4 == 0), the rest
     // on the checked one.
     const int64_t tiles = ceil_div(m, 16 * kTallWaves);
     const bool aligned = (ldq % 4) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
-    const int64_t nfull = (n % 32 == 0 && aligned) ? m / (16 * kTallWaves) : 0;
+    const int64_t nfull = (n % 32 == 0 && nb >= 4 && aligned) ? m / (16 * kTallWaves) : 0;
+    const int64_t gfull = (nb % 4 == 0) ? std::min<int64_t>(nfull, device_cus()) : nfull;
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
 #define RCQ_T3_CASE(NBV)                                                                   \
   case NBV:                                                                                \
     if (nfull > 0)                                                                         \
-      trmm_bf3_kernel<NBV, true><<<static_cast<unsigned>(nfull), 64 * kTallWaves, 0, st>>>( \
+      trmm_bf3_kernel<NBV, true><<<static_cast<unsigned>(gfull), 64 * kTallWaves, 0, st>>>( \
           q, m, n, ldq, p3, 0);                                                            \
     if (tiles > nfull)                                                                     \
       trmm_bf3_kernel<NBV, false><<<static_cast<unsigned>(tiles - nfull), 64 * kTallWaves, \

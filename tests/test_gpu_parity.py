@@ -117,11 +117,12 @@ def test_trsm_in_place_f32(rq, orc):
     assert np.linalg.norm(Qn - Qr) <= 8 * U32 * n * np.linalg.cond(R) * np.linalg.norm(Qr)
 
 
-@pytest.mark.parametrize("m,n", [(128 * 40 + 37, 96), (128 * 24, 256)])
+@pytest.mark.parametrize("m,n", [(128 * 40 + 37, 96), (128 * 24, 256), (128 * 600 + 5, 128)])
 def test_trsm_f32_whole_tiles(rq, orc, m, n):
     """FP32 solve with whole 128-row tiles (staged through LDS) and a ragged
     tail; a padded leading dimension, a misaligned copy (checked kernel) and
-    the in-place call give the same bits."""
+    the in-place call give the same bits.  n = 128, 256: persistent
+    workgroups; 600 tiles also walk several tiles per workgroup."""
     import torch
     rng = np.random.default_rng(m)
     X = np.asfortranarray(rng.standard_normal((m, n))).astype(np.float32)
