@@ -317,6 +317,30 @@ def test_mixed_two_pass(rq, orc, m, n, k, sig):
     assert dR <= 1e-4 and dQ <= 1e-3
 
 
+@pytest.mark.parametrize("precision", ["F32", "MIXED"])
+def test_staged_and_checked_paths_agree(rq, orc, precision):
+    """m = 40004 (ragged tail), n = 200: the whole-tile solves (staged by
+    direct loads) on an aligned X and the checked kernels on a misaligned
+    copy give the same bits; both match the oracle."""
+    import torch
+    m, n, k = 40004, 200, 600
+    prec = getattr(rq, precision)
+    X32 = synth.make_x(m, n, 1e-5, seed=12, dtype=np.float32)
+    Xa = _gpu(X32)
+    mis = torch.empty(m * n + 1, dtype=torch.float32, device="cuda")[1:].view(n, m).t()
+    mis.copy_(Xa)
+    assert mis.data_ptr() % 16 != 0
+    Qa, Ra = rq.factor(Xa, k, 6, rq.RADEMACHER, passes=2, precision=prec)
+    Qm, Rm = rq.factor(mis, k, 6, rq.RADEMACHER, passes=2, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(Ra, Rm) and torch.equal(Qa, Qm)
+    Qn, Rn = _np(Qa).astype(np.float64), _np(Ra)
+    ref = orc.rcholqr(X32.astype(np.float64), k, 6, orc.RADEMACHER, passes=2)
+    assert np.linalg.norm(Qn.T @ Qn - np.eye(n), 2) <= 2e-5
+    assert _colres(X32.astype(np.float64), Qn, Rn) <= 2e-5
+    assert np.linalg.norm(Rn - ref["R"]) <= 1e-4 * np.linalg.norm(ref["R"])
+
+
 def test_device_copy_is_exact(rq):
     import torch
     src = torch.randint(0, 256, (3 << 20,), dtype=torch.uint8, device="cuda")
