@@ -136,10 +136,11 @@ def measured_traffic(workload, kernel):
         rec = json.loads(line)["kernels"]
     except (OSError, IndexError, ValueError, KeyError):
         return None
-    for k, v in rec.items():
-        if k.startswith(kernel) and v.get("src") == source_hash(k):
-            return v["hbm_bytes"]
-    return None
+    # Several instances may match (e.g. whole-tile and ragged-tail kernels of
+    # a solve): the dominant one moves the most bytes.
+    found = [v["hbm_bytes"] for k, v in rec.items()
+             if k.startswith(kernel) and v.get("src") == source_hash(k)]
+    return max(found) if found else None
 
 WORKLOADS = {
     # name: (m, n, k, kind, sigma_min, value precision, x dtype bytes)
