@@ -398,21 +398,31 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
   const int nt = (n + 15) / 16;
   const int ntile = nt * (nt + 1) / 2;
   if (tid == 0) fail = 0;
-  // tile index -> (i, j), column-major over the upper triangle
-  auto decode = [](int t, int& ti, int& tj) {
-    tj = 0;
+  // Tile index -> (i, j), column-major over the upper triangle.  Lane u of
+  // each wave decodes the wave's u-th tile once, packed as i | j << 8 | (not
+  // a tile) << 16; the loops below read it back with a lane read.
+  int tcode = 1 << 16;
+  if (lane < kChPerWave) {
+    int t = wave + kChWaves * lane, tj = 0;
+    const bool live = t < ntile;
     while (t > tj) {
       t -= tj + 1;
       ++tj;
     }
-    ti = t;
+    tcode = t | (tj << 8) | (live ? 0 : 1 << 16);
+  }
+  auto decode = [&](int u, int& ti, int& tj) -> bool {
+    const int code = __builtin_amdgcn_readlane(tcode, u);
+    ti = code & 255;
+    tj = (code >> 8) & 255;
+    return (code >> 16) == 0;
   };
   d4 acc[kChPerWave];
 #pragma unroll
   for (int u = 0; u < kChPerWave; ++u) {
     const int t = wave + kChWaves * u;
     int ti, tj;
-    decode(t, ti, tj);
+    decode(u, ti, tj);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
@@ -450,8 +460,16 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
       for (int j = 0; j < 16; ++j) {
         const double d = read_lane(col[j], j);
         const bool ok = (d > 0.0) && isfinite(d);
-        const double r = ok ? sqrt(d) : 1.0;
-        const double ri = 1.0 / r;
+        // 1 / sqrt(d) from the hardware estimate and two Newton steps
+        // (y <- y (3/2 - d y^2 / 2), each squaring the relative error), then
+        // sqrt(d) = d / sqrt(d): a few dependent FMAs instead of a correctly
+        // rounded square root and division on this serial chain.
+        const double dd = ok ? d : 1.0;
+        const double hd = 0.5 * dd;
+        double ri = __builtin_amdgcn_rsq(dd);
+        ri *= __builtin_fma(-hd, ri * ri, 1.5);
+        ri *= __builtin_fma(-hd, ri * ri, 1.5);
+        const double r = dd * ri;
         if (!ok && lane == 0 && fail == 0 && 16 * P + j < n) fail = 16 * P + j + 1;
         // row j: R(j, c) = A(j, c) / r for c > j; the identity part is scaled whole
         if (apart) {
@@ -480,11 +498,8 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
     // 2. row P: diagonal tile <- R_PP; R_Pj = W^T G_Pj for j > P.
 #pragma unroll
     for (int u = 0; u < kChPerWave; ++u) {
-      const int t = wave + kChWaves * u;
-      if (t >= ntile) continue;
       int ti, tj;
-      decode(t, ti, tj);
-      if (ti != P) continue;
+      if (!decode(u, ti, tj) || ti != P) continue;
       if (tj == P) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -505,11 +520,8 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
     // 3. trailing tiles (i, j), P < i <= j: G_ij -= R_Pi^T R_Pj.
 #pragma unroll
     for (int u = 0; u < kChPerWave; ++u) {
-      const int t = wave + kChWaves * u;
-      if (t >= ntile) continue;
       int ti, tj;
-      decode(t, ti, tj);
-      if (ti <= P) continue;
+      if (!decode(u, ti, tj) || ti <= P) continue;
 #pragma unroll
       for (int sk = 0; sk < 4; ++sk) {
         const double a = -rp[4 * sk + lg][16 * ti + l16];  // A(M = l16, K) = R_Pi(K, l16)
@@ -523,10 +535,8 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
   if (!fail) {
 #pragma unroll
     for (int u = 0; u < kChPerWave; ++u) {
-      const int t = wave + kChWaves * u;
-      if (t >= ntile) continue;
       int ti, tj;
-      decode(t, ti, tj);
+      if (!decode(u, ti, tj)) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
