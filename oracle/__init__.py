@@ -10,6 +10,7 @@ Cholesky QR factorizations":
 * ``trsm_rows``         -- Algorithm 2 step 3, row-wise forward substitution
 * ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
 * ``rcholqr``           -- Algorithm 2 (passes=1) / Algorithm 3 (passes=2)
+* ``reduced_rcholqr``   -- Algorithm 5 (Reduced RCholeskyQR, Section 3.3)
 * ``qr_backward``       -- reverse-mode derivative of the positive-diagonal
                            thin QR (not in the paper; standard identity)
 
@@ -186,6 +187,28 @@ def rcholqr(X, k, seed, kind=GAUSSIAN, passes=2, want_s=False):
                            _ptr(Rs), _ptr(Rp))
     return dict(Q=Q, R=R, Rs=Rs, Rp=Rp if passes == 2 else None, S=S,
                 status=int(st))
+
+
+def extractor(kind, k, l, m, seed):
+    """L for the reduced variant: rows k .. k+l-1 of the seeded operator
+    (the rows after Theta's), scaled like an l-row embedding (1/sqrt(l)).
+    Dense kinds only (a CountSketch row set is not a CountSketch)."""
+    if kind not in (GAUSSIAN, RADEMACHER):
+        raise ValueError("extractor rows need a dense sketch kind")
+    return theta_block(kind, k + l, m, seed, k, l, 0, m) * sketch_scale(kind, l)
+
+
+def reduced_rcholqr(X, k, l, seed, kind=RADEMACHER, want_s=False):
+    """Algorithm 5: P = Theta X and Y = L X (step 1), [S, R] = QR(P)
+    (step 2, Householder with positive diagonal), Z = Y R^{-1} (step 3,
+    row-wise forward substitution).  Returns dict(Z, R, S, P, Y, status)."""
+    X = _f64(X)
+    m, n = X.shape
+    P = sketch(kind, X, k, seed)
+    Y = np.asfortranarray(extractor(kind, k, l, m, seed) @ X)
+    R, S, st = householder_qr(P, want_s=want_s)
+    Z = trsm_rows(Y, R) if st == 0 else None
+    return dict(Z=Z, R=R, S=S, P=P, Y=Y, status=int(st))
 
 
 def qr_backward(Q, R, dQ, dR):

@@ -456,3 +456,56 @@ def test_adjoint_single_column_closed_form(orc):
     dX = orc.qr_backward(q, np.array([[r]]), qb, rb)
     ref = (qb - q * (q.T @ qb)) / r + q * rb[0, 0]
     assert np.allclose(dX, ref, rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------- Algorithm 5
+@pytest.mark.parametrize("kind,k", [(G, 31), (G, 64), (RD, 130)])
+def test_extractor_rows_follow_theta_rows(orc, kind, k):
+    """Theta' = [Theta; L]: the rows of the (k + l)-row operator below k are
+    the k-row operator's own rows (entries depend on the row index only)."""
+    m, l = 300, 17
+    a = orc.theta_block(kind, k, m, 4, 0, k, 0, m)
+    b = orc.theta_block(kind, k + l, m, 4, 0, k + l, 0, m)
+    assert np.array_equal(a, b[:k])
+    L = orc.extractor(kind, k, l, m, 4)
+    assert np.array_equal(L, b[k:] * orc.sketch_scale(kind, l))
+    with pytest.raises(ValueError):
+        orc.extractor(CS, k, l, m, 4)
+
+
+@pytest.mark.parametrize("kind", [G, RD])
+def test_reduced_equals_extractor_times_q(orc, kind):
+    """Extracting before the solve (step 3 of Algorithm 5) gives L Q for the Q
+    of Algorithm 2 with the same Theta; R is the same R bit for bit."""
+    m, n, k, l = 3000, 12, 36, 9
+    X = synth.make_x(m, n, 1e-3, seed=21)
+    red = orc.reduced_rcholqr(X, k, l, 5, kind)
+    one = orc.rcholqr(X, k, 5, kind, passes=1)
+    assert red["status"] == 0 and one["status"] == 0
+    assert np.array_equal(red["R"], one["R"])
+    LQ = orc.extractor(kind, k, l, m, 5) @ one["Q"]
+    assert np.linalg.norm(red["Z"] - LQ) <= 1e-11 * np.linalg.norm(LQ)
+
+
+def test_reduced_is_invariant_under_power_of_two_column_scaling(orc):
+    """X D with D = diag(2^e): P, Y scale by D exactly, R by D, so Z = Y R^{-1}
+    is the same bits (catches a transposed or misplaced triangular factor)."""
+    m, n, k, l = 800, 7, 21, 5
+    X = synth.make_x(m, n, 1e-2, seed=22)
+    D = 2.0 ** np.array([3, -5, 0, 7, -2, 1, -9], dtype=np.float64)
+    a = orc.reduced_rcholqr(X, k, l, 8, RD)
+    b = orc.reduced_rcholqr(X * D, k, l, 8, RD)
+    assert np.array_equal(b["R"], a["R"] * D)
+    assert np.array_equal(b["Z"], a["Z"])
+
+
+def test_reduced_single_column_closed_form(orc):
+    """n = 1: R = ||Theta x||, Z = L x / ||Theta x|| (scaled operators)."""
+    m, k, l = 500, 9, 4
+    x = np.asfortranarray(np.random.default_rng(3).standard_normal((m, 1)))
+    red = orc.reduced_rcholqr(x, k, l, 2, G)
+    th = orc.theta_block(G, k, m, 2, 0, k, 0, m) * orc.sketch_scale(G, k)
+    r = np.linalg.norm(th @ x)
+    assert abs(red["R"][0, 0] - r) <= 1e-14 * r
+    z = (orc.extractor(G, k, l, m, 2) @ x) / r
+    assert np.allclose(red["Z"], z, rtol=1e-13, atol=0)
