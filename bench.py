@@ -250,6 +250,30 @@ def time_leg(torch, rq, X, k, kind, prec_code, steps, warmup, seed=1):
     return ms, phases, Q, R
 
 
+def reduced_leg(torch, rq, X, k, l, kind, prec_code, steps, warmup, seed=1):
+    """Reduced RCholeskyQR (Algorithm 5) on the same X: Z = L X R^{-1}.
+    Returns ms per call and ||S^T S - I||_2 of the sketch's orthonormal
+    factor (outside the timed region)."""
+    m, n = X.shape
+    ws = torch.empty(int(rq.lib().rcholqr_reduced_workspace_bytes(m, n, k, l, kind, prec_code)),
+                     dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        rq.reduced(X, k, l, seed, kind, prec_code, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        Z, R = rq.reduced(X, k, l, seed, kind, prec_code, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = rq.status(ws)
+    _, _, ex = rq.reduced(X, k, l, seed, kind, prec_code, want_s=True, ws=ws)
+    S = ex["S"]
+    orth_s = float(torch.linalg.matrix_norm(S.T @ S - torch.eye(n, dtype=S.dtype, device=S.device), 2))
+    return ms, orth_s, st
+
+
 def cpu_baseline(Xs_np, k, kind_code, budget_s=15.0):
     """FP64 CPU oracle (test infrastructure) on the first rows of X.
 
@@ -280,6 +304,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed-4m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-reduced-leg", action="store_true",
+                    help="skip the Reduced RCholeskyQR figure")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -341,6 +367,17 @@ def main():
     R_value = R.clone()
     del Q
 
+    # Reduced RCholeskyQR on the same X (one pass over X; l extractor rows).
+    red = None
+    if not args.no_reduced_leg and kind != rq.COUNTSKETCH:
+        l = min(256, 1024 - k)
+        ms_r, orth_s, st_r = reduced_leg(torch, rq, X, k, l, kind, prec_code, args.steps,
+                                         args.warmup)
+        red = {"value": round(m * n * xbytes / (ms_r * 1e-3) / 1e9, 2), "unit": "GB/s",
+               "ms_per_step": round(ms_r, 4), "l": l, "orth_S": orth_s, "status": st_r}
+        log(f"[bench] reduced (l={l}): {ms_r:.3f} ms/step {red['value']} GB/s "
+            f"||S^T S - I|| = {orth_s:.2e}")
+
     fp64 = None
     if not args.no_fp64_leg and prec != "f64":
         X64 = X.double()
@@ -385,6 +422,7 @@ def main():
         "roofline": roof,
         "phase_rooflines": phase_roof,
         "fp64": fp64,
+        "reduced": red,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

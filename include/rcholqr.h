@@ -108,6 +108,36 @@ int rcholqr_factor(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
                    int64_t lds, double* Rs, double* Rp, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* Reduced RCholeskyQR (Algorithm 5, Section 3.3): the l x n projection
+ * Z = L Q of the well-conditioned Q factor without forming Q.  One pass over
+ * X forms P = Theta X and Y = L X, then [S, R] = QR(P) (Householder, positive
+ * diagonal) and Z = Y R^{-1} (row-wise forward substitution, FP64).
+ *
+ * L is the extractor of rows k .. k+l-1 of the same counter-based operator as
+ * Theta (same seed and kind, independent rows), scaled by 1/sqrt(l): an
+ * oblivious embedding of its own.  Theta is exactly the k-row operator of
+ * rcholqr_factor with the same seed and kind.
+ *
+ *  X      [in]  m x n, column-major, ld ldx >= m; FP64 for RCHOLQR_F64,
+ *               FP32 for RCHOLQR_F32 and RCHOLQR_MIXED (device pointer).
+ *  k, l   sketch rows (n <= k) and extractor rows (l >= 1), k + l <= 1024.
+ *  seed, sketch_kind   RCHOLQR_GAUSSIAN or RCHOLQR_RADEMACHER (a CountSketch
+ *               maps every column of X to one row, so its rows are not
+ *               independent: refused); MIXED requires RADEMACHER.
+ *  Z      [out] l x n FP64, ld ldz >= l.     R [out] n x n FP64 upper, ld ldr.
+ *  S      [out, optional] k x n FP64, S = P R^{-1} (orthonormal), ld lds >= k.
+ *  ws     workspace of rcholqr_reduced_workspace_bytes(m, n, k, l, kind,
+ *         precision) bytes; its first word is the status (as rcholqr_factor:
+ *         1 rank-deficient sketch, 2 non-finite X).
+ * Returns 0, -i for invalid argument i (1-based), or RCHOLQR_ERR_HIP.
+ * Asynchronous on `stream`; allocates nothing. */
+size_t rcholqr_reduced_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l,
+                                       int sketch_kind, int precision);
+int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+                    int64_t l, uint64_t seed, int sketch_kind, int precision,
+                    double* Z, int64_t ldz, double* R, int64_t ldr, double* S,
+                    int64_t lds, void* ws, size_t ws_bytes, void* stream);
+
 /* Read the status word of a workspace used by a completed call
  * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.
  * Returns 0 or RCHOLQR_ERR_HIP. */

@@ -74,6 +74,11 @@ def lib():
     L.rcholqr_profile_enable.restype = i32
     L.rcholqr_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
     L.rcholqr_profile_read.restype = i32
+    L.rcholqr_reduced_workspace_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
+    L.rcholqr_reduced_workspace_bytes.restype = sz
+    L.rcholqr_reduced.argtypes = [vp, i64, i64, i64, i64, i64, u64, i32, i32, dp, i64, dp, i64,
+                                  dp, i64, vp, sz, vp]
+    L.rcholqr_reduced.restype = i32
     L.rcholqr_device_copy.argtypes = [vp, vp, sz, vp]
     L.rcholqr_device_copy.restype = i32
     L.rcholqr_error_string.argtypes = [i32]
@@ -169,6 +174,37 @@ def factor(X, k, seed, kind=GAUSSIAN, passes=2, precision=None, want_s=False,
     if want_s or want_factors:
         return Q, R, dict(S=S, Rs=Rs, Rp=Rp, ws=ws)
     return Q, R
+
+
+def reduced(X, k, l, seed, kind=RADEMACHER, precision=None, want_s=False, ws=None):
+    """Reduced RCholeskyQR (Algorithm 5): Z = L X R^{-1} (l x n FP64) and R,
+    where L is rows k .. k+l-1 of the seeded operator (scaled 1/sqrt(l)).
+
+    Returns (Z, R) or, with want_s, (Z, R, dict(S=S, ws=ws))."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X = fortran(X)
+    m, n = X.shape
+    dt = _dtype_for(precision)
+    if X.dtype != dt:
+        raise TypeError(f"X must be {dt} for precision {precision}")
+    need = int(lib().rcholqr_reduced_workspace_bytes(m, n, k, l, kind, precision))
+    if need == 0:
+        raise RCholQRError(-1, "invalid problem size")
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    if ws.numel() < need:
+        raise RCholQRError(-17, "workspace too small")
+    Z = empty_fortran(l, n, torch.float64, X.device)
+    R = empty_fortran(n, n, torch.float64, X.device)
+    S = empty_fortran(k, n, torch.float64, X.device) if want_s else None
+    code = lib().rcholqr_reduced(_ptr(X), m, n, _ld(X), k, l, int(seed), kind, precision,
+                                 _ptr(Z), _ld(Z), _ptr(R), _ld(R), _ptr(S), k, _ptr(ws),
+                                 ws.numel(), _stream())
+    _check(code, "rcholqr_reduced")
+    if want_s:
+        return Z, R, dict(S=S, ws=ws)
+    return Z, R
 
 
 def status(ws):

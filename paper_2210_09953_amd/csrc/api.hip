@@ -499,6 +499,61 @@ int rcholqr_profile_read(double* ms) {
   return n;
 }
 
+// Reduced RCholeskyQR: one (k + l)-row sketch pass, two fixed-order
+// reductions (P with 1/sqrt(k), Y = L X with 1/sqrt(l) straight into Z),
+// Householder on P, Z = Y R^{-1} in place by the FP64 row solve.
+size_t rcholqr_reduced_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int sketch_kind,
+                                       int precision) {
+  if (!valid_dims(m, n, k) || l < 1 || k + l > kMaxK || sketch_kind < 0 || sketch_kind > 1 ||
+      precision < 0 || precision > 2)
+    return 0;
+  return make_layout(m, n, k + l, sketch_kind, 1, precision).total;
+}
+
+int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, int64_t l,
+                    uint64_t seed, int sketch_kind, int precision, double* Z, int64_t ldz,
+                    double* R, int64_t ldr, double* S, int64_t lds, void* ws, size_t ws_bytes,
+                    void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (k < n || k > kMaxK) return -5;
+  if (l < 1 || k + l > kMaxK) return -6;
+  if (sketch_kind != kGaussian && sketch_kind != kRademacher) return -8;
+  if (precision < 0 || precision > 2) return -9;
+  if (precision == kPrecMixed && sketch_kind != kRademacher) return -9;
+  if (!Z) return -10;
+  if (ldz < l) return -11;
+  if (!R) return -12;
+  if (ldr < n) return -13;
+  if (S && lds < k) return -15;
+  if (!ws) return -16;
+  const int64_t kl = k + l;
+  const Layout L = make_layout(m, n, kl, sketch_kind, 1, precision);
+  if (ws_bytes < L.total) return -17;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int ni = static_cast<int>(n), ki = static_cast<int>(k), li = static_cast<int>(l);
+  double* part = at<double>(ws, L.part);
+  double* P = at<double>(ws, L.P);  // room for (k + l) x n; P uses k x n, ld k
+  if (precision == kPrecMixed)
+    RCQ_TRY(launch_sketch_mixed_partials(static_cast<const float*>(X), m, ni, ldx,
+                                         static_cast<int>(kl), seed, L.sp, part, st));
+  else
+    RCQ_TRY(launch_sketch_partials(X, precision != kPrecF64, m, ni, ldx, static_cast<int>(kl),
+                                   sketch_kind, seed, L.sp, part, at<uint32_t>(ws, L.keys), st));
+  RCQ_TRY(launch_sketch_reduce(part, L.sp, ki, ni, 1.0 / sqrt(static_cast<double>(k)), P, k, st));
+  RCQ_TRY(launch_sketch_reduce(part + k, L.sp, li, ni, 1.0 / sqrt(static_cast<double>(l)), Z, ldz,
+                               st));
+  double* Rsw = at<double>(ws, L.Rs);
+  RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
+                             at<double>(ws, L.T), S, lds, Rsw, R, ldr, at<int>(ws, L.status), st));
+  void* pan = at<void>(ws, L.pan);
+  RCQ_TRY(launch_make_panels(Rsw, n, ni, false, pan, st));
+  RCQ_TRY(launch_trsm(Z, false, l, ni, ldz, pan, Z, ldz, st));
+  return 0;
+}
+
 int rcholqr_status(const void* ws, int* info) {
   if (!ws || !info) return -1;
   if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;

@@ -42,10 +42,18 @@ hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t
                          uint32_t* keys, double* P, int64_t ldp, hipStream_t st);
 hipError_t launch_sketch_reduce(const double* part, const SketchPlan& pl, int k, int n,
                                 double scale, double* P, int64_t ldp, hipStream_t st);
+// The split partials of the sketch without the reduction (rows 0..k-1 of
+// each split's partial, layout as in launch_sketch_reduce).
+hipError_t launch_sketch_partials(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx,
+                                  int k, int kind, uint64_t seed, const SketchPlan& pl,
+                                  double* part, uint32_t* keys, hipStream_t st);
 void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp);
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
                                hipStream_t st);
+hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_t ldx, int k,
+                                        uint64_t seed, const SketchPlan& pl, double* part,
+                                        hipStream_t st);
 
 // small.hip
 hipError_t launch_householder(double* A, int k, int n, double* V, double* beta, double* T,

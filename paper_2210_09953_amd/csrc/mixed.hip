@@ -485,9 +485,9 @@ void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp) {
   sp.rows_per_split = round_up(ceil_div(m, sp.nsplit), stage);
 }
 
-hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
-                               const SketchPlan& pl, double* part, double* P, int64_t ldp,
-                               hipStream_t st) {
+hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_t ldx, int k,
+                                        uint64_t seed, const SketchPlan& pl, double* part,
+                                        hipStream_t st) {
   const I8Plan p = i8_plan(k, n);
   if (p.ktiles != pl.ktiles || p.kpad != pl.kpad || p.npad != pl.npad ||
       (pl.rows_per_split % (kQBlock * p.sb)) != 0 || (pl.nsplit % 8) != 0 ||
@@ -514,7 +514,13 @@ hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, in
   else
     RCQ_I8(4, 1, 1, 2, false);
 #undef RCQ_I8
-  e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
+                               const SketchPlan& pl, double* part, double* P, int64_t ldp,
+                               hipStream_t st) {
+  const hipError_t e = launch_sketch_mixed_partials(X, m, n, ldx, k, seed, pl, part, st);
   if (e != hipSuccess) return e;
   return launch_sketch_reduce(part, pl, k, n, 1.0 / sqrt(static_cast<double>(k)), P, ldp, st);
 }

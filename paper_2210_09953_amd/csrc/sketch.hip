@@ -288,9 +288,9 @@ static hipError_t dense_dispatch(int nb, const TX* X, int64_t m, int n, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
-                         int kind, uint64_t seed, const SketchPlan& pl, double* part,
-                         uint32_t* keys, double* P, int64_t ldp, hipStream_t st) {
+hipError_t launch_sketch_partials(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx,
+                                  int k, int kind, uint64_t seed, const SketchPlan& pl,
+                                  double* part, uint32_t* keys, hipStream_t st) {
   hipError_t e;
   if (kind == kCountSketch) {
     const int64_t ntile = ceil_div(m, kCsTile);
@@ -326,6 +326,14 @@ hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t
       e = dense_dispatch<double>(nb, static_cast<const double*>(X), m, n, ldx, kind, seed, pl, part, st);
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
+                         int kind, uint64_t seed, const SketchPlan& pl, double* part,
+                         uint32_t* keys, double* P, int64_t ldp, hipStream_t st) {
+  const hipError_t e = launch_sketch_partials(X, x_is_f32, m, n, ldx, k, kind, seed, pl, part, keys, st);
+  if (e != hipSuccess) return e;
   const double scale = (kind == kCountSketch) ? 1.0 : 1.0 / sqrt(static_cast<double>(k));
   return launch_sketch_reduce(part, pl, k, n, scale, P, ldp, st);
 }

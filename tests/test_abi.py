@@ -22,7 +22,8 @@ def test_header_declares_entry_points():
               "rcholqr_sketch", "rcholqr_debug_theta", "rcholqr_trsm",
               "rcholqr_error_string", "rcholqr_batched_workspace_bytes",
               "rcholqr_factor_batched", "rcholqr_batched_status",
-              "rcholqr_backward_workspace_bytes", "rcholqr_backward"]:
+              "rcholqr_backward_workspace_bytes", "rcholqr_backward",
+              "rcholqr_reduced_workspace_bytes", "rcholqr_reduced"]:
         assert n in names
 
 
@@ -81,3 +82,34 @@ def test_device_copy_argument_errors_without_gpu():
     assert L.rcholqr_device_copy(vp(256), vp(264), 16, None) == -2
     assert L.rcholqr_device_copy(vp(256), vp(512), 15, None) == -3
     assert L.rcholqr_device_copy(vp(256), vp(512), 0, None) == 0
+
+
+def test_reduced_argument_errors_without_gpu():
+    """Reduced RCholeskyQR: sizes and kinds are checked before any launch."""
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    vp = ctypes.c_void_p
+    W = L.rcholqr_reduced_workspace_bytes
+    assert W(1000, 10, 30, 8, rq.RADEMACHER, rq.F64) > 0
+    assert W(1000, 10, 30, 0, rq.RADEMACHER, rq.F64) == 0        # l >= 1
+    assert W(1000, 10, 1000, 100, rq.RADEMACHER, rq.F64) == 0    # k + l <= 1024
+    assert W(1000, 10, 30, 8, rq.COUNTSKETCH, rq.F64) == 0      # dense kinds only
+
+    def call(X=256, m=1000, n=10, ldx=1000, k=30, l=8, kind=rq.RADEMACHER, prec=rq.F64,
+             Z=256, ldz=8, R=256, ldr=10, S=None, lds=30, ws=256, wsb=1 << 30):
+        return L.rcholqr_reduced(vp(X), m, n, ldx, k, l, 1, kind, prec, vp(Z), ldz, vp(R), ldr,
+                                 vp(S) if S else None, lds, vp(ws), wsb, None)
+    assert call(X=0) == -1
+    assert call(m=5) == -2
+    assert call(ldx=10) == -4
+    assert call(k=5) == -5
+    assert call(l=0) == -6
+    assert call(kind=rq.COUNTSKETCH) == -8
+    assert call(kind=rq.GAUSSIAN, prec=rq.MIXED) == -9
+    assert call(Z=0) == -10
+    assert call(ldz=3) == -11
+    assert call(R=0) == -12
+    assert call(ldr=4) == -13
+    assert call(S=256, lds=10) == -15
+    assert call(ws=0) == -16
+    assert call(wsb=16) == -17
