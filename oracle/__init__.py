@@ -11,6 +11,8 @@ Cholesky QR factorizations":
 * ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
 * ``rcholqr``           -- Algorithm 2 (passes=1) / Algorithm 3 (passes=2)
 * ``reduced_rcholqr``   -- Algorithm 5 (Reduced RCholeskyQR, Section 3.3)
+* ``qrcp``/``rr_rcholqr`` -- Algorithm 7 (rank-revealing RCholeskyQR, Section 4)
+                           with QR with column pivoting as its RRQR step
 * ``qr_backward``       -- reverse-mode derivative of the positive-diagonal
                            thin QR (not in the paper; standard identity)
 
@@ -209,6 +211,64 @@ def reduced_rcholqr(X, k, l, seed, kind=RADEMACHER, want_s=False):
     R, S, st = householder_qr(P, want_s=want_s)
     Z = trsm_rows(Y, R) if st == 0 else None
     return dict(Z=Z, R=R, S=S, P=P, Y=Y, status=int(st))
+
+
+def qrcp(A):
+    """Householder QR with column pivoting (Businger-Golub): at step j the
+    remaining column of largest 2-norm over rows j.. (recomputed, first one
+    on ties) is swapped in, then reflected.  Returns (R, piv) with A[:, piv]
+    = Q R and a positive diagonal of R (rows of R and columns of Q flipped)."""
+    W = np.array(_f64(A), dtype=np.float64, order="F", copy=True)
+    k, n = W.shape
+    piv = np.arange(n)
+    for j in range(min(k, n)):
+        norms = np.sqrt(np.sum(W[j:, j:] ** 2, axis=0))
+        p = j + int(np.argmax(norms))
+        if p != j:
+            W[:, [j, p]] = W[:, [p, j]]
+            piv[[j, p]] = piv[[p, j]]
+        x = W[j:, j].copy()
+        nrm = np.linalg.norm(x)
+        if nrm == 0.0:
+            continue
+        alpha = -nrm if x[0] >= 0 else nrm
+        v = x.copy()
+        v[0] -= alpha
+        beta = 2.0 / (v @ v)
+        W[j:, j:] -= beta * np.outer(v, v @ W[j:, j:])
+        W[j, j] = alpha
+        W[j + 1:, j] = 0.0
+    R = np.triu(W[:n, :n]) if k >= n else np.triu(W)
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return np.asfortranarray(R * sgn[:, None]), piv
+
+
+def rr_rank(R, tau):
+    """Step 3 of Algorithm 7: the least r with ||R[r:, r:]||_F <= tau ||R||_2."""
+    n = R.shape[0]
+    s2 = np.linalg.norm(R, 2)
+    for r in range(n + 1):
+        if np.linalg.norm(R[r:, r:], "fro") <= tau * s2:
+            return r
+    return n
+
+
+def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12):
+    """Algorithm 7 on the column-normalised X (Section 4): D = column norms,
+    P = (Theta X) D^{-1}, [R, Pi] = RRQR(P) (column-pivoted Householder),
+    rank r, Q = (X Pi_{1:r}) (R_{1:r,1:r} (Pi^T D Pi)_{1:r})^{-1} and
+    R <- R_{1:r,:} Pi^T D Pi.  Returns dict(Q, R, piv, rank, Rn) (Rn: the
+    R of the normalised sketch)."""
+    X = _f64(X)
+    m, n = X.shape
+    d = np.linalg.norm(X, axis=0)
+    P = sketch(kind, X, k, seed) / d
+    Rn, piv = qrcp(P)
+    r = rr_rank(Rn, tau)
+    Rout = np.asfortranarray(Rn[:r, :] * d[piv][None, :])
+    Q = trsm_rows(np.asfortranarray(X[:, piv[:r]]), np.asfortranarray(Rout[:, :r])) if r else \
+        np.zeros((m, 0), order="F")
+    return dict(Q=Q, R=Rout, piv=piv, rank=r, Rn=Rn)
 
 
 def qr_backward(Q, R, dQ, dR):

@@ -509,3 +509,59 @@ def test_reduced_single_column_closed_form(orc):
     assert abs(red["R"][0, 0] - r) <= 1e-14 * r
     z = (orc.extractor(G, k, l, m, 2) @ x) / r
     assert np.allclose(red["Z"], z, rtol=1e-13, atol=0)
+
+
+# ----------------------------------------------------------------------------- Algorithm 7
+def test_qrcp_matches_lapack_geqp3(orc):
+    """Column-pivoted Householder against LAPACK's xGEQP3 (distinct norms:
+    the same pivots; R equal up to row signs)."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((60, 20)) * np.logspace(0, 4, 20)[rng.permutation(20)]
+    R, piv = orc.qrcp(A)
+    _, Rl, pl = scipy.linalg.qr(A, mode="economic", pivoting=True)
+    assert np.array_equal(piv, pl)
+    assert np.allclose(R, np.abs(np.diag(Rl))[:, None] / np.diag(Rl)[:, None] * Rl,
+                       rtol=1e-12, atol=1e-12 * np.abs(Rl).max())
+    assert np.all(np.diag(R) >= 0)
+    assert np.all(np.diff(np.diag(R)) <= 1e-12 * R[0, 0])  # non-increasing pivots
+
+
+@pytest.mark.parametrize("kind", [G, RD])
+def test_rr_rcholqr_finds_exact_rank(orc, kind):
+    """X = U V of exact rank 7 (n = 16): r = 7, X Pi = Q R on all columns
+    (the dropped ones within tau), Q well-conditioned."""
+    rng = np.random.default_rng(9)
+    m, n, rho, k = 4000, 16, 7, 48
+    X = rng.standard_normal((m, rho)) @ rng.standard_normal((rho, n))
+    X = np.asfortranarray(X * np.logspace(0, 3, n))
+    out = orc.rr_rcholqr(X, k, 3, kind, tau=1e-10)
+    assert out["rank"] == rho
+    Q, R, piv = out["Q"], out["R"], out["piv"]
+    assert np.linalg.cond(Q) <= 10
+    XP = X[:, piv]
+    err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
+    assert err.max() <= 1e-9
+
+
+def test_rr_rcholqr_full_rank_is_stable_beyond_cholesky(orc):
+    """kappa = 1e14 (beyond what the Cholesky-based passes take): with a tiny
+    tau every column is kept or the trailing part is below tau; Q stays
+    well-conditioned and X Pi = Q R to ~u n."""
+    m, n, k = 3000, 20, 60
+    X = synth.make_x(m, n, 1e-14, seed=4)
+    out = orc.rr_rcholqr(X, k, 2, G, tau=1e-15)
+    Q, R, piv, r = out["Q"], out["R"], out["piv"], out["rank"]
+    assert np.linalg.cond(Q) <= 20
+    XP = X[:, piv]
+    err = np.linalg.norm(XP[:, :r] - Q @ R[:, :r], axis=0) / np.linalg.norm(XP[:, :r], axis=0)
+    assert err.max() <= 1e-12
+
+
+def test_rr_rank_rule(orc):
+    """Step 3: the least r with ||R[r:, r:]||_F <= tau ||R||_2."""
+    R = np.diag([4.0, 2.0, 1e-3, 1e-9, 0.0])
+    assert orc.rr_rank(R, 1e-2) == 2
+    assert orc.rr_rank(R, 1e-8) == 3
+    assert orc.rr_rank(R, 1e-12) == 4
+    assert orc.rr_rank(R, 0.0) == 4
+    assert orc.rr_rank(np.zeros((3, 3)), 1e-3) == 0
