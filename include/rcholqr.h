@@ -138,6 +138,33 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
                     double* Z, int64_t ldz, double* R, int64_t ldr, double* S,
                     int64_t lds, void* ws, size_t ws_bytes, void* stream);
 
+/* Rank-revealing RCholeskyQR (Algorithm 7, Section 4): X Pi ~ Q R with Q
+ * (m x r) well-conditioned and R (r x n) upper trapezoidal, for any X
+ * (numerically rank-deficient included).  Steps: P = Theta X; D = diag of
+ * the column norms of X; the rank-revealing QR of P D^{-1} (Householder with
+ * column pivoting: largest remaining column norm, the first on ties); r =
+ * the least r with ||R_{r+1:n,r+1:n}||_F <= tau ||R||_2; Q = X Pi_{:,1:r}
+ * (R_{1:r,1:r} Pi^T D Pi)^{-1} by the tall forward substitution; R <-
+ * R_{1:r,:} Pi^T D Pi.
+ *
+ *  X, m, n, ldx, k, seed, sketch_kind, precision  as rcholqr_factor.
+ *  tau    truncation tolerance (>= 0).
+ *  Q      [out] m x n buffer (ld ldq >= m, FP64 or FP32 as X): columns 0..r-1
+ *         hold Q; columns r.. hold the dropped columns of X Pi (unscaled).
+ *  R      [out] n x n FP64 (ld ldr): rows 0..r-1 hold R, rows r.. are zero.
+ *  piv    [out] n int32 on the device: column j of X Pi is column piv[j] of X.
+ *  rank   [out] one int32 on the device: r (read it after the stream has
+ *         finished; the call never synchronises).
+ *  ws     rcholqr_rr_workspace_bytes(m, n, k, kind, precision) bytes; status
+ *         word 0, or 2 for non-finite X.
+ * Returns 0, -i for invalid argument i (1-based), or RCHOLQR_ERR_HIP. */
+size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
+                                  int precision);
+int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+               uint64_t seed, int sketch_kind, int precision, double tau, void* Q,
+               int64_t ldq, double* R, int64_t ldr, int* piv, int* rank, void* ws,
+               size_t ws_bytes, void* stream);
+
 /* Read the status word of a workspace used by a completed call
  * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.
  * Returns 0 or RCHOLQR_ERR_HIP. */

@@ -262,7 +262,7 @@ def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12):
     X = _f64(X)
     m, n = X.shape
     d = np.linalg.norm(X, axis=0)
-    P = sketch(kind, X, k, seed) / d
+    P = sketch(kind, X, k, seed) / np.where(d > 0, d, 1.0)  # a zero column stays zero
     Rn, piv = qrcp(P)
     r = rr_rank(Rn, tau)
     Rout = np.asfortranarray(Rn[:r, :] * d[piv][None, :])

@@ -13,7 +13,7 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, F64, F32, MIXED,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
                       status, error_string, fortran, empty_fortran, PHASES,
                       profile_enable, profile_read, backward, BatchedFactor, Problem,
-                      device_copy, reduced)
+                      device_copy, reduced, rr)
 from .autograd import RCholQR2, rcholqr2
 
 __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
@@ -21,4 +21,4 @@ __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",
            "profile_enable", "profile_read", "backward", "RCholQR2", "rcholqr2", "device_copy",
-           "BatchedFactor", "Problem", "reduced"]
+           "BatchedFactor", "Problem", "reduced", "rr"]

@@ -554,6 +554,66 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
   return 0;
 }
 
+// Rank-revealing RCholeskyQR: sketch, column norms and P D^{-1},
+// Householder of P D^{-1}, column-pivoted QR of its R, rank rule and the
+// factors, gather X Pi into Q, tall solve in place.
+size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
+                                  int precision) {
+  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 2 || precision < 0 ||
+      precision > 2)
+    return 0;
+  return align256(make_layout(m, n, k, sketch_kind, 1, precision).total) +
+         align256(rr_extra_bytes(static_cast<int>(n)));
+}
+
+int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
+               int sketch_kind, int precision, double tau, void* Q, int64_t ldq, double* R,
+               int64_t ldr, int* piv, int* rank, void* ws, size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (n < 1 || n > kMaxN) return -3;
+  if (m < n) return -2;
+  if (ldx < m) return -4;
+  if (k < n || k > kMaxK) return -5;
+  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (precision < 0 || precision > 2) return -8;
+  if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
+  if (!(tau >= 0.0) || !isfinite(tau)) return -9;
+  if (!Q) return -10;
+  if (ldq < m) return -11;
+  if (!R) return -12;
+  if (ldr < n) return -13;
+  if (!piv) return -14;
+  if (!rank) return -15;
+  if (!ws) return -16;
+  const Layout L = make_layout(m, n, k, sketch_kind, 1, precision);
+  if (ws_bytes < align256(L.total) + align256(rr_extra_bytes(static_cast<int>(n)))) return -17;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f32 = precision != kPrecF64;
+  const int ni = static_cast<int>(n), ki = static_cast<int>(k);
+  double* P = at<double>(ws, L.P);
+  unsigned char* extra = at<unsigned char>(ws, align256(L.total));
+  int* status = at<int>(ws, L.status);
+  if (precision == kPrecMixed)
+    RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
+                                at<double>(ws, L.part), P, k, st));
+  else
+    RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
+                          at<uint32_t>(ws, L.keys), P, k, st));
+  double* Rsolve = nullptr;
+  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, nullptr, tau, extra, R, ldr, piv, rank, status,
+                          &Rsolve, st, 0));
+  double* Rsw = at<double>(ws, L.Rs);
+  RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
+                             at<double>(ws, L.T), nullptr, k, Rsw, nullptr, ldr, status, st));
+  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, Rsw, tau, extra, R, ldr, piv, rank, status,
+                          &Rsolve, st, 1));
+  RCQ_TRY(launch_gather_cols(X, f32, m, ni, ldx, piv, Q, ldq, st));
+  void* pan = at<void>(ws, L.pan);
+  RCQ_TRY(launch_make_panels(Rsolve, n, ni, f32, pan, st));
+  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  return 0;
+}
+
 int rcholqr_status(const void* ws, int* info) {
   if (!ws || !info) return -1;
   if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;

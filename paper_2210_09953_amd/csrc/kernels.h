@@ -55,6 +55,17 @@ hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_
                                         uint64_t seed, const SketchPlan& pl, double* part,
                                         hipStream_t st);
 
+// rr.hip (rank-revealing variant).  stage 0: column norms d of X and P <-
+// P D^{-1} (P k x n, ld k); stage 1: column-pivoted QR of Rp (n x n), rank,
+// R (ld ldr), piv, rank, status, and *Rs_out = the solve's n x n factor.
+size_t rr_extra_bytes(int n);
+hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ldx, double* P,
+                           int k, const double* Rp, double tau, unsigned char* extra,
+                           double* R, int64_t ldr, int* piv_out, int* rank_out, int* status,
+                           double** Rs_out, hipStream_t st, int stage);
+hipError_t launch_gather_cols(const void* X, bool f32, int64_t m, int n, int64_t ldx,
+                              const int* piv, void* Q, int64_t ldq, hipStream_t st);
+
 // small.hip
 hipError_t launch_householder(double* A, int k, int n, double* V, double* beta, double* T,
                               double* S, int64_t lds, double* Rs, double* R, int64_t ldr,

@@ -23,7 +23,8 @@ def test_header_declares_entry_points():
               "rcholqr_error_string", "rcholqr_batched_workspace_bytes",
               "rcholqr_factor_batched", "rcholqr_batched_status",
               "rcholqr_backward_workspace_bytes", "rcholqr_backward",
-              "rcholqr_reduced_workspace_bytes", "rcholqr_reduced"]:
+              "rcholqr_reduced_workspace_bytes", "rcholqr_reduced",
+              "rcholqr_rr_workspace_bytes", "rcholqr_rr"]:
         assert n in names
 
 
@@ -111,5 +112,35 @@ def test_reduced_argument_errors_without_gpu():
     assert call(R=0) == -12
     assert call(ldr=4) == -13
     assert call(S=256, lds=10) == -15
+    assert call(ws=0) == -16
+    assert call(wsb=16) == -17
+
+
+def test_rr_argument_errors_without_gpu():
+    """Rank-revealing RCholeskyQR: sizes, kinds and tau are checked first."""
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    vp = ctypes.c_void_p
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64) > 0
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 5, rq.GAUSSIAN, rq.F64) == 0
+
+    def call(X=256, m=1000, n=10, ldx=1000, k=30, kind=rq.GAUSSIAN, prec=rq.F64, tau=1e-12,
+             Q=256, ldq=1000, R=256, ldr=10, piv=256, rank=256, ws=256, wsb=1 << 30):
+        return L.rcholqr_rr(vp(X), m, n, ldx, k, 1, kind, prec, tau, vp(Q), ldq, vp(R), ldr,
+                            vp(piv), vp(rank), vp(ws), wsb, None)
+    assert call(X=0) == -1
+    assert call(m=5) == -2
+    assert call(ldx=10) == -4
+    assert call(k=5) == -5
+    assert call(kind=7) == -7
+    assert call(kind=rq.GAUSSIAN, prec=rq.MIXED) == -8
+    assert call(tau=-1.0) == -9
+    assert call(tau=float("nan")) == -9
+    assert call(Q=0) == -10
+    assert call(ldq=10) == -11
+    assert call(R=0) == -12
+    assert call(ldr=3) == -13
+    assert call(piv=0) == -14
+    assert call(rank=0) == -15
     assert call(ws=0) == -16
     assert call(wsb=16) == -17

@@ -1,0 +1,102 @@
+"""GPU parity of rank-revealing RCholeskyQR (Algorithm 7) against the oracle.
+
+Compared where the result is unique: the rank, the first r pivots (the
+dropped columns are noise-level and their order is not determined), Q's r
+columns and R with its columns put back in X's order.  Both sides take the
+pivots by the same rule (largest remaining norm, first on ties); the GPU
+pivots the R factor of the normalised sketch, which has the sketch's column
+norms and inner products, so the decisions agree while the norms are apart.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_09953_amd as rq
+    rq.lib()
+    return rq
+
+
+def _gpu(a, dtype=None):
+    import torch
+    import paper_2210_09953_amd as rq
+    t = torch.from_numpy(np.asfortranarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return rq.fortran(t.to("cuda"))
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _low_rank(m, n, rho, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((m, rho)) @ rng.standard_normal((rho, n))
+    return np.asfortranarray(X * np.logspace(0, 2, n))
+
+
+def _back_to_x_order(R, piv):
+    out = np.zeros_like(R)
+    out[:, piv] = R
+    return out
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_rr_low_rank_f64(rq, orc, kind):
+    m, n, rho, k = 20000, 64, 20, 192
+    X = _low_rank(m, n, rho, 7)
+    Q, R, piv, r = rq.rr(_gpu(X), k, 5, kind, tau=1e-10)
+    ref = orc.rr_rcholqr(X, k, 5, kind, tau=1e-10)
+    assert r == ref["rank"] == rho
+    piv = _np(piv)
+    assert np.array_equal(piv[:r], ref["piv"][:r])
+    Q, R = _np(Q), _np(R)
+    assert np.linalg.norm(Q - ref["Q"]) <= 1e-9 * np.linalg.norm(ref["Q"])
+    Rx, Rx_ref = _back_to_x_order(R, piv), _back_to_x_order(ref["R"], ref["piv"])
+    assert np.linalg.norm(Rx - Rx_ref) <= 1e-9 * np.linalg.norm(Rx_ref)
+    XP = X[:, piv]
+    err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
+    assert err.max() <= 1e-8
+    assert np.linalg.cond(Q) <= 10
+
+
+def test_rr_full_rank_ill_conditioned_f64(rq, orc):
+    """kappa = 1e14: Q stays well-conditioned (the unconditional stability of
+    Algorithm 7) and X Pi = Q R to working accuracy on the kept columns."""
+    m, n, k = 30000, 40, 120
+    X = synth.make_x(m, n, 1e-14, seed=8)
+    Q, R, piv, r = rq.rr(_gpu(X), k, 3, 0, tau=1e-15)
+    ref = orc.rr_rcholqr(X, k, 3, 0, tau=1e-15)
+    assert abs(r - ref["rank"]) <= 1
+    Q, R, piv = _np(Q), _np(R), _np(piv)
+    assert np.linalg.cond(Q) <= 20
+    XP = X[:, piv[:r]]
+    err = np.linalg.norm(XP - Q @ R[:, :r], axis=0) / np.linalg.norm(XP, axis=0)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["F32", "MIXED"])
+def test_rr_low_rank_f32_and_mixed(rq, orc, precision):
+    m, n, rho, k = 40000, 64, 24, 192
+    X = _low_rank(m, n, rho, 11).astype(np.float32)
+    Q, R, piv, r = rq.rr(_gpu(X), k, 9, rq.RADEMACHER, precision=getattr(rq, precision),
+                         tau=1e-5)
+    ref = orc.rr_rcholqr(X.astype(np.float64), k, 9, orc.RADEMACHER, tau=1e-5)
+    assert r == ref["rank"] == rho
+    piv = _np(piv)
+    assert np.array_equal(piv[:r], ref["piv"][:r])
+    Q, R = _np(Q).astype(np.float64), _np(R)
+    XP = X.astype(np.float64)[:, piv]
+    err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
+    print(f"rr {precision}: max column error {err.max():.2e} cond(Q) {np.linalg.cond(Q):.2f}")
+    assert err.max() <= 1e-4
+    assert np.linalg.cond(Q) <= 10
