@@ -274,6 +274,42 @@ def reduced_leg(torch, rq, X, k, l, kind, prec_code, steps, warmup, seed=1):
     return ms, orth_s, st
 
 
+def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, seed=1):
+    """Rank-revealing RCholeskyQR (Algorithm 7) on the same X.  Returns ms per
+    call (the rank read after the timed region), the rank and cond(Q)."""
+    m, n = X.shape
+    ws = torch.empty(int(rq.lib().rcholqr_rr_workspace_bytes(m, n, k, kind, prec_code)),
+                     dtype=torch.uint8, device="cuda")
+    Q = rq.empty_fortran(m, n, X.dtype)
+    R = rq.empty_fortran(n, n, torch.float64)
+    piv = torch.empty(n, dtype=torch.int32, device="cuda")
+    rank = torch.empty(1, dtype=torch.int32, device="cuda")
+    L = rq.lib()
+    import ctypes
+
+    def call():
+        code = L.rcholqr_rr(ctypes.c_void_p(X.data_ptr()), m, n, max(X.stride(1), m), k, seed,
+                            kind, prec_code, float(tau), ctypes.c_void_p(Q.data_ptr()), m,
+                            ctypes.c_void_p(R.data_ptr()), n, ctypes.c_void_p(piv.data_ptr()),
+                            ctypes.c_void_p(rank.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                            ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if code != 0:
+            raise RuntimeError(f"rcholqr_rr: {code}")
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    r = int(rank.item())
+    s = torch.linalg.svdvals(Q[:, :r].double().T @ Q[:, :r].double())
+    return ms, r, float(torch.sqrt(s[0] / s[-1]))
+
+
 def cpu_baseline(Xs_np, k, kind_code, budget_s=15.0):
     """FP64 CPU oracle (test infrastructure) on the first rows of X.
 
@@ -306,6 +342,8 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-reduced-leg", action="store_true",
                     help="skip the Reduced RCholeskyQR figure")
+    ap.add_argument("--no-rr-leg", action="store_true",
+                    help="skip the rank-revealing RCholeskyQR figure")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -378,6 +416,16 @@ def main():
         log(f"[bench] reduced (l={l}): {ms_r:.3f} ms/step {red['value']} GB/s "
             f"||S^T S - I|| = {orth_s:.2e}")
 
+    # Rank-revealing RCholeskyQR on the same X.
+    rrf = None
+    if not args.no_rr_leg:
+        tau = 1e-10
+        ms_rr, r_rr, cond_q = rr_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup, tau)
+        rrf = {"value": round(m * n * xbytes / (ms_rr * 1e-3) / 1e9, 2), "unit": "GB/s",
+               "ms_per_step": round(ms_rr, 4), "tau": tau, "rank": r_rr, "cond_Q": cond_q}
+        log(f"[bench] rank-revealing: {ms_rr:.3f} ms/step {rrf['value']} GB/s rank {r_rr} "
+            f"cond(Q) {cond_q:.3f}")
+
     fp64 = None
     if not args.no_fp64_leg and prec != "f64":
         X64 = X.double()
@@ -423,6 +471,7 @@ def main():
         "phase_rooflines": phase_roof,
         "fp64": fp64,
         "reduced": red,
+        "rank_revealing": rrf,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

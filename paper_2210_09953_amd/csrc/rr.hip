@@ -49,58 +49,78 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const T* __restric
   if (lane == 0) part[static_cast<int64_t>(s) * n + c] = t;
 }
 
-// d[c] = sqrt(sum over splits in order); P(:, c) /= d[c] (a zero column stays
-// zero).  One thread per column.
-__global__ void colnorm_scale_kernel(const double* __restrict__ part, int nsplit, int n,
-                                     double* __restrict__ d, double* __restrict__ P, int k,
-                                     int64_t ldp) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// d[c] = sqrt(sum of the split partials, a fixed-order block reduction);
+// P(:, c) /= d[c] (a zero column stays zero).  One workgroup per column.
+__global__ __launch_bounds__(256) void colnorm_scale_kernel(const double* __restrict__ part,
+                                                            int nsplit, int n,
+                                                            double* __restrict__ d,
+                                                            double* __restrict__ P, int k,
+                                                            int64_t ldp) {
+  __shared__ double red[4];
+  const int c = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int i = 0; i < nsplit; ++i) s += part[static_cast<int64_t>(i) * n + c];
+  for (int i = t; i < nsplit; i += 256) s += part[static_cast<int64_t>(i) * n + c];
+  s = block_sum(s, red);
   const double dc = sqrt(s);
-  d[c] = dc;
+  if (t == 0) d[c] = dc;
   const double inv = (dc > 0.0) ? 1.0 / dc : 0.0;
   double* pc = P + static_cast<int64_t>(c) * ldp;
-  for (int i = 0; i < k; ++i) pc[i] *= inv;
+  for (int i = t; i < k; i += 256) pc[i] *= inv;
 }
 
 // Householder QR with column pivoting of the n x n upper triangular Rp (ld
-// n).  W (n x n, row-major scratch) is the working matrix; thread c owns
-// column c.  Step j: the remaining column of largest norm over rows j..
-// (norms carried from the previous step's update, first index on ties) is
-// swapped to j, reflected (alpha = -sign(x_j) ||x||), and the reflector is
-// applied to the columns right of it.  Out: Rt (ld n, column-major, positive
-// diagonal: rows flipped with alpha), piv.
-__global__ __launch_bounds__(256) void qrcp_kernel(const double* __restrict__ Rp, int n,
-                                                   double* __restrict__ W,
-                                                   double* __restrict__ Rt, int* __restrict__ piv) {
+// n).  W (n x n, row-major scratch) is the working matrix; column c belongs
+// to the four threads c + 256 q, thread q taking rows 64 q .. 64 q + 63; the
+// four partial sums of a column are added in q order.  Step j: the
+// remaining column of largest norm over rows j.. (carried from the previous
+// step's update, first index on ties) is swapped to j, reflected (alpha =
+// -sign(x_j) ||x||), and the reflector is applied to the columns right of
+// it.  Out: Rt (ld n, column-major, positive diagonal: rows flipped with
+// alpha), the same factor row-major in W, piv.
+constexpr int kQcpThreads = 4 * kMaxN;
+
+__global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restrict__ Rp, int n,
+                                                           double* __restrict__ W,
+                                                           double* __restrict__ Rt,
+                                                           int* __restrict__ piv) {
   __shared__ double v[kMaxN];
   __shared__ double nrm2[kMaxN];
   __shared__ double sgn[kMaxN];
+  __shared__ double qpart[4][kMaxN];
   __shared__ int pcol[kMaxN];
   __shared__ int pivot;
   __shared__ double hb[2];  // beta, alpha
-  const int c = threadIdx.x, lane = c & 63;
-  if (c < n) {
+  const int tid = threadIdx.x, c = tid & (kMaxN - 1), q = tid >> 8, lane = tid & 63;
+  const int i0 = 64 * q;
+  const bool col = c < n;
+  // start: W = Rp (upper part), column norms
+  {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double x = (i <= c) ? Rp[i + static_cast<int64_t>(c) * n] : 0.0;
-      W[static_cast<int64_t>(i) * n + c] = x;
-      s += x * x;
-    }
-    nrm2[c] = s;
-    pcol[c] = c;
+    if (col)
+      for (int u = 0; u < 64; ++u) {
+        const int i = i0 + u;
+        if (i < n) {
+          const double x = (i <= c) ? Rp[i + static_cast<int64_t>(c) * n] : 0.0;
+          W[static_cast<int64_t>(i) * n + c] = x;
+          s += x * x;
+        }
+      }
+    qpart[q][c] = s;
+  }
+  __syncthreads();
+  if (tid < kMaxN && tid < n) {
+    nrm2[tid] = ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid];
+    pcol[tid] = tid;
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     // pivot: wave 0 scans the candidates c >= j (4 per lane), largest norm,
     // lowest index among equal ones
-    if (c < 64) {
+    if (tid < 64) {
       double best = -1.0;
       int bi = n;
-      for (int q = 0; q < 4; ++q) {
-        const int cc = lane + 64 * q;
+      for (int qq = 0; qq < 4; ++qq) {
+        const int cc = lane + 64 * qq;
         if (cc >= j && cc < n && nrm2[cc] > best) {
           best = nrm2[cc];
           bi = cc;
@@ -116,12 +136,12 @@ __global__ __launch_bounds__(256) void qrcp_kernel(const double* __restrict__ Rp
     const int p = pivot;
     if (p != j) {
       // swap columns j and p (rows 0..n-1), their norms and labels
-      for (int i = c; i < n; i += blockDim.x) {
+      for (int i = tid; i < n; i += kQcpThreads) {
         const double a = W[static_cast<int64_t>(i) * n + j];
         W[static_cast<int64_t>(i) * n + j] = W[static_cast<int64_t>(i) * n + p];
         W[static_cast<int64_t>(i) * n + p] = a;
       }
-      if (c == 0) {
+      if (tid == 0) {
         const double t = nrm2[j];
         nrm2[j] = nrm2[p];
         nrm2[p] = t;
@@ -132,9 +152,9 @@ __global__ __launch_bounds__(256) void qrcp_kernel(const double* __restrict__ Rp
     }
     __syncthreads();
     // reflector of column j (rows j..n-1), from its norm (already known)
-    for (int i = j + c; i < n; i += blockDim.x) v[i] = W[static_cast<int64_t>(i) * n + j];
+    for (int i = j + tid; i < n; i += kQcpThreads) v[i] = W[static_cast<int64_t>(i) * n + j];
     __syncthreads();
-    if (c == 0) {
+    if (tid == 0) {
       const double x0 = v[j];
       const double nr = sqrt(nrm2[j]);
       const double alpha = (x0 >= 0.0) ? -nr : nr;
@@ -147,27 +167,63 @@ __global__ __launch_bounds__(256) void qrcp_kernel(const double* __restrict__ Rp
     }
     __syncthreads();
     const double beta = hb[0];
-    if (c > j && c < n) {
-      double w = 0.0;
-      for (int i = j; i < n; ++i) w += v[i] * W[static_cast<int64_t>(i) * n + c];
-      const double f = beta * w;
-      double s = 0.0;
-      for (int i = j; i < n; ++i) {
-        const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
-        W[static_cast<int64_t>(i) * n + c] = x;
-        if (i > j) s += x * x;
+    // this thread's rows of the trailing part: max(j, i0) .. min(n, i0 + 64)
+    const int lo = (j > i0) ? j : i0, hi = (i0 + 64 < n) ? i0 + 64 : n;
+    const bool upd = col && c > j;
+    {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (upd) {
+        int i = lo;
+        for (; i + 3 < hi; i += 4) {
+          a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
+          a1 += v[i + 1] * W[static_cast<int64_t>(i + 1) * n + c];
+          a2 += v[i + 2] * W[static_cast<int64_t>(i + 2) * n + c];
+          a3 += v[i + 3] * W[static_cast<int64_t>(i + 3) * n + c];
+        }
+        for (; i < hi; ++i) a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
       }
-      nrm2[c] = s;  // norm over rows j+1.. for the next pivot
-    } else if (c == j) {
-      W[static_cast<int64_t>(j) * n + j] = hb[1];
-      for (int i = j + 1; i < n; ++i) W[static_cast<int64_t>(i) * n + j] = 0.0;
+      qpart[q][c] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
+    {
+      const double f = upd ? beta * (((qpart[0][c] + qpart[1][c]) + qpart[2][c]) + qpart[3][c]) : 0.0;
+      __syncthreads();
+      double s0 = 0.0, s1 = 0.0;
+      if (upd) {
+        int i = lo;
+        for (; i + 1 < hi; i += 2) {
+          const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
+          const double y = W[static_cast<int64_t>(i + 1) * n + c] - f * v[i + 1];
+          W[static_cast<int64_t>(i) * n + c] = x;
+          W[static_cast<int64_t>(i + 1) * n + c] = y;
+          if (i > j) s0 += x * x;
+          s1 += y * y;  // i + 1 > j
+        }
+        for (; i < hi; ++i) {
+          const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
+          W[static_cast<int64_t>(i) * n + c] = x;
+          if (i > j) s0 += x * x;
+        }
+      } else if (col && c == j) {
+        for (int i = lo; i < hi; ++i) W[static_cast<int64_t>(i) * n + j] = (i == j) ? hb[1] : 0.0;
+      }
+      qpart[q][c] = s0 + s1;
+    }
+    __syncthreads();
+    if (tid < n && tid > j)  // norm over rows j+1.. for the next pivot
+      nrm2[tid] = ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid];
+    __syncthreads();
   }
-  if (c < n) {
-    for (int i = 0; i < n; ++i)
-      Rt[i + static_cast<int64_t>(c) * n] = (i <= c) ? sgn[i] * W[static_cast<int64_t>(i) * n + c] : 0.0;
-    piv[c] = pcol[c];
+  if (col) {
+    for (int u = 0; u < 64; ++u) {
+      const int i = i0 + u;
+      if (i < n) {
+        const double a = (i <= c) ? sgn[i] * W[static_cast<int64_t>(i) * n + c] : 0.0;
+        Rt[i + static_cast<int64_t>(c) * n] = a;
+        W[static_cast<int64_t>(i) * n + c] = a;
+      }
+    }
+    if (q == 0) piv[c] = pcol[c];
   }
 }
 
@@ -176,75 +232,106 @@ __global__ __launch_bounds__(256) void qrcp_kernel(const double* __restrict__ Rp
 // Rt_{1:r,:} diag(d[piv]) (rows >= r zero), Rs (ld n) the factor of the
 // solve (that block on 1:r, identity on the dropped columns), rank.  The
 // status word keeps only the non-finite flag (rank deficiency is expected).
-__global__ __launch_bounds__(256) void rr_finish_kernel(const double* __restrict__ Rt, int n,
-                                                        double tau, const double* __restrict__ d,
-                                                        const int* __restrict__ piv,
-                                                        double* __restrict__ R, int64_t ldr,
-                                                        double* __restrict__ Rs,
-                                                        int* __restrict__ rank,
-                                                        int* __restrict__ status) {
-  __shared__ double x[kMaxN], y[kMaxN], red[4];
+// Rt is read column-major for the products Rt x and row-major (Rw) for
+// Rt^T y, so that both are coalesced; output entry t of either product is
+// the sum of four quarter sums (threads t + 256 q over indices 64 q ..
+// 64 q + 63) added in q order.
+constexpr int kFinThreads = 4 * kMaxN;
+
+__global__ __launch_bounds__(kFinThreads) void rr_finish_kernel(
+    const double* __restrict__ Rt, const double* __restrict__ Rw, int n, double tau,
+    const double* __restrict__ d, const int* __restrict__ piv, double* __restrict__ R,
+    int64_t ldr, double* __restrict__ Rs, int* __restrict__ rank, int* __restrict__ status) {
+  __shared__ double x[kMaxN], y[kMaxN], qp[4][kMaxN], red[kFinThreads / 64];
   __shared__ double tail[kMaxN + 1];
   __shared__ int rr;
-  const int t = threadIdx.x;
-  if (t < n) x[t] = 1.0;
+  const int tid = threadIdx.x, t = tid & (kMaxN - 1), q = tid >> 8;
+  const int c0 = 64 * q, c1 = (c0 + 64 < n) ? c0 + 64 : n;
+  const bool live = t < n;
+  // quarter q of row t of Rt times x: columns max(t, c0) .. c1 (upper part)
+  auto row_part = [&](bool sq) -> double {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (live) {
+      int c = (t > c0) ? t : c0;
+      for (; c + 3 < c1; c += 4) {
+        const double r0 = Rt[t + static_cast<int64_t>(c) * n];
+        const double r1 = Rt[t + static_cast<int64_t>(c + 1) * n];
+        const double r2 = Rt[t + static_cast<int64_t>(c + 2) * n];
+        const double r3 = Rt[t + static_cast<int64_t>(c + 3) * n];
+        a0 += r0 * (sq ? r0 : x[c]);
+        a1 += r1 * (sq ? r1 : x[c + 1]);
+        a2 += r2 * (sq ? r2 : x[c + 2]);
+        a3 += r3 * (sq ? r3 : x[c + 3]);
+      }
+      for (; c < c1; ++c) {
+        const double r0 = Rt[t + static_cast<int64_t>(c) * n];
+        a0 += r0 * (sq ? r0 : x[c]);
+      }
+    }
+    return (a0 + a1) + (a2 + a3);
+  };
+  // y = Rt x, every thread gets ||y||^2
+  auto mul_rt = [&]() -> double {
+    qp[q][t] = row_part(false);
+    __syncthreads();
+    double yt = 0.0;
+    if (q == 0 && live) {
+      yt = ((qp[0][t] + qp[1][t]) + qp[2][t]) + qp[3][t];
+      y[t] = yt;
+    }
+    return block_sum(yt * yt, red);  // its barriers also publish y
+  };
+  if (tid < n) x[tid] = 1.0;
   __syncthreads();
   double sigma = 0.0;
   for (int it = 0; it < 64; ++it) {
     // y = Rt x, x = Rt^T y / ||Rt^T y||
-    if (t < n) {
-      double s = 0.0;
-      for (int c = t; c < n; ++c) s += Rt[t + static_cast<int64_t>(c) * n] * x[c];
-      y[t] = s;
-    }
-    __syncthreads();
-    double z = 0.0;
-    if (t < n)
-      for (int i = 0; i <= t; ++i) z += Rt[i + static_cast<int64_t>(t) * n] * y[i];
-    const double zz = block_sum(z * z, red);
-    const double yy = block_sum((t < n) ? y[t] * y[t] : 0.0, red);
+    const double yy = mul_rt();
     sigma = sqrt(yy);  // ||Rt x|| with ||x|| = 1 after the first step
-    const double inv = (zz > 0.0) ? 1.0 / sqrt(zz) : 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (live) {
+      // quarter q of column t of Rt times y: rows c0 .. min(c1, t + 1)
+      const int i1 = (c1 < t + 1) ? c1 : t + 1;
+      int i = c0;
+      for (; i + 3 < i1; i += 4) {
+        a0 += Rw[static_cast<int64_t>(i) * n + t] * y[i];
+        a1 += Rw[static_cast<int64_t>(i + 1) * n + t] * y[i + 1];
+        a2 += Rw[static_cast<int64_t>(i + 2) * n + t] * y[i + 2];
+        a3 += Rw[static_cast<int64_t>(i + 3) * n + t] * y[i + 3];
+      }
+      for (; i < i1; ++i) a0 += Rw[static_cast<int64_t>(i) * n + t] * y[i];
+    }
+    qp[q][t] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    if (t < n) x[t] = z * inv;
+    const double z = (q == 0 && live) ? ((qp[0][t] + qp[1][t]) + qp[2][t]) + qp[3][t] : 0.0;
+    const double zz = block_sum(z * z, red);
+    const double inv = (zz > 0.0) ? 1.0 / sqrt(zz) : 0.0;
+    if (q == 0 && live) x[t] = z * inv;
     __syncthreads();
   }
   // ||Rt x|| for the final unit x
-  if (t < n) {
-    double s = 0.0;
-    for (int c = t; c < n; ++c) s += Rt[t + static_cast<int64_t>(c) * n] * x[c];
-    y[t] = s;
-  }
-  const double yy = block_sum((t < n) ? y[t] * y[t] : 0.0, red);
-  sigma = fmax(sigma, sqrt(yy));
+  sigma = fmax(sigma, sqrt(mul_rt()));
   // row sums of squares, suffix sums in order
-  if (t < n) {
-    double s = 0.0;
-    for (int c = t; c < n; ++c) {
-      const double a = Rt[t + static_cast<int64_t>(c) * n];
-      s += a * a;
-    }
-    y[t] = s;
-  }
+  qp[q][t] = row_part(true);
   __syncthreads();
-  if (t == 0) {
+  if (q == 0 && live) y[t] = ((qp[0][t] + qp[1][t]) + qp[2][t]) + qp[3][t];
+  const int bad = __syncthreads_or((tid < n && !isfinite(d[tid])) ? 1 : 0);
+  if (tid == 0) {
     tail[n] = 0.0;
     for (int i = n - 1; i >= 0; --i) tail[i] = tail[i + 1] + y[i];
     int r = n;
-    for (int q = 0; q <= n; ++q)
-      if (sqrt(tail[q]) <= tau * sigma) {
-        r = q;
+    for (int k = 0; k <= n; ++k)
+      if (sqrt(tail[k]) <= tau * sigma) {
+        r = k;
         break;
       }
     rr = r;
     *rank = r;
-    bool bad = !isfinite(sigma);
-    for (int c = 0; c < n; ++c) bad = bad || !isfinite(d[c]);
-    *status = bad ? 2 : 0;
+    *status = (bad || !isfinite(sigma)) ? 2 : 0;
   }
   __syncthreads();
   const int r = rr;
-  for (int idx = t; idx < n * n; idx += blockDim.x) {
+  for (int idx = tid; idx < n * n; idx += kFinThreads) {
     const int i = idx % n, c = idx / n;
     const double v = (i < r && i <= c) ? Rt[i + static_cast<int64_t>(c) * n] * d[piv[c]] : 0.0;
     R[i + static_cast<int64_t>(c) * ldr] = v;
@@ -293,11 +380,12 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
     else
       colnorm_partial_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(X), m, n,
                                                             ldx, rows, part);
-    colnorm_scale_kernel<<<1, 256, 0, st>>>(part, kRrSplits, n, d, P, k, k);
+    colnorm_scale_kernel<<<n, 256, 0, st>>>(part, kRrSplits, n, d, P, k, k);
     return hipGetLastError();
   }
-  qrcp_kernel<<<1, 256, 0, st>>>(Rp, n, W, Rt, piv_out);
-  rr_finish_kernel<<<1, 256, 0, st>>>(Rt, n, tau, d, piv_out, R, ldr, Rs, rank_out, status);
+  qrcp_kernel<<<1, kQcpThreads, 0, st>>>(Rp, n, W, Rt, piv_out);
+  rr_finish_kernel<<<1, kFinThreads, 0, st>>>(Rt, W, n, tau, d, piv_out, R, ldr, Rs, rank_out,
+                                              status);
   return hipGetLastError();
 }
 

@@ -50,9 +50,11 @@ def _back_to_x_order(R, piv):
     return out
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_rr_low_rank_f64(rq, orc, kind):
-    m, n, rho, k = 20000, 64, 20, 192
+@pytest.mark.parametrize("kind,n,rho", [(0, 64, 20), (1, 64, 20), (0, 200, 77), (1, 256, 190)])
+def test_rr_low_rank_f64(rq, orc, kind, n, rho):
+    """n = 200 and 256 span the four row quarters of the pivoted QR's threads
+    (200 with a ragged last quarter)."""
+    m, k = 20000, 3 * n
     X = _low_rank(m, n, rho, 7)
     Q, R, piv, r = rq.rr(_gpu(X), k, 5, kind, tau=1e-10)
     ref = orc.rr_rcholqr(X, k, 5, kind, tau=1e-10)
