@@ -274,11 +274,11 @@ def reduced_leg(torch, rq, X, k, l, kind, prec_code, steps, warmup, seed=1):
     return ms, orth_s, st
 
 
-def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, seed=1):
+def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, passes=1, seed=1):
     """Rank-revealing RCholeskyQR (Algorithm 7) on the same X.  Returns ms per
     call (the rank read after the timed region), the rank and cond(Q)."""
     m, n = X.shape
-    ws = torch.empty(int(rq.lib().rcholqr_rr_workspace_bytes(m, n, k, kind, prec_code)),
+    ws = torch.empty(int(rq.lib().rcholqr_rr_workspace_bytes(m, n, k, kind, prec_code, passes)),
                      dtype=torch.uint8, device="cuda")
     Q = rq.empty_fortran(m, n, X.dtype)
     R = rq.empty_fortran(n, n, torch.float64)
@@ -289,7 +289,7 @@ def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, seed=1):
 
     def call():
         code = L.rcholqr_rr(ctypes.c_void_p(X.data_ptr()), m, n, max(X.stride(1), m), k, seed,
-                            kind, prec_code, float(tau), ctypes.c_void_p(Q.data_ptr()), m,
+                            kind, prec_code, passes, float(tau), ctypes.c_void_p(Q.data_ptr()), m,
                             ctypes.c_void_p(R.data_ptr()), n, ctypes.c_void_p(piv.data_ptr()),
                             ctypes.c_void_p(rank.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                             ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
@@ -306,8 +306,10 @@ def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, seed=1):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     r = int(rank.item())
-    s = torch.linalg.svdvals(Q[:, :r].double().T @ Q[:, :r].double())
-    return ms, r, float(torch.sqrt(s[0] / s[-1]))
+    G = Q[:, :r].double().T @ Q[:, :r].double()
+    s = torch.linalg.svdvals(G)
+    orth = float(torch.linalg.matrix_norm(G - torch.eye(r, dtype=G.dtype, device=G.device), 2))
+    return ms, r, float(torch.sqrt(s[0] / s[-1])), orth
 
 
 def cpu_baseline(Xs_np, k, kind_code, budget_s=15.0):
@@ -420,11 +422,19 @@ def main():
     rrf = None
     if not args.no_rr_leg:
         tau = 1e-10
-        ms_rr, r_rr, cond_q = rr_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup, tau)
+        ms_rr, r_rr, cond_q, _ = rr_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup,
+                                        tau)
         rrf = {"value": round(m * n * xbytes / (ms_rr * 1e-3) / 1e9, 2), "unit": "GB/s",
                "ms_per_step": round(ms_rr, 4), "tau": tau, "rank": r_rr, "cond_Q": cond_q}
         log(f"[bench] rank-revealing: {ms_rr:.3f} ms/step {rrf['value']} GB/s rank {r_rr} "
             f"cond(Q) {cond_q:.3f}")
+        ms2, r2, cond2, orth2 = rr_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup,
+                                       tau, passes=2)
+        rrf["two_pass"] = {"value": round(m * n * xbytes / (ms2 * 1e-3) / 1e9, 2),
+                           "unit": "GB/s", "ms_per_step": round(ms2, 4), "rank": r2,
+                           "orth": orth2}
+        log(f"[bench] rank-revealing, 2 passes: {ms2:.3f} ms/step {rrf['two_pass']['value']} "
+            f"GB/s rank {r2} ||Q^T Q - I|| = {orth2:.2e}")
 
     fp64 = None
     if not args.no_fp64_leg and prec != "f64":

@@ -145,25 +145,30 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
  * column pivoting: largest remaining column norm, the first on ties); r =
  * the least r with ||R_{r+1:n,r+1:n}||_F <= tau ||R||_2; Q = X Pi_{:,1:r}
  * (R_{1:r,1:r} Pi^T D Pi)^{-1} by the tall forward substitution; R <-
- * R_{1:r,:} Pi^T D Pi.
+ * R_{1:r,:} Pi^T D Pi.  With passes = 2 (RRRCholeskyQR2, Section 4) one
+ * Cholesky QR pass follows on the r columns of Q: G = Q^T Q = R'^T R',
+ * Q <- Q R'^{-1}, R <- R' R (Algorithm 3 steps 2-4).
  *
  *  X, m, n, ldx, k, seed, sketch_kind, precision  as rcholqr_factor.
+ *  passes 1 (Algorithm 7) or 2 (with the Cholesky QR pass).  passes = 2
+ *         reads r back to the host: the call then waits for the stream.
  *  tau    truncation tolerance (>= 0).
  *  Q      [out] m x n buffer (ld ldq >= m, FP64 or FP32 as X): columns 0..r-1
  *         hold Q; columns r.. hold the dropped columns of X Pi (unscaled).
  *  R      [out] n x n FP64 (ld ldr): rows 0..r-1 hold R, rows r.. are zero.
  *  piv    [out] n int32 on the device: column j of X Pi is column piv[j] of X.
- *  rank   [out] one int32 on the device: r (read it after the stream has
- *         finished; the call never synchronises).
- *  ws     rcholqr_rr_workspace_bytes(m, n, k, kind, precision) bytes; status
- *         word 0, or 2 for non-finite X.
+ *  rank   [out] one int32 on the device: r (with passes = 1 read it after
+ *         the stream has finished; that call never synchronises).
+ *  ws     rcholqr_rr_workspace_bytes(m, n, k, kind, precision, passes)
+ *         bytes; status word 0, 2 for non-finite X, or 1000 + j when the
+ *         second pass's Cholesky breaks down at column j.
  * Returns 0, -i for invalid argument i (1-based), or RCHOLQR_ERR_HIP. */
 size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
-                                  int precision);
+                                  int precision, int passes);
 int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
-               uint64_t seed, int sketch_kind, int precision, double tau, void* Q,
-               int64_t ldq, double* R, int64_t ldr, int* piv, int* rank, void* ws,
-               size_t ws_bytes, void* stream);
+               uint64_t seed, int sketch_kind, int precision, int passes, double tau,
+               void* Q, int64_t ldq, double* R, int64_t ldr, int* piv, int* rank,
+               void* ws, size_t ws_bytes, void* stream);
 
 /* Read the status word of a workspace used by a completed call
  * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.

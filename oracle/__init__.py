@@ -13,6 +13,8 @@ Cholesky QR factorizations":
 * ``reduced_rcholqr``   -- Algorithm 5 (Reduced RCholeskyQR, Section 3.3)
 * ``qrcp``/``rr_rcholqr`` -- Algorithm 7 (rank-revealing RCholeskyQR, Section 4)
                            with QR with column pivoting as its RRQR step
+* ``rr_rcholqr2``       -- RRRCholeskyQR2 (Section 4): Algorithm 7 and one
+                           Cholesky QR pass (Algorithm 3 steps 2-4)
 * ``qr_backward``       -- reverse-mode derivative of the positive-diagonal
                            thin QR (not in the paper; standard identity)
 
@@ -269,6 +271,23 @@ def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12):
     Q = trsm_rows(np.asfortranarray(X[:, piv[:r]]), np.asfortranarray(Rout[:, :r])) if r else \
         np.zeros((m, 0), order="F")
     return dict(Q=Q, R=Rout, piv=piv, rank=r, Rn=Rn)
+
+
+def rr_rcholqr2(X, k, seed, kind=GAUSSIAN, tau=1e-12):
+    """RRRCholeskyQR2 (Section 4): Algorithm 7, then one Cholesky QR pass on
+    the r kept columns as in Algorithm 3 steps 2-4: G = Q^T Q = R'^T R',
+    Q <- Q R'^{-1}, R <- R' R.  Returns rr_rcholqr's dict with Q and R
+    replaced and the Cholesky's status."""
+    out = rr_rcholqr(X, k, seed, kind, tau)
+    r = out["rank"]
+    out["status"] = 0
+    if r == 0:
+        return out
+    Rp, st = cholesky_upper(gram(out["Q"]))
+    out["Q"] = trsm_rows(out["Q"], Rp)
+    out["R"] = np.asfortranarray(np.triu(Rp) @ out["R"])
+    out["status"] = int(st)
+    return out
 
 
 def qr_backward(Q, R, dQ, dR):

@@ -110,6 +110,18 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   return L;
 }
 
+// Gram partials of the second rank-revealing pass: the largest over the
+// possible ranks r = 1..n of the r-column plan.
+size_t rr_second_gram_bytes(int64_t m, int64_t n, int prec) {
+  size_t most = 0;
+  for (int64_t r = 1; r <= n; ++r) {
+    const GramPlan gp = make_layout(m, r, r, kGaussian, 2, prec).gp;
+    const size_t b = align256(static_cast<size_t>(gp.nsplit) * gp.npg * gp.npg * sizeof(double));
+    if (b > most) most = b;
+  }
+  return most;
+}
+
 template <typename T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
@@ -558,17 +570,19 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
 // Householder of P D^{-1}, column-pivoted QR of its R, rank rule and the
 // factors, gather X Pi into Q, tall solve in place.
 size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
-                                  int precision) {
+                                  int precision, int passes) {
   if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 2 || precision < 0 ||
-      precision > 2)
+      precision > 2 || passes < 1 || passes > 2)
     return 0;
   return align256(make_layout(m, n, k, sketch_kind, 1, precision).total) +
-         align256(rr_extra_bytes(static_cast<int>(n)));
+         align256(rr_extra_bytes(static_cast<int>(n))) +
+         (passes == 2 ? rr_second_gram_bytes(m, n, precision) : 0);
 }
 
 int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
-               int sketch_kind, int precision, double tau, void* Q, int64_t ldq, double* R,
-               int64_t ldr, int* piv, int* rank, void* ws, size_t ws_bytes, void* stream) {
+               int sketch_kind, int precision, int passes, double tau, void* Q, int64_t ldq,
+               double* R, int64_t ldr, int* piv, int* rank, void* ws, size_t ws_bytes,
+               void* stream) {
   if (!X) return -1;
   if (n < 1 || n > kMaxN) return -3;
   if (m < n) return -2;
@@ -577,21 +591,24 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   if (sketch_kind < 0 || sketch_kind > 2) return -7;
   if (precision < 0 || precision > 2) return -8;
   if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
-  if (!(tau >= 0.0) || !isfinite(tau)) return -9;
-  if (!Q) return -10;
-  if (ldq < m) return -11;
-  if (!R) return -12;
-  if (ldr < n) return -13;
-  if (!piv) return -14;
-  if (!rank) return -15;
-  if (!ws) return -16;
+  if (passes < 1 || passes > 2) return -9;
+  if (!(tau >= 0.0) || !isfinite(tau)) return -10;
+  if (!Q) return -11;
+  if (ldq < m) return -12;
+  if (!R) return -13;
+  if (ldr < n) return -14;
+  if (!piv) return -15;
+  if (!rank) return -16;
+  if (!ws) return -17;
   const Layout L = make_layout(m, n, k, sketch_kind, 1, precision);
-  if (ws_bytes < align256(L.total) + align256(rr_extra_bytes(static_cast<int>(n)))) return -17;
+  const size_t extra_off = align256(L.total);
+  const size_t gram_off = extra_off + align256(rr_extra_bytes(static_cast<int>(n)));
+  if (ws_bytes < gram_off + (passes == 2 ? rr_second_gram_bytes(m, n, precision) : 0)) return -18;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool f32 = precision != kPrecF64;
   const int ni = static_cast<int>(n), ki = static_cast<int>(k);
   double* P = at<double>(ws, L.P);
-  unsigned char* extra = at<unsigned char>(ws, align256(L.total));
+  unsigned char* extra = at<unsigned char>(ws, extra_off);
   int* status = at<int>(ws, L.status);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
@@ -611,6 +628,28 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   void* pan = at<void>(ws, L.pan);
   RCQ_TRY(launch_make_panels(Rsolve, n, ni, f32, pan, st));
   RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  if (passes == 1) return 0;
+  // RRRCholeskyQR2: one Cholesky QR pass (Algorithm 3 steps 2-4) over the r
+  // kept columns of Q; r is read back first (the only synchronisation).
+  int r = 0;
+  RCQ_TRY(hipMemcpyAsync(&r, rank, sizeof(int), hipMemcpyDeviceToHost, st));
+  RCQ_TRY(hipStreamSynchronize(st));
+  if (r < 1 || r > ni) return 0;
+  const GramPlan gp = make_layout(m, r, r, kGaussian, 2, precision).gp;
+  double* G = at<double>(ws, L.G);
+  RCQ_TRY(launch_gram(Q, f32, m, r, ldq, gp, at<double>(ws, gram_off), st));
+  RCQ_TRY(launch_gram_reduce(at<double>(ws, gram_off), gp, r, G, st));
+  RCQ_TRY(launch_cholesky(G, r, gp.npg, status, st));
+  RCQ_TRY(launch_left_upper(G, gp.npg, r, R, ldr, ni, st));
+  double* Tinv = at<double>(ws, L.Tinv);
+  RCQ_TRY(launch_set_identity(Tinv, r, r, r, st));
+  RCQ_TRY(launch_make_panels(G, gp.npg, r, false, pan, st));
+  RCQ_TRY(launch_trsm(Tinv, false, r, r, r, pan, Tinv, r, st));
+  if (f32)
+    RCQ_TRY(launch_make_bf3_panels(Tinv, r, r, pan, st));
+  else
+    RCQ_TRY(launch_make_panels(Tinv, r, r, false, pan, st, false));
+  RCQ_TRY(launch_trmm(Q, f32, m, r, ldq, pan, st));
   return 0;
 }
 

@@ -63,6 +63,9 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
                            int k, const double* Rp, double tau, unsigned char* extra,
                            double* R, int64_t ldr, int* piv_out, int* rank_out, int* status,
                            double** Rs_out, hipStream_t st, int stage);
+// R(0:r, 0:n) <- U R(0:r, 0:n), U upper triangular r x r (second pass).
+hipError_t launch_left_upper(const double* U, int64_t ldu, int r, double* R, int64_t ldr, int n,
+                             hipStream_t st);
 hipError_t launch_gather_cols(const void* X, bool f32, int64_t m, int n, int64_t ldx,
                               const int* piv, void* Q, int64_t ldq, hipStream_t st);
 

@@ -69,161 +69,149 @@ __global__ __launch_bounds__(256) void colnorm_scale_kernel(const double* __rest
 }
 
 // Householder QR with column pivoting of the n x n upper triangular Rp (ld
-// n).  W (n x n, row-major scratch) is the working matrix; column c belongs
-// to the four threads c + 256 q, thread q taking rows 64 q .. 64 q + 63; the
-// four partial sums of a column are added in q order.  Step j: the
-// remaining column of largest norm over rows j.. (carried from the previous
-// step's update, first index on ties) is swapped to j, reflected (alpha =
-// -sign(x_j) ||x||), and the reflector is applied to the columns right of
-// it.  Out: Rt (ld n, column-major, positive diagonal: rows flipped with
-// alpha), the same factor row-major in W, piv.
+// n).  W (n x n, row-major scratch) is the working matrix, kept in its
+// original column order: column c belongs to the four threads c + 256 q,
+// thread q taking the rows i = q mod 4, and the pivoted order is kept as a
+// permutation (pos: position of a column, colat: column at a position).
+// Step j: among the columns at positions >= j, the one of largest norm over
+// rows j.. (recomputed from the previous update, lowest position on ties)
+// goes to position j; its reflector (alpha = -sign(x_j) ||x||) is applied to
+// the columns still unplaced.  Three barriers a step: after the reflector
+// load, after the products, after the update.  Out: Rt (ld n, column-major,
+// pivoted order, positive diagonal: rows flipped with alpha), the same
+// factor row-major in Rw, piv.
 constexpr int kQcpThreads = 4 * kMaxN;
 
 __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restrict__ Rp, int n,
                                                            double* __restrict__ W,
                                                            double* __restrict__ Rt,
+                                                           double* __restrict__ Rw,
                                                            int* __restrict__ piv) {
   __shared__ double v[kMaxN];
-  __shared__ double nrm2[kMaxN];
   __shared__ double sgn[kMaxN];
-  __shared__ double qpart[4][kMaxN];
-  __shared__ int pcol[kMaxN];
-  __shared__ int pivot;
-  __shared__ double hb[2];  // beta, alpha
+  __shared__ double dotp[4][kMaxN];  // reflector products, by row class
+  __shared__ double nrmp[4][kMaxN];  // squared norms below the current row, by row class
+  __shared__ int pos[kMaxN];
+  __shared__ int colat[kMaxN];
   const int tid = threadIdx.x, c = tid & (kMaxN - 1), q = tid >> 8, lane = tid & 63;
-  const int i0 = 64 * q;
   const bool col = c < n;
-  // start: W = Rp (upper part), column norms
   {
     double s = 0.0;
     if (col)
-      for (int u = 0; u < 64; ++u) {
-        const int i = i0 + u;
-        if (i < n) {
-          const double x = (i <= c) ? Rp[i + static_cast<int64_t>(c) * n] : 0.0;
-          W[static_cast<int64_t>(i) * n + c] = x;
-          s += x * x;
-        }
+      for (int i = q; i < n; i += 4) {
+        const double x = (i <= c) ? Rp[i + static_cast<int64_t>(c) * n] : 0.0;
+        W[static_cast<int64_t>(i) * n + c] = x;
+        s += x * x;
       }
-    qpart[q][c] = s;
+    nrmp[q][c] = s;
+    if (tid < kMaxN) {
+      pos[tid] = tid;
+      colat[tid] = tid;
+    }
   }
-  __syncthreads();
-  if (tid < kMaxN && tid < n) {
-    nrm2[tid] = ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid];
-    pcol[tid] = tid;
-  }
+  bool placed = false;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    // pivot: wave 0 scans the candidates c >= j (4 per lane), largest norm,
-    // lowest index among equal ones
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int qq = 0; qq < 4; ++qq) {
-        const int cc = lane + 64 * qq;
-        if (cc >= j && cc < n && nrm2[cc] > best) {
-          best = nrm2[cc];
-          bi = cc;
+    // pivot, found by every wave alike (4 columns a lane)
+    double best = -1.0;
+    int bpos = n;
+    for (int qq = 0; qq < 4; ++qq) {
+      const int cc = lane + 64 * qq;
+      if (cc < n) {
+        const int pc = pos[cc];
+        if (pc >= j) {
+          double a = ((nrmp[0][cc] + nrmp[1][cc]) + nrmp[2][cc]) + nrmp[3][cc];
+          if (!(a >= 0.0)) a = -0.5;  // a NaN norm takes the lowest priority
+          if (a > best || (a == best && pc < bpos)) {
+            best = a;
+            bpos = pc;
+          }
         }
       }
-      double mx = best;
-      for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-      int cand = (best == mx) ? bi : n;
-      for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
-      if (lane == 0) pivot = cand;
     }
+    double mx = best;
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    int cand = (best == mx) ? bpos : n;
+    for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
+    const int p = colat[cand];
+    const double nr2 = ((nrmp[0][p] + nrmp[1][p]) + nrmp[2][p]) + nrmp[3][p];
+    for (int i = j + tid; i < n; i += kQcpThreads) v[i] = W[static_cast<int64_t>(i) * n + p];
     __syncthreads();
-    const int p = pivot;
-    if (p != j) {
-      // swap columns j and p (rows 0..n-1), their norms and labels
-      for (int i = tid; i < n; i += kQcpThreads) {
-        const double a = W[static_cast<int64_t>(i) * n + j];
-        W[static_cast<int64_t>(i) * n + j] = W[static_cast<int64_t>(i) * n + p];
-        W[static_cast<int64_t>(i) * n + p] = a;
-      }
-      if (tid == 0) {
-        const double t = nrm2[j];
-        nrm2[j] = nrm2[p];
-        nrm2[p] = t;
-        const int l = pcol[j];
-        pcol[j] = pcol[p];
-        pcol[p] = l;
-      }
-    }
-    __syncthreads();
-    // reflector of column j (rows j..n-1), from its norm (already known)
-    for (int i = j + tid; i < n; i += kQcpThreads) v[i] = W[static_cast<int64_t>(i) * n + j];
-    __syncthreads();
+    const double x0 = v[j];
+    const double nr = sqrt(nr2);
+    const double alpha = (x0 >= 0.0) ? -nr : nr;
+    const double v0 = x0 - alpha;
+    const double vtv = v0 * v0 + (nr2 - x0 * x0);
+    const double beta = (vtv > 0.0 && nr > 0.0) ? 2.0 / vtv : 0.0;
+    const double rjj = (nr > 0.0) ? alpha : x0;
     if (tid == 0) {
-      const double x0 = v[j];
-      const double nr = sqrt(nrm2[j]);
-      const double alpha = (x0 >= 0.0) ? -nr : nr;
-      const double v0 = x0 - alpha;
-      const double vtv = v0 * v0 + (nrm2[j] - x0 * x0);
-      v[j] = v0;
-      hb[0] = (vtv > 0.0 && nr > 0.0) ? 2.0 / vtv : 0.0;
-      hb[1] = (nr > 0.0) ? alpha : x0;
-      sgn[j] = (hb[1] < 0.0) ? -1.0 : 1.0;
+      sgn[j] = (rjj < 0.0) ? -1.0 : 1.0;
+      const int cj = colat[j], pp = pos[p];
+      pos[cj] = pp;
+      colat[pp] = cj;
+      pos[p] = j;
+      colat[j] = p;
     }
-    __syncthreads();
-    const double beta = hb[0];
-    // this thread's rows of the trailing part: max(j, i0) .. min(n, i0 + 64)
-    const int lo = (j > i0) ? j : i0, hi = (i0 + 64 < n) ? i0 + 64 : n;
-    const bool upd = col && c > j;
+    const bool is_p = col && c == p;
+    const bool upd = col && !placed && !is_p;
+    placed = placed || is_p;
+    const int is = j + ((q - j) & 3);  // this thread's first row >= j
     {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (upd) {
-        int i = lo;
-        for (; i + 3 < hi; i += 4) {
-          a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
-          a1 += v[i + 1] * W[static_cast<int64_t>(i + 1) * n + c];
-          a2 += v[i + 2] * W[static_cast<int64_t>(i + 2) * n + c];
-          a3 += v[i + 3] * W[static_cast<int64_t>(i + 3) * n + c];
+        int i = is;
+        if (i == j) {
+          a0 = v0 * W[static_cast<int64_t>(j) * n + c];
+          i += 4;
         }
-        for (; i < hi; ++i) a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
+        for (; i + 12 < n; i += 16) {
+          a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
+          a1 += v[i + 4] * W[static_cast<int64_t>(i + 4) * n + c];
+          a2 += v[i + 8] * W[static_cast<int64_t>(i + 8) * n + c];
+          a3 += v[i + 12] * W[static_cast<int64_t>(i + 12) * n + c];
+        }
+        for (; i < n; i += 4) a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
       }
-      qpart[q][c] = (a0 + a1) + (a2 + a3);
+      dotp[q][c] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
     {
-      const double f = upd ? beta * (((qpart[0][c] + qpart[1][c]) + qpart[2][c]) + qpart[3][c]) : 0.0;
-      __syncthreads();
       double s0 = 0.0, s1 = 0.0;
       if (upd) {
-        int i = lo;
-        for (; i + 1 < hi; i += 2) {
-          const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
-          const double y = W[static_cast<int64_t>(i + 1) * n + c] - f * v[i + 1];
-          W[static_cast<int64_t>(i) * n + c] = x;
-          W[static_cast<int64_t>(i + 1) * n + c] = y;
-          if (i > j) s0 += x * x;
-          s1 += y * y;  // i + 1 > j
+        const double f = beta * (((dotp[0][c] + dotp[1][c]) + dotp[2][c]) + dotp[3][c]);
+        int i = is;
+        if (i == j) {  // row j is final after this step and leaves the norm
+          W[static_cast<int64_t>(j) * n + c] -= f * v0;
+          i += 4;
         }
-        for (; i < hi; ++i) {
+        for (; i + 4 < n; i += 8) {
+          const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
+          const double y = W[static_cast<int64_t>(i + 4) * n + c] - f * v[i + 4];
+          W[static_cast<int64_t>(i) * n + c] = x;
+          W[static_cast<int64_t>(i + 4) * n + c] = y;
+          s0 += x * x;
+          s1 += y * y;
+        }
+        for (; i < n; i += 4) {
           const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
           W[static_cast<int64_t>(i) * n + c] = x;
-          if (i > j) s0 += x * x;
+          s0 += x * x;
         }
-      } else if (col && c == j) {
-        for (int i = lo; i < hi; ++i) W[static_cast<int64_t>(i) * n + j] = (i == j) ? hb[1] : 0.0;
+      } else if (is_p) {
+        for (int i = is; i < n; i += 4) W[static_cast<int64_t>(i) * n + c] = (i == j) ? rjj : 0.0;
       }
-      qpart[q][c] = s0 + s1;
+      nrmp[q][c] = s0 + s1;
     }
-    __syncthreads();
-    if (tid < n && tid > j)  // norm over rows j+1.. for the next pivot
-      nrm2[tid] = ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid];
     __syncthreads();
   }
   if (col) {
-    for (int u = 0; u < 64; ++u) {
-      const int i = i0 + u;
-      if (i < n) {
-        const double a = (i <= c) ? sgn[i] * W[static_cast<int64_t>(i) * n + c] : 0.0;
-        Rt[i + static_cast<int64_t>(c) * n] = a;
-        W[static_cast<int64_t>(i) * n + c] = a;
-      }
+    const int jc = pos[c];
+    for (int i = q; i < n; i += 4) {
+      const double a = (i <= jc) ? sgn[i] * W[static_cast<int64_t>(i) * n + c] : 0.0;
+      Rt[i + static_cast<int64_t>(jc) * n] = a;
+      Rw[static_cast<int64_t>(i) * n + jc] = a;
     }
-    if (q == 0) piv[c] = pcol[c];
+    if (q == 0) piv[jc] = c;
   }
 }
 
@@ -352,11 +340,35 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const T* __restrict__ 
     dst[r] = src[r];
 }
 
+// Second pass (Algorithm 3 steps 2-3 on the r columns of Q): R(0:r, :) <-
+// U R(0:r, :) with U (ld ldu) upper triangular r x r.  One workgroup per
+// column of R; the column is read into LDS before it is overwritten.
+__global__ __launch_bounds__(256) void left_upper_kernel(const double* __restrict__ U,
+                                                         int64_t ldu, int r,
+                                                         double* __restrict__ R, int64_t ldr) {
+  __shared__ double col[kMaxN];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double* rc = R + static_cast<int64_t>(c) * ldr;
+  if (t < r) col[t] = rc[t];
+  __syncthreads();
+  if (t < r) {
+    double s = 0.0;
+    for (int l = t; l < r; ++l) s += U[t + static_cast<int64_t>(l) * ldu] * col[l];
+    rc[t] = s;
+  }
+}
+
+hipError_t launch_left_upper(const double* U, int64_t ldu, int r, double* R, int64_t ldr, int n,
+                             hipStream_t st) {
+  left_upper_kernel<<<n, 256, 0, st>>>(U, ldu, r, R, ldr);
+  return hipGetLastError();
+}
+
 size_t rr_extra_bytes(int n) {
   const size_t nn = static_cast<size_t>(n) * n * sizeof(double);
   return static_cast<size_t>(kRrSplits) * n * sizeof(double)  // norm partials
          + n * sizeof(double)                                 // d
-         + 3 * nn                                             // W, Rt, Rs
+         + 4 * nn                                             // W, Rt, Rs, Rw
          + 2 * n * sizeof(int) + 256;                         // piv, rank
 }
 
@@ -369,6 +381,7 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
   double* W = d + n;
   double* Rt = W + static_cast<size_t>(n) * n;
   double* Rs = Rt + static_cast<size_t>(n) * n;
+  double* Rw = Rs + static_cast<size_t>(n) * n;
   *Rs_out = Rs;
   if (stage == 0) {
     // column norms of X and the normalised sketch
@@ -383,8 +396,8 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
     colnorm_scale_kernel<<<n, 256, 0, st>>>(part, kRrSplits, n, d, P, k, k);
     return hipGetLastError();
   }
-  qrcp_kernel<<<1, kQcpThreads, 0, st>>>(Rp, n, W, Rt, piv_out);
-  rr_finish_kernel<<<1, kFinThreads, 0, st>>>(Rt, W, n, tau, d, piv_out, R, ldr, Rs, rank_out,
+  qrcp_kernel<<<1, kQcpThreads, 0, st>>>(Rp, n, W, Rt, Rw, piv_out);
+  rr_finish_kernel<<<1, kFinThreads, 0, st>>>(Rt, Rw, n, tau, d, piv_out, R, ldr, Rs, rank_out,
                                               status);
   return hipGetLastError();
 }

@@ -121,26 +121,34 @@ def test_rr_argument_errors_without_gpu():
     import paper_2210_09953_amd as rq
     L = rq.lib()
     vp = ctypes.c_void_p
-    assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64) > 0
-    assert L.rcholqr_rr_workspace_bytes(1000, 10, 5, rq.GAUSSIAN, rq.F64) == 0
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 1) > 0
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 2) > \
+        L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 1)
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 5, rq.GAUSSIAN, rq.F64, 1) == 0
+    assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 3) == 0
 
-    def call(X=256, m=1000, n=10, ldx=1000, k=30, kind=rq.GAUSSIAN, prec=rq.F64, tau=1e-12,
-             Q=256, ldq=1000, R=256, ldr=10, piv=256, rank=256, ws=256, wsb=1 << 30):
-        return L.rcholqr_rr(vp(X), m, n, ldx, k, 1, kind, prec, tau, vp(Q), ldq, vp(R), ldr,
-                            vp(piv), vp(rank), vp(ws), wsb, None)
+    def call(X=256, m=1000, n=10, ldx=1000, k=30, kind=rq.GAUSSIAN, prec=rq.F64, passes=1,
+             tau=1e-12, Q=256, ldq=1000, R=256, ldr=10, piv=256, rank=256, ws=256, wsb=1 << 30):
+        return L.rcholqr_rr(vp(X), m, n, ldx, k, 1, kind, prec, passes, tau, vp(Q), ldq, vp(R),
+                            ldr, vp(piv), vp(rank), vp(ws), wsb, None)
     assert call(X=0) == -1
     assert call(m=5) == -2
+    assert call(n=0) == -3
     assert call(ldx=10) == -4
     assert call(k=5) == -5
     assert call(kind=7) == -7
     assert call(kind=rq.GAUSSIAN, prec=rq.MIXED) == -8
-    assert call(tau=-1.0) == -9
-    assert call(tau=float("nan")) == -9
-    assert call(Q=0) == -10
-    assert call(ldq=10) == -11
-    assert call(R=0) == -12
-    assert call(ldr=3) == -13
-    assert call(piv=0) == -14
-    assert call(rank=0) == -15
-    assert call(ws=0) == -16
-    assert call(wsb=16) == -17
+    assert call(passes=0) == -9
+    assert call(passes=3) == -9
+    assert call(tau=-1.0) == -10
+    assert call(tau=float("nan")) == -10
+    assert call(Q=0) == -11
+    assert call(ldq=10) == -12
+    assert call(R=0) == -13
+    assert call(ldr=3) == -14
+    assert call(piv=0) == -15
+    assert call(rank=0) == -16
+    assert call(ws=0) == -17
+    assert call(wsb=16) == -18
+    need2 = L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 2)
+    assert call(passes=2, wsb=need2 - 1) == -18

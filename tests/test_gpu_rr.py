@@ -102,3 +102,36 @@ def test_rr_low_rank_f32_and_mixed(rq, orc, precision):
     print(f"rr {precision}: max column error {err.max():.2e} cond(Q) {np.linalg.cond(Q):.2f}")
     assert err.max() <= 1e-4
     assert np.linalg.cond(Q) <= 10
+
+
+@pytest.mark.parametrize("precision,n,rho", [("F64", 64, 20), ("F64", 200, 200), ("F32", 96, 40),
+                                             ("MIXED", 256, 190)])
+def test_rr_two_pass(rq, orc, precision, n, rho):
+    """RRRCholeskyQR2: the rank and pivots of the single pass, Q orthonormal
+    to working accuracy, X Pi = Q R; FP64 against the oracle's second pass."""
+    m, k = 20000, 3 * n
+    X = _low_rank(m, n, rho, 21)
+    kind = 0 if precision == "F64" else rq.RADEMACHER
+    tau = 1e-10 if precision == "F64" else 1e-5
+    if precision != "F64":
+        X = X.astype(np.float32)
+    Q, R, piv, r = rq.rr(_gpu(X), k, 6, kind, precision=getattr(rq, precision), tau=tau,
+                         passes=2)
+    ref = orc.rr_rcholqr2(X.astype(np.float64), k, 6, kind, tau=tau)
+    assert r == ref["rank"] == rho
+    piv = _np(piv)
+    assert np.array_equal(piv[:r], ref["piv"][:r])
+    Q, R = _np(Q).astype(np.float64), _np(R)
+    orth = np.linalg.norm(Q.T @ Q - np.eye(r), 2)
+    XP = X.astype(np.float64)[:, piv]
+    err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
+    print(f"rr2 {precision} n={n}: orth {orth:.2e} max column error {err.max():.2e}")
+    if precision == "F64":
+        assert orth <= 1e-13
+        assert err.max() <= 1e-9
+        assert np.linalg.norm(Q - ref["Q"]) <= 1e-9 * np.linalg.norm(ref["Q"])
+        Rx, Rx_ref = _back_to_x_order(R, piv), _back_to_x_order(ref["R"], ref["piv"])
+        assert np.linalg.norm(Rx - Rx_ref) <= 1e-9 * np.linalg.norm(Rx_ref)
+    else:
+        assert orth <= 1e-5
+        assert err.max() <= 1e-4

@@ -565,3 +565,39 @@ def test_rr_rank_rule(orc):
     assert orc.rr_rank(R, 1e-12) == 4
     assert orc.rr_rank(R, 0.0) == 4
     assert orc.rr_rank(np.zeros((3, 3)), 1e-3) == 0
+
+
+def test_rr_rcholqr2_full_rank_equals_householder_r(orc):
+    """RRRCholeskyQR2 on a full-rank X (kappa 1e4): Q is orthonormal to
+    working accuracy and, the positive-diagonal QR of X Pi being unique, R is
+    LAPACK's Householder R of X[:, piv] with its rows made positive."""
+    m, n, k = 3000, 24, 72
+    X = synth.make_x(m, n, 1e-4, seed=6)
+    out = orc.rr_rcholqr2(X, k, 4, G, tau=1e-14)
+    assert out["rank"] == n and out["status"] == 0
+    Q, R, piv = out["Q"], out["R"], out["piv"]
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 1e-14
+    Rl = np.linalg.qr(X[:, piv], mode="r")
+    Rl = np.sign(np.diag(Rl))[:, None] * Rl
+    assert np.linalg.norm(R - Rl) <= 1e-12 * np.linalg.norm(Rl)
+    # the pivots and rank are those of the single pass
+    one = orc.rr_rcholqr(X, k, 4, G, tau=1e-14)
+    assert np.array_equal(one["piv"], piv) and one["rank"] == n
+
+
+def test_rr_rcholqr2_low_rank_restores_orthogonality(orc):
+    """Exact rank 9 of n = 20: the single pass leaves cond(Q) of a few units;
+    the second pass makes Q orthonormal to ~u and keeps X Pi = Q R."""
+    rng = np.random.default_rng(12)
+    m, n, rho, k = 5000, 20, 9, 60
+    X = np.asfortranarray((rng.standard_normal((m, rho)) @ rng.standard_normal((rho, n)))
+                          * np.logspace(0, 2, n))
+    one = orc.rr_rcholqr(X, k, 8, RD, tau=1e-10)
+    two = orc.rr_rcholqr2(X, k, 8, RD, tau=1e-10)
+    assert one["rank"] == two["rank"] == rho
+    assert np.linalg.norm(one["Q"].T @ one["Q"] - np.eye(rho), 2) > 1e-3
+    Q, R = two["Q"], two["R"]
+    assert np.linalg.norm(Q.T @ Q - np.eye(rho), 2) <= 1e-14
+    XP = X[:, two["piv"]]
+    err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
+    assert err.max() <= 1e-9
