@@ -289,7 +289,8 @@ def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, passes=1, seed=
 
     def call():
         code = L.rcholqr_rr(ctypes.c_void_p(X.data_ptr()), m, n, max(X.stride(1), m), k, seed,
-                            kind, prec_code, passes, float(tau), ctypes.c_void_p(Q.data_ptr()), m,
+                            kind, prec_code, passes, float(tau), 1.5,
+                            ctypes.c_void_p(Q.data_ptr()), m,
                             ctypes.c_void_p(R.data_ptr()), n, ctypes.c_void_p(piv.data_ptr()),
                             ctypes.c_void_p(rank.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                             ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))

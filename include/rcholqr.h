@@ -142,8 +142,12 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
  * (m x r) well-conditioned and R (r x n) upper trapezoidal, for any X
  * (numerically rank-deficient included).  Steps: P = Theta X; D = diag of
  * the column norms of X; the rank-revealing QR of P D^{-1} (Householder with
- * column pivoting: largest remaining column norm, the first on ties); r =
- * the least r with ||R_{r+1:n,r+1:n}||_F <= tau ||R||_2; Q = X Pi_{:,1:r}
+ * column pivoting: largest remaining column norm, the first on ties,
+ * followed for f > 0 by the strong RRQR swaps of Gu and Eisenstat for k = the
+ * rank the rule gives: while some rho_ij^2 = (R11^{-1} R12)_ij^2 +
+ * ||R22 e_j||^2 ||e_i^T R11^{-1}||^2 exceeds f^2, the largest is swapped in
+ * and R triangularised again, at most 4n times); r = the least r with
+ * ||R_{r+1:n,r+1:n}||_F <= tau ||R||_2 (again after any swap); Q = X Pi_{:,1:r}
  * (R_{1:r,1:r} Pi^T D Pi)^{-1} by the tall forward substitution; R <-
  * R_{1:r,:} Pi^T D Pi.  With passes = 2 (RRRCholeskyQR2, Section 4) one
  * Cholesky QR pass follows on the r columns of Q: G = Q^T Q = R'^T R',
@@ -153,6 +157,8 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
  *  passes 1 (Algorithm 7) or 2 (with the Cholesky QR pass).  passes = 2
  *         reads r back to the host: the call then waits for the stream.
  *  tau    truncation tolerance (>= 0).
+ *  f      strong RRQR parameter: 0 (column pivoting alone) or > 1 (the
+ *         paper's experiments use 1.5).
  *  Q      [out] m x n buffer (ld ldq >= m, FP64 or FP32 as X): columns 0..r-1
  *         hold Q; columns r.. hold the dropped columns of X Pi (unscaled).
  *  R      [out] n x n FP64 (ld ldr): rows 0..r-1 hold R, rows r.. are zero.
@@ -167,8 +173,8 @@ size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_ki
                                   int precision, int passes);
 int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
                uint64_t seed, int sketch_kind, int precision, int passes, double tau,
-               void* Q, int64_t ldq, double* R, int64_t ldr, int* piv, int* rank,
-               void* ws, size_t ws_bytes, void* stream);
+               double f, void* Q, int64_t ldq, double* R, int64_t ldr, int* piv,
+               int* rank, void* ws, size_t ws_bytes, void* stream);
 
 /* Read the status word of a workspace used by a completed call
  * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.

@@ -11,8 +11,9 @@ Cholesky QR factorizations":
 * ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
 * ``rcholqr``           -- Algorithm 2 (passes=1) / Algorithm 3 (passes=2)
 * ``reduced_rcholqr``   -- Algorithm 5 (Reduced RCholeskyQR, Section 3.3)
-* ``qrcp``/``rr_rcholqr`` -- Algorithm 7 (rank-revealing RCholeskyQR, Section 4)
-                           with QR with column pivoting as its RRQR step
+* ``qrcp``/``strong_rrqr``/``rr_rcholqr`` -- Algorithm 7 (rank-revealing
+                           RCholeskyQR, Section 4); its RRQR step is QR with
+                           column pivoting and the strong RRQR swaps
 * ``rr_rcholqr2``       -- RRRCholeskyQR2 (Section 4): Algorithm 7 and one
                            Cholesky QR pass (Algorithm 3 steps 2-4)
 * ``qr_backward``       -- reverse-mode derivative of the positive-diagonal
@@ -255,30 +256,68 @@ def rr_rank(R, tau):
     return n
 
 
-def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12):
+def strong_rrqr(R, k, f=1.5, max_swaps=None):
+    """Strong RRQR (Gu and Eisenstat, 1996, the method Section 4 names for the
+    RRQR step, with f = 1.5 in the experiments) applied to a QR factor R
+    (n x n, upper triangular) for a fixed k: while some pair (i, j) has
+    rho_ij^2 = (R11^{-1} R12)_ij^2 + (||R22 e_j|| ||e_i^T R11^{-1}||)^2 > f^2,
+    columns i and k + j trade places and R is triangularised again; each such
+    swap raises |det R11| by the factor rho_ij > f.  The largest rho_ij
+    (first in row-major order on ties) is taken each time.  Returns (R with a
+    positive diagonal, perm, swaps): the input's columns perm, factored."""
+    R = np.array(_f64(R), dtype=np.float64, order="F", copy=True)
+    n = R.shape[0]
+    perm = np.arange(n)
+    cap = 4 * n if max_swaps is None else max_swaps
+    swaps = 0
+    while 0 < k < n and swaps < cap:
+        Rinv = np.linalg.solve(R[:k, :k], np.eye(k))
+        A = Rinv @ R[:k, k:]
+        w = np.linalg.norm(Rinv, axis=1)       # 1 / omega_i
+        g = np.linalg.norm(R[k:, k:], axis=0)  # gamma_j
+        rho2 = A ** 2 + np.outer(w, g) ** 2
+        i, j = np.unravel_index(int(np.argmax(rho2)), rho2.shape)
+        if not rho2[i, j] > f * f:
+            break
+        R[:, [i, k + j]] = R[:, [k + j, i]]
+        perm[[i, k + j]] = perm[[k + j, i]]
+        R = np.linalg.qr(R, mode="r")
+        R = np.asfortranarray(R * np.where(np.diag(R) < 0, -1.0, 1.0)[:, None])
+        swaps += 1
+    return R, perm, swaps
+
+
+def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12, f=1.5):
     """Algorithm 7 on the column-normalised X (Section 4): D = column norms,
-    P = (Theta X) D^{-1}, [R, Pi] = RRQR(P) (column-pivoted Householder),
-    rank r, Q = (X Pi_{1:r}) (R_{1:r,1:r} (Pi^T D Pi)_{1:r})^{-1} and
-    R <- R_{1:r,:} Pi^T D Pi.  Returns dict(Q, R, piv, rank, Rn) (Rn: the
-    R of the normalised sketch)."""
+    P = (Theta X) D^{-1}, [R, Pi] = RRQR(P), rank r, Q = (X Pi_{1:r})
+    (R_{1:r,1:r} (Pi^T D Pi)_{1:r})^{-1} and R <- R_{1:r,:} Pi^T D Pi.  The
+    RRQR is column-pivoted Householder followed, when f > 0, by the strong
+    RRQR swaps for k = the rank that the rule gives on the pivoted R; the
+    rule is then applied again.  Returns dict(Q, R, piv, rank, Rn, swaps)
+    (Rn: the R of the normalised sketch)."""
     X = _f64(X)
     m, n = X.shape
     d = np.linalg.norm(X, axis=0)
     P = sketch(kind, X, k, seed) / np.where(d > 0, d, 1.0)  # a zero column stays zero
     Rn, piv = qrcp(P)
     r = rr_rank(Rn, tau)
+    swaps = 0
+    if f > 0:
+        Rn, perm, swaps = strong_rrqr(Rn, r, f)
+        piv = piv[perm]
+        r = rr_rank(Rn, tau)
     Rout = np.asfortranarray(Rn[:r, :] * d[piv][None, :])
     Q = trsm_rows(np.asfortranarray(X[:, piv[:r]]), np.asfortranarray(Rout[:, :r])) if r else \
         np.zeros((m, 0), order="F")
-    return dict(Q=Q, R=Rout, piv=piv, rank=r, Rn=Rn)
+    return dict(Q=Q, R=Rout, piv=piv, rank=r, Rn=Rn, swaps=swaps)
 
 
-def rr_rcholqr2(X, k, seed, kind=GAUSSIAN, tau=1e-12):
+def rr_rcholqr2(X, k, seed, kind=GAUSSIAN, tau=1e-12, f=1.5):
     """RRRCholeskyQR2 (Section 4): Algorithm 7, then one Cholesky QR pass on
     the r kept columns as in Algorithm 3 steps 2-4: G = Q^T Q = R'^T R',
     Q <- Q R'^{-1}, R <- R' R.  Returns rr_rcholqr's dict with Q and R
     replaced and the Cholesky's status."""
-    out = rr_rcholqr(X, k, seed, kind, tau)
+    out = rr_rcholqr(X, k, seed, kind, tau, f)
     r = out["rank"]
     out["status"] = 0
     if r == 0:

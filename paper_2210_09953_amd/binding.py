@@ -81,7 +81,8 @@ def lib():
     L.rcholqr_reduced.restype = i32
     L.rcholqr_rr_workspace_bytes.argtypes = [i64, i64, i64, i32, i32, i32]
     L.rcholqr_rr_workspace_bytes.restype = sz
-    L.rcholqr_rr.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, i32, ctypes.c_double, vp, i64,
+    L.rcholqr_rr.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, i32, ctypes.c_double,
+                             ctypes.c_double, vp, i64,
                              dp, i64, vp, vp, vp, sz, vp]
     L.rcholqr_rr.restype = i32
     L.rcholqr_device_copy.argtypes = [vp, vp, sz, vp]
@@ -212,11 +213,13 @@ def reduced(X, k, l, seed, kind=RADEMACHER, precision=None, want_s=False, ws=Non
     return Z, R
 
 
-def rr(X, k, seed, kind=GAUSSIAN, precision=None, tau=1e-12, passes=1, ws=None, Q=None, R=None):
+def rr(X, k, seed, kind=GAUSSIAN, precision=None, tau=1e-12, passes=1, f=1.5, ws=None, Q=None,
+       R=None):
     """Rank-revealing RCholeskyQR (Algorithm 7; passes=2: RRRCholeskyQR2 with
     one Cholesky QR pass on the kept columns): X[:, piv] ~ Q R with Q (m x r)
-    well-conditioned, R (r x n).  Returns (Q, R, piv, r); reading r waits
-    for the stream."""
+    well-conditioned, R (r x n).  The RRQR step is column pivoting followed
+    by the strong RRQR swaps with parameter f (f=0: none).  Returns (Q, R,
+    piv, r); reading r waits for the stream."""
     if precision is None:
         precision = F64 if X.dtype == torch.float64 else F32
     X = fortran(X)
@@ -230,7 +233,7 @@ def rr(X, k, seed, kind=GAUSSIAN, precision=None, tau=1e-12, passes=1, ws=None, 
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=X.device)
     if ws.numel() < need:
-        raise RCholQRError(-18, "workspace too small")
+        raise RCholQRError(-19, "workspace too small")
     if Q is None:
         Q = empty_fortran(m, n, dt, X.device)
     if R is None:
@@ -238,8 +241,8 @@ def rr(X, k, seed, kind=GAUSSIAN, precision=None, tau=1e-12, passes=1, ws=None, 
     piv = torch.empty(n, dtype=torch.int32, device=X.device)
     rank = torch.empty(1, dtype=torch.int32, device=X.device)
     code = lib().rcholqr_rr(_ptr(X), m, n, _ld(X), k, int(seed), kind, precision, int(passes),
-                            float(tau), _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(piv), _ptr(rank),
-                            _ptr(ws), ws.numel(), _stream())
+                            float(tau), float(f), _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(piv),
+                            _ptr(rank), _ptr(ws), ws.numel(), _stream())
     _check(code, "rcholqr_rr")
     r = int(rank.item())
     return Q[:, :r], R[:r, :], piv, r

@@ -580,9 +580,9 @@ size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_ki
 }
 
 int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint64_t seed,
-               int sketch_kind, int precision, int passes, double tau, void* Q, int64_t ldq,
-               double* R, int64_t ldr, int* piv, int* rank, void* ws, size_t ws_bytes,
-               void* stream) {
+               int sketch_kind, int precision, int passes, double tau, double f, void* Q,
+               int64_t ldq, double* R, int64_t ldr, int* piv, int* rank, void* ws,
+               size_t ws_bytes, void* stream) {
   if (!X) return -1;
   if (n < 1 || n > kMaxN) return -3;
   if (m < n) return -2;
@@ -593,17 +593,18 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
   if (passes < 1 || passes > 2) return -9;
   if (!(tau >= 0.0) || !isfinite(tau)) return -10;
-  if (!Q) return -11;
-  if (ldq < m) return -12;
-  if (!R) return -13;
-  if (ldr < n) return -14;
-  if (!piv) return -15;
-  if (!rank) return -16;
-  if (!ws) return -17;
+  if (!(f == 0.0 || (f > 1.0 && isfinite(f)))) return -11;
+  if (!Q) return -12;
+  if (ldq < m) return -13;
+  if (!R) return -14;
+  if (ldr < n) return -15;
+  if (!piv) return -16;
+  if (!rank) return -17;
+  if (!ws) return -18;
   const Layout L = make_layout(m, n, k, sketch_kind, 1, precision);
   const size_t extra_off = align256(L.total);
   const size_t gram_off = extra_off + align256(rr_extra_bytes(static_cast<int>(n)));
-  if (ws_bytes < gram_off + (passes == 2 ? rr_second_gram_bytes(m, n, precision) : 0)) return -18;
+  if (ws_bytes < gram_off + (passes == 2 ? rr_second_gram_bytes(m, n, precision) : 0)) return -19;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool f32 = precision != kPrecF64;
   const int ni = static_cast<int>(n), ki = static_cast<int>(k);
@@ -617,13 +618,13 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
     RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
                           at<uint32_t>(ws, L.keys), P, k, st));
   double* Rsolve = nullptr;
-  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, nullptr, tau, extra, R, ldr, piv, rank, status,
-                          &Rsolve, st, 0));
+  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, nullptr, tau, f, extra, R, ldr, piv, rank,
+                          status, &Rsolve, st, 0));
   double* Rsw = at<double>(ws, L.Rs);
   RCQ_TRY(launch_householder(P, ki, ni, at<double>(ws, L.v0), at<double>(ws, L.beta),
                              at<double>(ws, L.T), nullptr, k, Rsw, nullptr, ldr, status, st));
-  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, Rsw, tau, extra, R, ldr, piv, rank, status,
-                          &Rsolve, st, 1));
+  RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, Rsw, tau, f, extra, R, ldr, piv, rank,
+                          status, &Rsolve, st, 1));
   RCQ_TRY(launch_gather_cols(X, f32, m, ni, ldx, piv, Q, ldq, st));
   void* pan = at<void>(ws, L.pan);
   RCQ_TRY(launch_make_panels(Rsolve, n, ni, f32, pan, st));

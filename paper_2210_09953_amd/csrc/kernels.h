@@ -57,10 +57,11 @@ hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_
 
 // rr.hip (rank-revealing variant).  stage 0: column norms d of X and P <-
 // P D^{-1} (P k x n, ld k); stage 1: column-pivoted QR of Rp (n x n), rank,
-// R (ld ldr), piv, rank, status, and *Rs_out = the solve's n x n factor.
+// the strong RRQR swaps with parameter f (none for f = 0), R (ld ldr), piv,
+// rank, status, and *Rs_out = the solve's n x n factor.
 size_t rr_extra_bytes(int n);
 hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ldx, double* P,
-                           int k, const double* Rp, double tau, unsigned char* extra,
+                           int k, const double* Rp, double tau, double f, unsigned char* extra,
                            double* R, int64_t ldr, int* piv_out, int* rank_out, int* status,
                            double** Rs_out, hipStream_t st, int stage);
 // R(0:r, 0:n) <- U R(0:r, 0:n), U upper triangular r x r (second pass).

@@ -215,24 +215,22 @@ __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restr
   }
 }
 
-// Step 3 (rank: least r with ||Rt_{r:,r:}||_F <= tau ||Rt||_2, the 2-norm by
-// 64 power-iteration steps on Rt^T Rt) and the outputs: R (ld ldr) =
-// Rt_{1:r,:} diag(d[piv]) (rows >= r zero), Rs (ld n) the factor of the
-// solve (that block on 1:r, identity on the dropped columns), rank.  The
-// status word keeps only the non-finite flag (rank deficiency is expected).
+// Step 3, the rank: least r with ||Rt_{r:,r:}||_F <= tau ||Rt||_2, the
+// 2-norm by 64 power-iteration steps on Rt^T Rt (kept in *sigma_out for the
+// strong RRQR step).  The status word keeps only the non-finite flag (rank
+// deficiency is expected).
 // Rt is read column-major for the products Rt x and row-major (Rw) for
 // Rt^T y, so that both are coalesced; output entry t of either product is
 // the sum of four quarter sums (threads t + 256 q over indices 64 q ..
 // 64 q + 63) added in q order.
 constexpr int kFinThreads = 4 * kMaxN;
 
-__global__ __launch_bounds__(kFinThreads) void rr_finish_kernel(
+__global__ __launch_bounds__(kFinThreads) void rr_rank_kernel(
     const double* __restrict__ Rt, const double* __restrict__ Rw, int n, double tau,
-    const double* __restrict__ d, const int* __restrict__ piv, double* __restrict__ R,
-    int64_t ldr, double* __restrict__ Rs, int* __restrict__ rank, int* __restrict__ status) {
+    const double* __restrict__ d, double* __restrict__ sigma_out, int* __restrict__ rank,
+    int* __restrict__ status) {
   __shared__ double x[kMaxN], y[kMaxN], qp[4][kMaxN], red[kFinThreads / 64];
   __shared__ double tail[kMaxN + 1];
-  __shared__ int rr;
   const int tid = threadIdx.x, t = tid & (kMaxN - 1), q = tid >> 8;
   const int c0 = 64 * q, c1 = (c0 + 64 < n) ? c0 + 64 : n;
   const bool live = t < n;
@@ -313,17 +311,225 @@ __global__ __launch_bounds__(kFinThreads) void rr_finish_kernel(
         r = k;
         break;
       }
-    rr = r;
     *rank = r;
+    *sigma_out = sigma;
     *status = (bad || !isfinite(sigma)) ? 2 : 0;
   }
-  __syncthreads();
-  const int r = rr;
-  for (int idx = tid; idx < n * n; idx += kFinThreads) {
+}
+
+// The outputs of step 3: R (ld ldr) = Rt_{1:r,:} diag(d[piv]) (rows >= r
+// zero) and Rs (ld n), the factor of the solve: that block on 1:r, the
+// identity on the dropped columns.
+__global__ __launch_bounds__(256) void rr_out_kernel(const double* __restrict__ Rt, int n,
+                                                     const double* __restrict__ d,
+                                                     const int* __restrict__ piv,
+                                                     const int* __restrict__ rank,
+                                                     double* __restrict__ R, int64_t ldr,
+                                                     double* __restrict__ Rs) {
+  const int r = *rank;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const int i = idx % n, c = idx / n;
     const double v = (i < r && i <= c) ? Rt[i + static_cast<int64_t>(c) * n] * d[piv[c]] : 0.0;
     R[i + static_cast<int64_t>(c) * ldr] = v;
     Rs[idx] = (i < r && c < r) ? v : ((i == c) ? 1.0 : 0.0);
+  }
+}
+
+// Strong RRQR (Gu and Eisenstat's swaps, with parameter f) on the pivoted
+// factor for k = the rank of the rule: while the largest rho_ij^2 =
+// (R11^{-1} R12)_ij^2 + ||R22 e_j||^2 ||e_i^T R11^{-1}||^2 (first in
+// row-major order on ties) exceeds f^2, columns i and k + j trade places
+// (and their labels in piv) and R is triangularised again by Householder
+// steps from column i on (earlier columns are untouched), rows made
+// positive.  At most 4n swaps.  Rw (row-major) is worked in place, Ri holds
+// R11^{-1} (row-major); after a swap Rt is refreshed and the rank rule is
+// applied again with the same ||R||_2 (the swaps keep the singular values).
+constexpr int kSrThreads = 4 * kMaxN;
+
+__global__ __launch_bounds__(kSrThreads) void srrqr_kernel(double* __restrict__ Rt,
+                                                           double* __restrict__ Rw,
+                                                           double* __restrict__ Ri, int n,
+                                                           double tau, double f,
+                                                           const double* __restrict__ sigma,
+                                                           int* __restrict__ piv,
+                                                           int* __restrict__ rank) {
+  __shared__ double part[4][kMaxN];
+  __shared__ double w2[kMaxN], g2[kMaxN], v[kMaxN], sgn[kMaxN], tail[kMaxN + 1];
+  __shared__ double wbest[kSrThreads / 64];
+  __shared__ int wkey[kSrThreads / 64];
+  __shared__ double hb;
+  const int tid = threadIdx.x, c = tid & (kMaxN - 1), q = tid >> 8;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int k = *rank;
+  if (k <= 0 || k >= n) return;
+  auto at = [n](int i, int j) { return static_cast<int64_t>(i) * n + j; };
+  bool swapped = false;
+  for (int it = 0; it < 4 * n; ++it) {
+    // Ri = R11^{-1}, row i from rows i+1.. (four row classes per column)
+    for (int i = k - 1; i >= 0; --i) {
+      double a = 0.0;
+      if (c > i && c < k)
+        for (int l = i + 1 + ((q - i - 1) & 3); l <= c; l += 4) a += Rw[at(i, l)] * Ri[at(l, c)];
+      part[q][c] = a;
+      __syncthreads();
+      if (q == 0 && c >= i && c < k) {
+        const double rii = Rw[at(i, i)];
+        Ri[at(i, c)] =
+            (c == i) ? 1.0 / rii : -(((part[0][c] + part[1][c]) + part[2][c]) + part[3][c]) / rii;
+      }
+      __syncthreads();
+    }
+    // squared row norms of R11^{-1}, squared column norms of R22
+    {
+      double s = 0.0;
+      if (c < k)
+        for (int l = c + ((q - c) & 3); l < k; l += 4) {
+          const double x = Ri[at(c, l)];
+          s += x * x;
+        }
+      else if (c < n)
+        for (int l = k + ((q - k) & 3); l < n; l += 4) {
+          const double x = Rw[at(l, c)];
+          s += x * x;
+        }
+      part[q][c] = s;
+    }
+    __syncthreads();
+    if (q == 0 && c < n) {
+      const double s = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+      if (c < k)
+        w2[c] = s;
+      else
+        g2[c] = s;
+    }
+    __syncthreads();
+    // the largest rho^2: thread (c, q) takes column c of R12 and rows i = q mod 4
+    double best = -1.0;
+    int bkey = n * n;
+    if (c >= k && c < n)
+      for (int i = q; i < k; i += 4) {
+        double a0 = 0.0, a1 = 0.0;
+        int l = i;
+        for (; l + 1 < k; l += 2) {
+          a0 += Ri[at(i, l)] * Rw[at(l, c)];
+          a1 += Ri[at(i, l + 1)] * Rw[at(l + 1, c)];
+        }
+        if (l < k) a0 += Ri[at(i, l)] * Rw[at(l, c)];
+        const double a = a0 + a1;
+        const double r2 = a * a + w2[i] * g2[c];
+        if (r2 > best) {  // rows rise within a thread: the first of equal values stays
+          best = r2;
+          bkey = i * n + c;
+        }
+      }
+    {
+      double mx = best;
+      for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+      int key = (best == mx) ? bkey : n * n;
+      for (int off = 32; off >= 1; off >>= 1) key = min(key, __shfl_xor(key, off));
+      if (lane == 0) {
+        wbest[wave] = mx;
+        wkey[wave] = key;
+      }
+    }
+    __syncthreads();
+    double gb = -1.0;
+    int gk = n * n;
+    for (int w = 0; w < kSrThreads / 64; ++w)
+      if (wbest[w] > gb || (wbest[w] == gb && wkey[w] < gk)) {
+        gb = wbest[w];
+        gk = wkey[w];
+      }
+    __syncthreads();  // wbest and wkey are rewritten by the next round
+    if (!(gb > f * f) || gk >= n * n) break;
+    const int si = gk / n, sc = gk % n;
+    if (tid < n) {
+      const double a = Rw[at(tid, si)];
+      Rw[at(tid, si)] = Rw[at(tid, sc)];
+      Rw[at(tid, sc)] = a;
+    }
+    if (tid == 0) {
+      const int p = piv[si];
+      piv[si] = piv[sc];
+      piv[sc] = p;
+    }
+    __syncthreads();
+    // Householder from column si on, no pivoting
+    for (int j = si; j < n; ++j) {
+      for (int l = j + tid; l < n; l += kSrThreads) v[l] = Rw[at(l, j)];
+      __syncthreads();
+      if (wave == 0) {
+        double s = 0.0;
+        for (int l = j + lane; l < n; l += 64) s += v[l] * v[l];
+        s = wave_sum(s);
+        if (lane == 0) hb = s;
+      }
+      __syncthreads();
+      const double nr2 = hb, x0 = v[j];
+      const double nr = sqrt(nr2);
+      const double alpha = (x0 >= 0.0) ? -nr : nr;
+      const double v0 = x0 - alpha;
+      const double vtv = v0 * v0 + (nr2 - x0 * x0);
+      const double beta = (vtv > 0.0 && nr > 0.0) ? 2.0 / vtv : 0.0;
+      const double rjj = (nr > 0.0) ? alpha : x0;
+      if (tid == 0) sgn[j] = (rjj < 0.0) ? -1.0 : 1.0;
+      const int is = j + ((q - j) & 3);
+      const bool upd = c > j && c < n;
+      {
+        double a0 = 0.0, a1 = 0.0;
+        if (upd) {
+          int l = is;
+          if (l == j) {
+            a0 = v0 * Rw[at(j, c)];
+            l += 4;
+          }
+          for (; l + 4 < n; l += 8) {
+            a0 += v[l] * Rw[at(l, c)];
+            a1 += v[l + 4] * Rw[at(l + 4, c)];
+          }
+          if (l < n) a0 += v[l] * Rw[at(l, c)];
+        }
+        part[q][c] = a0 + a1;
+      }
+      __syncthreads();
+      if (upd) {
+        const double fj = beta * (((part[0][c] + part[1][c]) + part[2][c]) + part[3][c]);
+        for (int l = is; l < n; l += 4) Rw[at(l, c)] -= fj * ((l == j) ? v0 : v[l]);
+      } else if (c == j) {
+        for (int l = is; l < n; l += 4) Rw[at(l, j)] = (l == j) ? rjj : 0.0;
+      }
+      __syncthreads();
+    }
+    if (c < n)
+      for (int l = si + ((q - si) & 3); l < n; l += 4) Rw[at(l, c)] *= sgn[l];
+    __syncthreads();
+    swapped = true;
+  }
+  if (!swapped) return;
+  for (int idx = tid; idx < n * n; idx += kSrThreads)
+    Rt[(idx % n) * static_cast<int64_t>(n) + idx / n] = Rw[idx];
+  {
+    double s = 0.0;
+    if (c < n)
+      for (int l = c + ((q - c) & 3); l < n; l += 4) {
+        const double x = Rw[at(c, l)];
+        s += x * x;
+      }
+    part[q][c] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double lim = tau * *sigma;
+    tail[n] = 0.0;
+    for (int i = n - 1; i >= 0; --i)
+      tail[i] = tail[i + 1] + (((part[0][i] + part[1][i]) + part[2][i]) + part[3][i]);
+    int r = n;
+    for (int t = 0; t <= n; ++t)
+      if (sqrt(tail[t]) <= lim) {
+        r = t;
+        break;
+      }
+    *rank = r;
   }
 }
 
@@ -368,12 +574,13 @@ size_t rr_extra_bytes(int n) {
   const size_t nn = static_cast<size_t>(n) * n * sizeof(double);
   return static_cast<size_t>(kRrSplits) * n * sizeof(double)  // norm partials
          + n * sizeof(double)                                 // d
-         + 4 * nn                                             // W, Rt, Rs, Rw
+         + 5 * nn                                             // W, Rt, Rs, Rw, Ri
+         + 256                                                // ||R||_2
          + 2 * n * sizeof(int) + 256;                         // piv, rank
 }
 
 hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ldx, double* P,
-                           int k, const double* Rp, double tau, unsigned char* extra,
+                           int k, const double* Rp, double tau, double f, unsigned char* extra,
                            double* R, int64_t ldr, int* piv_out, int* rank_out, int* status,
                            double** Rs_out, hipStream_t st, int stage) {
   double* part = reinterpret_cast<double*>(extra);
@@ -382,6 +589,8 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
   double* Rt = W + static_cast<size_t>(n) * n;
   double* Rs = Rt + static_cast<size_t>(n) * n;
   double* Rw = Rs + static_cast<size_t>(n) * n;
+  double* Ri = Rw + static_cast<size_t>(n) * n;
+  double* sig = Ri + static_cast<size_t>(n) * n;
   *Rs_out = Rs;
   if (stage == 0) {
     // column norms of X and the normalised sketch
@@ -397,8 +606,11 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
     return hipGetLastError();
   }
   qrcp_kernel<<<1, kQcpThreads, 0, st>>>(Rp, n, W, Rt, Rw, piv_out);
-  rr_finish_kernel<<<1, kFinThreads, 0, st>>>(Rt, Rw, n, tau, d, piv_out, R, ldr, Rs, rank_out,
-                                              status);
+  rr_rank_kernel<<<1, kFinThreads, 0, st>>>(Rt, Rw, n, tau, d, sig, rank_out, status);
+  if (f > 0.0)
+    srrqr_kernel<<<1, kSrThreads, 0, st>>>(Rt, Rw, Ri, n, tau, f, sig, piv_out, rank_out);
+  const unsigned out_blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(n * n, 256), 256));
+  rr_out_kernel<<<out_blocks, 256, 0, st>>>(Rt, n, d, piv_out, rank_out, R, ldr, Rs);
   return hipGetLastError();
 }
 

@@ -128,9 +128,10 @@ def test_rr_argument_errors_without_gpu():
     assert L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 3) == 0
 
     def call(X=256, m=1000, n=10, ldx=1000, k=30, kind=rq.GAUSSIAN, prec=rq.F64, passes=1,
-             tau=1e-12, Q=256, ldq=1000, R=256, ldr=10, piv=256, rank=256, ws=256, wsb=1 << 30):
-        return L.rcholqr_rr(vp(X), m, n, ldx, k, 1, kind, prec, passes, tau, vp(Q), ldq, vp(R),
-                            ldr, vp(piv), vp(rank), vp(ws), wsb, None)
+             tau=1e-12, f=1.5, Q=256, ldq=1000, R=256, ldr=10, piv=256, rank=256, ws=256,
+             wsb=1 << 30):
+        return L.rcholqr_rr(vp(X), m, n, ldx, k, 1, kind, prec, passes, tau, f, vp(Q), ldq,
+                            vp(R), ldr, vp(piv), vp(rank), vp(ws), wsb, None)
     assert call(X=0) == -1
     assert call(m=5) == -2
     assert call(n=0) == -3
@@ -142,13 +143,16 @@ def test_rr_argument_errors_without_gpu():
     assert call(passes=3) == -9
     assert call(tau=-1.0) == -10
     assert call(tau=float("nan")) == -10
-    assert call(Q=0) == -11
-    assert call(ldq=10) == -12
-    assert call(R=0) == -13
-    assert call(ldr=3) == -14
-    assert call(piv=0) == -15
-    assert call(rank=0) == -16
-    assert call(ws=0) == -17
-    assert call(wsb=16) == -18
+    assert call(f=1.0) == -11
+    assert call(f=0.5) == -11
+    assert call(f=float("inf")) == -11
+    assert call(Q=0) == -12
+    assert call(ldq=10) == -13
+    assert call(R=0) == -14
+    assert call(ldr=3) == -15
+    assert call(piv=0) == -16
+    assert call(rank=0) == -17
+    assert call(ws=0) == -18
+    assert call(wsb=16) == -19
     need2 = L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 2)
-    assert call(passes=2, wsb=need2 - 1) == -18
+    assert call(passes=2, wsb=need2 - 1) == -19

@@ -135,3 +135,38 @@ def test_rr_two_pass(rq, orc, precision, n, rho):
     else:
         assert orth <= 1e-5
         assert err.max() <= 1e-4
+
+
+def _graded(m, n, seed):
+    """U diag(10^(-14 t)) V^T: singular values without a gap, so that column
+    pivoting alone leaves a pair for the strong RRQR swaps."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return np.asfortranarray((U * np.logspace(0, -14, n)) @ V.T)
+
+
+@pytest.mark.parametrize("m,n,seed,kind", [(4000, 64, 1, 0), (4000, 64, 3, 0), (8000, 200, 1, 1)])
+def test_rr_strong_swaps_f64(rq, orc, m, n, seed, kind):
+    """Inputs where the strong RRQR swaps act (the oracle counts at least
+    one): rank, pivots, Q and R as the oracle's; with f = 0 the pivots of
+    column pivoting alone."""
+    k, tau = 3 * n, 1e-7
+    X = _graded(m, n, seed)
+    ref = orc.rr_rcholqr(X, k, seed, kind, tau=tau, f=1.5)
+    assert ref["swaps"] >= 1
+    Q, R, piv, r = rq.rr(_gpu(X), k, seed, kind, tau=tau, f=1.5)
+    assert r == ref["rank"]
+    piv = _np(piv)
+    assert np.array_equal(piv[:r], ref["piv"][:r])
+    Q, R = _np(Q), _np(R)
+    assert np.linalg.norm(Q - ref["Q"]) <= 1e-7 * np.linalg.norm(ref["Q"])
+    Rx, Rx_ref = _back_to_x_order(R, piv), _back_to_x_order(ref["R"], ref["piv"])
+    assert np.linalg.norm(Rx - Rx_ref) <= 1e-7 * np.linalg.norm(Rx_ref)
+    assert np.linalg.cond(Q) <= 10
+    ref0 = orc.rr_rcholqr(X, k, seed, kind, tau=tau, f=0.0)
+    _, _, piv0, r0 = rq.rr(_gpu(X), k, seed, kind, tau=tau, f=0.0)
+    piv0 = _np(piv0)
+    assert r0 == ref0["rank"]
+    assert np.array_equal(piv0[:r0], ref0["piv"][:r0])
+    assert not np.array_equal(piv0[:r], piv[:r])

@@ -601,3 +601,62 @@ def test_rr_rcholqr2_low_rank_restores_orthogonality(orc):
     XP = X[:, two["piv"]]
     err = np.linalg.norm(XP - Q @ R, axis=0) / np.linalg.norm(XP, axis=0)
     assert err.max() <= 1e-9
+
+
+def _kahan(n, c):
+    s = math.sqrt(1.0 - c * c)
+    K = np.diag(s ** np.arange(n)) @ (np.eye(n) - c * np.triu(np.ones((n, n)), 1))
+    return K * (1.0 - 1e-10) ** np.arange(n)[None, :]  # column pivoting keeps the order
+
+
+def _ge_bound(n, k, f):
+    return math.sqrt(1.0 + f * f * k * (n - k))
+
+
+def test_strong_rrqr_reveals_the_kahan_rank(orc):
+    """Kahan's matrix (n = 32, c = 0.285) defeats column pivoting: it keeps the
+    natural order and leaves R[n-1, n-1] ~ 0.27 while sigma_n ~ 2e-4.  The
+    strong RRQR swaps meet Gu and Eisenstat's bounds for k = n - 1:
+    sigma_i(R11) >= sigma_i / b and sigma_j(R22) <= sigma_{k+j} b with
+    b = sqrt(1 + f^2 k (n - k)), and R is the QR factor of K[:, perm]."""
+    n, f = 32, 1.5
+    K = _kahan(n, 0.285)
+    sv = np.linalg.svd(K, compute_uv=False)
+    R0, piv0 = orc.qrcp(K)
+    assert np.array_equal(piv0, np.arange(n))
+    assert R0[-1, -1] > 1e3 * sv[-1]
+    R, perm, swaps = orc.strong_rrqr(R0, n - 1, f)
+    assert swaps >= 1
+    b = _ge_bound(n, n - 1, f)
+    s11 = np.linalg.svd(R[:-1, :-1], compute_uv=False)
+    assert np.all(s11 >= sv[:-1] / b)
+    assert abs(R[-1, -1]) <= sv[-1] * b
+    Rl = np.linalg.qr(K[:, perm], mode="r")
+    Rl = np.sign(np.diag(Rl))[:, None] * Rl
+    assert np.allclose(R, Rl, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_strong_rrqr_bounds_on_a_graded_spectrum(orc, seed):
+    """X = U diag(10^(-14 t)) V^T (n = 64, no gap): at k = the rule's rank the
+    singular values of R11 and R22 after the swaps are within Gu and
+    Eisenstat's factor of X's, and rr_rcholqr's Q and R factor X Pi."""
+    rng = np.random.default_rng(seed)
+    m, n, k = 4000, 64, 192
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    X = np.asfortranarray((U * np.logspace(0, -14, n)) @ V.T)
+    out = orc.rr_rcholqr(X, k, seed, G, tau=1e-7)
+    r, Rn = out["rank"], out["Rn"]
+    assert out["swaps"] >= 1
+    # Rn factors the normalised sketch; compare with its own singular values
+    Pn = orc.sketch(G, X, k, seed) / np.linalg.norm(X, axis=0)
+    sv = np.linalg.svd(Pn[:, out["piv"]], compute_uv=False)
+    b = _ge_bound(n, r, 1.5)
+    assert np.all(np.linalg.svd(Rn[:r, :r], compute_uv=False) >= sv[:r] / b * (1 - 1e-9))
+    assert np.all(np.linalg.svd(Rn[r:, r:], compute_uv=False) <= sv[r:] * b * (1 + 1e-9) + 1e-15)
+    Q, R, piv = out["Q"], out["R"], out["piv"]
+    assert np.linalg.cond(Q) <= 10
+    XP = X[:, piv]
+    err = np.linalg.norm(XP - Q @ R) / np.linalg.norm(XP)
+    assert err <= 1e-6
