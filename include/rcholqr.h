@@ -43,11 +43,16 @@ extern "C" {
 
 /* Sketching embeddings (Section 2): rescaled Gaussian (entries z/sqrt(k),
  * z ~ N(0,1) by Box-Muller), Rademacher (+-1/sqrt(k)), CountSketch (one
- * +-1 per column of Theta at a hashed row, no scaling). */
+ * +-1 per column of Theta at a hashed row, no scaling), SRHT (subsampled
+ * randomized Hadamard transform sqrt(m'/k) S H D, m' = 2^ceil(log2 m): random
+ * signs D, the normalised Sylvester-Hadamard matrix H, k rows sampled
+ * uniformly and independently; entries d_j (-1)^popcount(s_i & j) / sqrt(k),
+ * formed on the fly, so no transform of X is stored). */
 enum rcholqr_sketch_kind {
   RCHOLQR_GAUSSIAN = 0,
   RCHOLQR_RADEMACHER = 1,
-  RCHOLQR_COUNTSKETCH = 2
+  RCHOLQR_COUNTSKETCH = 2,
+  RCHOLQR_SRHT = 3
 };
 
 /* Working precision of the dominant (tall) operations.
@@ -55,11 +60,11 @@ enum rcholqr_sketch_kind {
  *   F32:   X, Q FP32; sketch accumulated in FP64; solves and Gram with
  *          FP32 accuracy on bf16 matrix cores (each FP32 operand split
  *          exactly into three bf16 parts, six products kept).
- *   MIXED: X, Q FP32; Rademacher sketch computed exactly on int8 matrix
- *          cores (each column of X rounded to a 24-bit fixed-point value
- *          under a power-of-two scale, three byte planes times the +-1
+ *   MIXED: X, Q FP32; Rademacher or SRHT sketch computed exactly on int8
+ *          matrix cores (each column of X rounded to a 24-bit fixed-point
+ *          value under a power-of-two scale, three byte planes times the +-1
  *          entries, integer sums folded into FP64); solves and Gram as F32.
- *          Requires RCHOLQR_RADEMACHER.
+ *          Requires RCHOLQR_RADEMACHER or RCHOLQR_SRHT.
  * In every precision the small k x n QR, the Cholesky factorisation and
  * the R' R_s product run in FP64 on the GPU (Section 5: minor operations
  * in higher precision). */
@@ -191,11 +196,13 @@ int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
 /* Test-only export of raw Theta entries (before 1/sqrt(k) scaling):
  * out[ii + jj*ni] = Theta(i0+ii, j0+jj) for 0 <= ii < ni, 0 <= jj < nj, as
  * FP64 (Gaussian z, +-1, or the CountSketch column: s(j) at row h(j),
- * zero elsewhere).  Lets tests compare Theta with the oracle bit for bit.
- * Requires 0 <= i0, i0+ni <= k, 0 <= j0, ni*nj <= 2^26. */
-int rcholqr_debug_theta(int sketch_kind, int64_t k, uint64_t seed, int64_t i0,
-                        int64_t ni, int64_t j0, int64_t nj, double* out,
-                        void* stream);
+ * zero elsewhere).  m is the row count of the X that Theta is for (only the
+ * SRHT depends on it, through m').  Lets tests compare Theta with the oracle
+ * bit for bit.  Requires m >= 1, 0 <= i0, i0+ni <= k, 0 <= j0,
+ * ni*nj <= 2^26. */
+int rcholqr_debug_theta(int sketch_kind, int64_t k, int64_t m, uint64_t seed,
+                        int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                        double* out, void* stream);
 
 /* Test-only: Q = X R^{-1} by the library's tall triangular solve for an
  * upper triangular FP64 R (n x n, ld = ldr, positive diagonal), in the

@@ -5,7 +5,8 @@ this package.  It shares no code with the HIP product path and never
 imports it.  Every routine follows a passage of Balabanov, "Randomized
 Cholesky QR factorizations":
 
-* ``sketch``            -- Algorithm 2 step 1, P = Theta X (Section 2 embeddings)
+* ``sketch``            -- Algorithm 2 step 1, P = Theta X (Section 2 embeddings;
+                           the SRHT by its fast Walsh-Hadamard form, ``fwht``)
 * ``householder_qr``    -- Algorithm 2 step 2, Householder as in Section 6.1
 * ``trsm_rows``         -- Algorithm 2 step 3, row-wise forward substitution
 * ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
@@ -29,7 +30,9 @@ import numpy as np
 
 from . import build as _build
 
-GAUSSIAN, RADEMACHER, COUNTSKETCH, IDENTITY = 0, 1, 2, 99
+GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, IDENTITY = 0, 1, 2, 3, 99
+
+SRHT_TAG_SIGNS, SRHT_TAG_ROWS = 0x53524844, 0x53524853  # "SRHD", "SRHS"
 
 _lib = None
 
@@ -108,9 +111,75 @@ def sincos2pi_dyadic(b: int):
     return s.value, c.value
 
 
+def srht_log2(m):
+    """L with m' = 2^L the least power of two >= m."""
+    L = 0
+    while (1 << L) < m:
+        L += 1
+    return L
+
+
+def srht_signs(seed, m, j0=0):
+    """The diagonal D of the SRHT for rows j0 .. m-1: d_j = -1 where bit
+    (8e + t) of word q of Philox((blk, 0, SRHD), seed) is set, j = 128 blk +
+    32 q + 4 t + e."""
+    d = np.ones(m - j0)
+    for blk in range(j0 // 128, (m + 127) // 128):
+        w = philox4x32_10((blk & 0xffffffff, blk >> 32, 0, SRHT_TAG_SIGNS),
+                          (seed & 0xffffffff, seed >> 32))
+        for r in range(128):
+            j = 128 * blk + r
+            if j0 <= j < m:
+                q, t, e = r >> 5, (r & 31) >> 2, r & 3
+                if (w[q] >> (8 * e + t)) & 1:
+                    d[j - j0] = -1.0
+    return d
+
+
+def _parity(a):
+    """Parity of the set bits of each non-negative int64 (XOR folding)."""
+    a = np.array(a, dtype=np.int64, copy=True)
+    for sh in (32, 16, 8, 4, 2, 1):
+        a ^= a >> sh
+    return a & 1
+
+
+def srht_rows(seed, k, m):
+    """The k sampled rows of the SRHT, uniform on [0, m') and independent:
+    the top L bits of the 64-bit word (w1 w0) of Philox((i, 0, SRHS), seed)."""
+    L = srht_log2(m)
+    s = np.zeros(k, dtype=np.int64)
+    for i in range(k):
+        w = philox4x32_10((i, 0, 0, SRHT_TAG_ROWS), (seed & 0xffffffff, seed >> 32))
+        x = (w[1] << 32) | w[0]
+        s[i] = 0 if L == 0 else x >> (64 - L)
+    return s
+
+
+def fwht(Y):
+    """Unnormalised fast Walsh-Hadamard transform along axis 0 (length a power
+    of two): Y <- H Y with H the Sylvester-Hadamard matrix of +-1."""
+    Y = np.array(Y, dtype=np.float64, copy=True)
+    h, mp = 1, Y.shape[0]
+    while h < mp:
+        Y = Y.reshape(mp // (2 * h), 2, h, -1)
+        a, b = Y[:, 0].copy(), Y[:, 1].copy()
+        Y[:, 0], Y[:, 1] = a + b, a - b
+        Y = Y.reshape(mp, -1)
+        h *= 2
+    return Y
+
+
 def theta_block(kind, k, m, seed, i0, ni, j0, nj):
     """Raw Theta(i0:i0+ni, j0:j0+nj): z for Gaussian, +-1 for Rademacher,
-    s(j) at row h(j) for CountSketch (no 1/sqrt(k) scaling)."""
+    s(j) at row h(j) for CountSketch, d_j (-1)^popcount(s_i & j) for the
+    SRHT (no 1/sqrt(k) scaling)."""
+    if kind == SRHT:
+        s = srht_rows(seed, k, m)[i0:i0 + ni]
+        d = srht_signs(seed, j0 + nj, j0)
+        j = np.arange(j0, j0 + nj, dtype=np.int64)
+        par = _parity(s[:, None] & j[None, :]).astype(np.float64)
+        return np.asfortranarray((1.0 - 2.0 * par) * d[None, :])
     out = np.zeros((ni, nj), dtype=np.float64, order="F")
     lib().orc_theta_block(kind, k, m, seed, i0, ni, j0, nj, _ptr(out))
     return out
@@ -123,12 +192,22 @@ def countsketch_hash(k, seed, j):
 
 
 def sketch_scale(kind, k):
+    if kind == SRHT:
+        return 1.0 / np.sqrt(k)
     return lib().orc_sketch_scale(kind, k)
 
 
 def sketch(kind, X, k, seed):
+    """P = Theta X (Algorithm 2 step 1).  The SRHT takes its fast form (the
+    n m log m cost the paper counts): signs, the Walsh-Hadamard transform of
+    the rows padded to m' = 2^L, then the sampled rows scaled by 1/sqrt(k)."""
     X = _f64(X)
     m, n = X.shape
+    if kind == SRHT:
+        Y = np.zeros((1 << srht_log2(m), n))
+        Y[:m] = srht_signs(seed, m)[:, None] * X
+        Y = fwht(Y)
+        return np.asfortranarray(Y[srht_rows(seed, k, m)] / np.sqrt(k))
     P = np.zeros((k, n), dtype=np.float64, order="F")
     lib().orc_sketch(kind, m, n, k, seed, _ptr(X), max(m, 1), _ptr(P), k)
     return P
@@ -179,9 +258,20 @@ def rcholqr(X, k, seed, kind=GAUSSIAN, passes=2, want_s=False):
     """Algorithm 2 (passes=1) or Algorithm 3 (passes=2).
 
     Returns dict(Q, R, Rs, Rp, S, status).  FP32 inputs are promoted to
-    FP64 exactly; the oracle always computes in FP64."""
+    FP64 exactly; the oracle always computes in FP64.  The SRHT runs the
+    same steps from the routines above (sketch, Householder, row solve,
+    Gram, Cholesky, product)."""
     X = _f64(X)
     m, n = X.shape
+    if kind == SRHT:
+        Rs, S, st = householder_qr(sketch(SRHT, X, k, seed), want_s)
+        Q = trsm_rows(X, Rs)
+        out = dict(Q=Q, R=Rs, Rs=Rs, Rp=None, S=S, status=int(st))
+        if passes == 2:
+            Rp, st2 = cholesky_upper(gram(Q))
+            out.update(Q=trsm_rows(Q, Rp), R=triu_product(Rp, Rs), Rp=Rp,
+                       status=int(st) or int(st2))
+        return out
     Q = np.zeros((m, n), order="F")
     R = np.zeros((n, n), order="F")
     Rs = np.zeros((n, n), order="F")

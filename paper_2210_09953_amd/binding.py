@@ -4,7 +4,7 @@ import os
 
 import torch
 
-GAUSSIAN, RADEMACHER, COUNTSKETCH = 0, 1, 2
+GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT = 0, 1, 2, 3
 F64, F32, MIXED = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +54,7 @@ def lib():
     L.rcholqr_status.restype = i32
     L.rcholqr_sketch.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, dp, i64, vp, sz, vp]
     L.rcholqr_sketch.restype = i32
-    L.rcholqr_debug_theta.argtypes = [i32, i64, u64, i64, i64, i64, i64, dp, vp]
+    L.rcholqr_debug_theta.argtypes = [i32, i64, i64, u64, i64, i64, i64, i64, dp, vp]
     L.rcholqr_debug_theta.restype = i32
     L.rcholqr_trsm.argtypes = [vp, i64, i64, i64, dp, i64, i32, vp, i64, vp, sz, vp]
     L.rcholqr_trsm.restype = i32
@@ -269,10 +269,12 @@ def sketch(X, k, seed, kind=GAUSSIAN, precision=None, ws=None):
     return P
 
 
-def debug_theta(kind, k, seed, i0, ni, j0, nj, device="cuda"):
-    """Raw Theta(i0:i0+ni, j0:j0+nj) as FP64 (test export)."""
+def debug_theta(kind, k, seed, i0, ni, j0, nj, device="cuda", m=1):
+    """Raw Theta(i0:i0+ni, j0:j0+nj) as FP64 (test export); m, the rows of X,
+    matters for the SRHT only."""
     out = empty_fortran(ni, nj, torch.float64, device)
-    code = lib().rcholqr_debug_theta(kind, k, int(seed), i0, ni, j0, nj, _ptr(out), _stream())
+    code = lib().rcholqr_debug_theta(kind, k, int(m), int(seed), i0, ni, j0, nj, _ptr(out),
+                                     _stream())
     _check(code, "rcholqr_debug_theta")
     return out
 

@@ -166,7 +166,7 @@ extern "C" {
 
 size_t rcholqr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind, int passes,
                                int precision) {
-  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 2 || passes < 1 || passes > 2 ||
+  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 3 || passes < 1 || passes > 2 ||
       precision < 0 || precision > 2)
     return 0;
   return make_layout(m, n, k, sketch_kind, passes, precision).total;
@@ -185,10 +185,10 @@ int check_factor_args(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t 
   if (m < n) return -2;
   if (ldx < m) return -4;
   if (k < n || k > kMaxK) return -5;
-  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (sketch_kind < 0 || sketch_kind > 3) return -7;
   if (passes < 1 || passes > 2) return -8;
   if (precision < 0 || precision > 2) return -9;
-  if (precision == kPrecMixed && sketch_kind != kRademacher) return -9;
+  if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -9;
   if (!Q) return -10;
   if (ldq < m) return -11;
   if (!R) return -12;
@@ -211,7 +211,7 @@ int factor_one(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   if (profile) prof_begin(st);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
-                                at<double>(ws, L.part), P, k, st));
+                                at<double>(ws, L.part), P, k, st, sketch_kind));
   else
     RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
                           at<uint32_t>(ws, L.keys), P, k, st));
@@ -316,7 +316,7 @@ size_t rcholqr_batched_workspace_bytes(const rcholqr_problem* probs, int batch, 
   if (!probs || batch < 1) return 0;
   for (int i = 0; i < batch; ++i)
     if (!valid_dims(probs[i].m, probs[i].n, probs[i].k)) return 0;
-  if (sketch_kind < 0 || sketch_kind > 2 || passes < 1 || passes > 2 || precision < 0 ||
+  if (sketch_kind < 0 || sketch_kind > 3 || passes < 1 || passes > 2 || precision < 0 ||
       precision > 2)
     return 0;
   return batched_offset(probs, batch, sketch_kind, passes, precision);
@@ -326,7 +326,7 @@ int rcholqr_factor_batched(const rcholqr_problem* probs, int batch, int sketch_k
                            int precision, void* ws, size_t ws_bytes, void* stream) {
   if (!probs) return -1;
   if (batch < 1) return -2;
-  if (sketch_kind < 0 || sketch_kind > 2) return -3;
+  if (sketch_kind < 0 || sketch_kind > 3) return -3;
   if (passes < 1 || passes > 2) return -4;
   if (precision < 0 || precision > 2) return -5;
   for (int i = 0; i < batch; ++i) {
@@ -534,7 +534,7 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
   if (l < 1 || k + l > kMaxK) return -6;
   if (sketch_kind != kGaussian && sketch_kind != kRademacher) return -8;
   if (precision < 0 || precision > 2) return -9;
-  if (precision == kPrecMixed && sketch_kind != kRademacher) return -9;
+  if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -9;
   if (!Z) return -10;
   if (ldz < l) return -11;
   if (!R) return -12;
@@ -571,7 +571,7 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
 // factors, gather X Pi into Q, tall solve in place.
 size_t rcholqr_rr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind,
                                   int precision, int passes) {
-  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 2 || precision < 0 ||
+  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 3 || precision < 0 ||
       precision > 2 || passes < 1 || passes > 2)
     return 0;
   return align256(make_layout(m, n, k, sketch_kind, 1, precision).total) +
@@ -588,9 +588,9 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   if (m < n) return -2;
   if (ldx < m) return -4;
   if (k < n || k > kMaxK) return -5;
-  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (sketch_kind < 0 || sketch_kind > 3) return -7;
   if (precision < 0 || precision > 2) return -8;
-  if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
+  if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -8;
   if (passes < 1 || passes > 2) return -9;
   if (!(tau >= 0.0) || !isfinite(tau)) return -10;
   if (!(f == 0.0 || (f > 1.0 && isfinite(f)))) return -11;
@@ -613,7 +613,7 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   int* status = at<int>(ws, L.status);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
-                                at<double>(ws, L.part), P, k, st));
+                                at<double>(ws, L.part), P, k, st, sketch_kind));
   else
     RCQ_TRY(launch_sketch(X, f32, m, ni, ldx, ki, sketch_kind, seed, L.sp, at<double>(ws, L.part),
                           at<uint32_t>(ws, L.keys), P, k, st));
@@ -669,9 +669,9 @@ int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   if (m < n) return -2;
   if (ldx < m) return -4;
   if (k < n || k > kMaxK) return -5;
-  if (sketch_kind < 0 || sketch_kind > 2) return -7;
+  if (sketch_kind < 0 || sketch_kind > 3) return -7;
   if (precision < 0 || precision > 2) return -8;
-  if (precision == kPrecMixed && sketch_kind != kRademacher) return -8;
+  if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -8;
   if (!P) return -9;
   if (ldp < k) return -10;
   if (!ws) return -11;
@@ -680,7 +680,8 @@ int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, static_cast<int>(n), ldx,
-                                static_cast<int>(k), seed, L.sp, at<double>(ws, L.part), P, ldp, st));
+                                static_cast<int>(k), seed, L.sp, at<double>(ws, L.part), P, ldp, st,
+                                sketch_kind));
   else
     RCQ_TRY(launch_sketch(X, precision != kPrecF64, m, static_cast<int>(n), ldx, static_cast<int>(k),
                           sketch_kind, seed, L.sp, at<double>(ws, L.part), at<uint32_t>(ws, L.keys),
@@ -688,15 +689,16 @@ int rcholqr_sketch(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, 
   return 0;
 }
 
-int rcholqr_debug_theta(int sketch_kind, int64_t k, uint64_t seed, int64_t i0, int64_t ni,
-                        int64_t j0, int64_t nj, double* out, void* stream) {
-  if (sketch_kind < 0 || sketch_kind > 2) return -1;
+int rcholqr_debug_theta(int sketch_kind, int64_t k, int64_t m, uint64_t seed, int64_t i0,
+                        int64_t ni, int64_t j0, int64_t nj, double* out, void* stream) {
+  if (sketch_kind < 0 || sketch_kind > 3) return -1;
   if (k < 1 || k > kMaxK) return -2;
-  if (i0 < 0 || ni < 0 || i0 + ni > k) return -4;
-  if (j0 < 0 || nj < 0) return -7;
-  if (ni * nj > (int64_t(1) << 26)) return -6;
-  if (!out && ni * nj > 0) return -8;
-  RCQ_TRY(launch_theta_debug(sketch_kind, static_cast<int>(k), seed, i0, ni, j0, nj, out,
+  if (m < 1) return -3;
+  if (i0 < 0 || ni < 0 || i0 + ni > k) return -5;
+  if (j0 < 0 || nj < 0) return -8;
+  if (ni * nj > (int64_t(1) << 26)) return -7;
+  if (!out && ni * nj > 0) return -9;
+  RCQ_TRY(launch_theta_debug(sketch_kind, static_cast<int>(k), m, seed, i0, ni, j0, nj, out,
                              static_cast<hipStream_t>(stream)));
   return 0;
 }

@@ -9,6 +9,7 @@ namespace rcq {
 constexpr int kGaussian = 0;
 constexpr int kRademacher = 1;
 constexpr int kCountSketch = 2;
+constexpr int kSRHT = 3;
 
 constexpr int kPrecF64 = 0;
 constexpr int kPrecF32 = 1;
@@ -35,8 +36,8 @@ struct GramPlan {
 };
 
 // sketch.hip
-hipError_t launch_theta_debug(int kind, int k, uint64_t seed, int64_t i0, int64_t ni, int64_t j0,
-                              int64_t nj, double* out, hipStream_t st);
+hipError_t launch_theta_debug(int kind, int k, int64_t m, uint64_t seed, int64_t i0, int64_t ni,
+                              int64_t j0, int64_t nj, double* out, hipStream_t st);
 hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
                          int kind, uint64_t seed, const SketchPlan& pl, double* part,
                          uint32_t* keys, double* P, int64_t ldp, hipStream_t st);
@@ -48,12 +49,13 @@ hipError_t launch_sketch_partials(const void* X, bool x_is_f32, int64_t m, int n
                                   int k, int kind, uint64_t seed, const SketchPlan& pl,
                                   double* part, uint32_t* keys, hipStream_t st);
 void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp);
+// kind: kRademacher or kSRHT (the +-1 kinds).
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
-                               hipStream_t st);
+                               hipStream_t st, int kind = kRademacher);
 hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_t ldx, int k,
                                         uint64_t seed, const SketchPlan& pl, double* part,
-                                        hipStream_t st);
+                                        hipStream_t st, int kind = kRademacher);
 
 // rr.hip (rank-revealing variant).  stage 0: column norms d of X and P <-
 // P D^{-1} (P k x n, ld k); stage 1: column-pivoted QR of Rp (n x n), rank,

@@ -1,4 +1,5 @@
-// mixed.hip -- Rademacher sketch P = Theta X for FP32 X on int8 matrix cores.
+// mixed.hip -- Rademacher or SRHT sketch P = Theta X for FP32 X on int8 matrix
+// cores (both kinds have +-1 entries).
 //
 // Section 5 asks for the sketch to be computed more accurately than the
 // working precision.  Here the products Theta X are exact integer sums:
@@ -70,11 +71,11 @@ __device__ __forceinline__ float group_max(float v) {
 // rows) per stage.  NSL: quantiser task slots per thread.  FULL: the tasks
 // fill every slot of every thread (no per-slot guards) and the stage's
 // matrix-core steps are interleaved with the next stage's quantisation.
-template <int TT, int CT, int SB, int NSL, bool FULL>
+template <int TT, int CT, int SB, int NSL, bool FULL, bool SRHT>
 __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
     const float* __restrict__ X, int64_t m, int n, int64_t ldx, int k, uint64_t seed, int wt,
     int wc, int ktiles, int nh, int64_t rows_per_split, int kpad, int npad,
-    double* __restrict__ part) {
+    double* __restrict__ part, int srht_l) {
   constexpr int S = kQBlock * SB;  // rows per stage
   constexpr int KS = S / 64;       // matrix-core steps per stage
   constexpr int LD = S + 16;       // LDS bytes per column of a digit plane
@@ -206,13 +207,20 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
   };
 
   // Philox words of the stage starting at row r0 into buffer buf: draw c is
-  // Theta row theta0 + c % Tg, block (r0 >> 7) + c / Tg.
+  // Theta row theta0 + c % Tg, block (r0 >> 7) + c / Tg.  The block size is a
+  // multiple of Tg, so a thread always draws row theta0 + tid % Tg: its SRHT
+  // sample (srht_l >= 0; -1 means Rademacher) is taken once.
+  constexpr bool srht = SRHT;
+  const uint64_t srow =
+      (srht && theta0 + tid % Tg < k) ? srht_row(seed, theta0 + tid % Tg, srht_l) : 0;
   auto draw = [&](int64_t r0, int buf) {
     for (int c = tid; c < Tg * SB; c += nthr) {
       const int r = c % Tg, sb = c / Tg;
       const int i = theta0 + r;
       Words w{0u, 0u, 0u, 0u};
-      if (i < k) w = radem_words(seed, i, (r0 >> 7) + sb);
+      if (i < k)
+        w = srht ? srht_words(seed, srow, srht_walsh(srow), (r0 >> 7) + sb)
+                 : radem_words(seed, i, (r0 >> 7) + sb);
       uint32_t* z = zb + buf * zb_sz + (sb * Tg + r) * kQZs;
       z[0] = w.w0;
       z[1] = w.w1;
@@ -333,6 +341,7 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
       float fq = 0.f;
       const int pr = tid % Tg, psb = tid / Tg;  // this thread's Philox draw
       PhiloxState ph;
+      uint32_t shi = 0u;  // SRHT: the block's parity term
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -350,9 +359,13 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
           } else if (ks == NSL) {
             if (j == 0) {
               const uint64_t blk = static_cast<uint64_t>((r0 + S) >> 7) + psb;
+              // Rademacher: words (blk, row, RADE); SRHT: the signs (blk, 0, SRHD),
+              // then the row's Walsh pattern and parity term (srht_words)
               ph = PhiloxState{static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
-                               static_cast<uint32_t>(theta0 + pr), kTagRadem,
-                               static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+                               srht ? 0u : static_cast<uint32_t>(theta0 + pr),
+                               srht ? kTagSrhtD : kTagRadem, static_cast<uint32_t>(seed),
+                               static_cast<uint32_t>(seed >> 32)};
+              shi = (srht && (__builtin_popcountll(srow & (blk << 7)) & 1)) ? 0xFFFFFFFFu : 0u;
             }
             if (j < 5) {
               philox_round(ph);
@@ -360,10 +373,18 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
             }
             if (j == 5) {
               uint32_t* z = zb + (cur ^ 1) * zb_sz + (psb * Tg + pr) * kQZs;
-              z[0] = ph.c0;
-              z[1] = ph.c1;
-              z[2] = ph.c2;
-              z[3] = ph.c3;
+              if (srht) {
+                const Words wl = srht_walsh(srow);
+                z[0] = ph.c0 ^ wl.w0 ^ shi;
+                z[1] = ph.c1 ^ wl.w1 ^ shi;
+                z[2] = ph.c2 ^ wl.w2 ^ shi;
+                z[3] = ph.c3 ^ wl.w3 ^ shi;
+              } else {
+                z[0] = ph.c0;
+                z[1] = ph.c1;
+                z[2] = ph.c2;
+                z[3] = ph.c3;
+              }
             }
           }
           if (ks + 1 < KS && j >= NG - TT) {
@@ -487,8 +508,14 @@ void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp) {
 
 hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_t ldx, int k,
                                         uint64_t seed, const SketchPlan& pl, double* part,
-                                        hipStream_t st) {
+                                        hipStream_t st, int kind) {
   const I8Plan p = i8_plan(k, n);
+  if (kind != kRademacher && kind != kSRHT) return hipErrorInvalidValue;
+  const int srht_l = (kind == kSRHT) ? srht_log2(m) : -1;
+  // every thread draws one Theta row: the block is a multiple of Tg
+  const int tt = p.full ? kQMainTT : 4;
+  if ((64 * p.wt * p.wc) % (16 * tt * p.wt) != 0) return hipErrorInvalidValue;
+  const bool sr = kind == kSRHT;
   if (p.ktiles != pl.ktiles || p.kpad != pl.kpad || p.npad != pl.npad ||
       (pl.rows_per_split % (kQBlock * p.sb)) != 0 || (pl.nsplit % 8) != 0 ||
       pl.rows_per_split > (int64_t{1} << 23))
@@ -496,31 +523,37 @@ hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_
   const size_t shm = i8_lds_bytes(p);
   const dim3 grid(pl.nsplit * p.ktiles * p.nh), block(64 * p.wt * p.wc);
   hipError_t e = hipSuccess;
-#define RCQ_I8(TTV, CTV, SBV, NSLV, FV)                                                        \
+#define RCQ_I8(TTV, CTV, SBV, NSLV, FV, SRV)                                                   \
   do {                                                                                         \
     const void* fn =                                                                           \
-        reinterpret_cast<const void*>(&sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV>);            \
+        reinterpret_cast<const void*>(&sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV, SRV>);       \
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,                    \
                             static_cast<int>(shm));                                            \
     if (e != hipSuccess) return e;                                                             \
-    sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV><<<grid, block, shm, st>>>(                       \
+    sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV, SRV><<<grid, block, shm, st>>>(                  \
         X, m, n, ldx, k, seed, p.wt, p.wc, p.ktiles, p.nh, pl.rows_per_split, pl.kpad, pl.npad, \
-        part);                                                                                 \
+        part, srht_l);                                                                         \
   } while (0)
-  if (p.full)
-    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true);
+  if (p.full && sr)
+    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true, true);
+  else if (p.full)
+    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true, false);
+  else if (p.ct == 2 && sr)
+    RCQ_I8(4, 2, 1, 2, false, true);
   else if (p.ct == 2)
-    RCQ_I8(4, 2, 1, 2, false);
+    RCQ_I8(4, 2, 1, 2, false, false);
+  else if (sr)
+    RCQ_I8(4, 1, 1, 2, false, true);
   else
-    RCQ_I8(4, 1, 1, 2, false);
+    RCQ_I8(4, 1, 1, 2, false, false);
 #undef RCQ_I8
   return hipGetLastError();
 }
 
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
-                               hipStream_t st) {
-  const hipError_t e = launch_sketch_mixed_partials(X, m, n, ldx, k, seed, pl, part, st);
+                               hipStream_t st, int kind) {
+  const hipError_t e = launch_sketch_mixed_partials(X, m, n, ldx, k, seed, pl, part, st, kind);
   if (e != hipSuccess) return e;
   return launch_sketch_reduce(part, pl, k, n, 1.0 / sqrt(static_cast<double>(k)), P, ldp, st);
 }

@@ -23,8 +23,8 @@ namespace rcq {
 
 // ----------------------------------------------------------------------------
 // Theta export for tests.
-__global__ void theta_debug_kernel(int kind, int k, uint64_t seed, int64_t i0, int64_t ni,
-                                   int64_t j0, int64_t nj, double* out) {
+__global__ void theta_debug_kernel(int kind, int k, int64_t m, uint64_t seed, int64_t i0,
+                                   int64_t ni, int64_t j0, int64_t nj, double* out) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= ni * nj) return;
   const int64_t ii = idx % ni, jj = idx / ni;
@@ -36,6 +36,10 @@ __global__ void theta_debug_kernel(int kind, int k, uint64_t seed, int64_t i0, i
     v = (i & 1) ? z1 : z0;
   } else if (kind == kRademacher) {
     const Words w = radem_words(seed, static_cast<int>(i), j >> 7);
+    v = radem_bit(w, static_cast<int>(j & 127)) ? -1.0 : 1.0;
+  } else if (kind == kSRHT) {
+    const uint64_t sr = srht_row(seed, static_cast<int>(i), srht_log2(m));
+    const Words w = srht_words(seed, sr, srht_walsh(sr), j >> 7);
     v = radem_bit(w, static_cast<int>(j & 127)) ? -1.0 : 1.0;
   } else {
     int h, neg;
@@ -78,8 +82,11 @@ __global__ __launch_bounds__(256, 2) void sketch_dense_kernel(const TX* __restri
   d4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
-  Words rw{0u, 0u, 0u, 0u};  // Rademacher words of this lane's Theta row
+  Words rw{0u, 0u, 0u, 0u};  // Rademacher or SRHT words of this lane's Theta row
   int64_t rblk = -1;
+  const bool srht = kind == kSRHT;
+  const uint64_t srow = srht ? srht_row(seed, ibase + l16, srht_log2(m)) : 0;
+  const Words swal = srht_walsh(srow);
 
   // X prefetch: element e of thread t is row t % 16, column t / 16 + 16 e.
   const int pjj = threadIdx.x & 15, pc0 = threadIdx.x >> 4;
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(256, 2) void sketch_dense_kernel(const TX* __restri
       const int ii = lane & 15, jj0 = 4 * (lane >> 4);
       const int64_t blk = r0 >> 7;
       if (blk != rblk) {
-        rw = radem_words(seed, ibase + ii, blk);
+        rw = srht ? srht_words(seed, srow, swal, blk) : radem_words(seed, ibase + ii, blk);
         rblk = blk;
       }
       const int o = static_cast<int>(r0 & 127) + jj0;
@@ -259,12 +266,12 @@ __global__ __launch_bounds__(256) void count_accum_kernel(const TX* __restrict__
 // ----------------------------------------------------------------------------
 // Host-side launchers.
 
-hipError_t launch_theta_debug(int kind, int k, uint64_t seed, int64_t i0, int64_t ni, int64_t j0,
-                              int64_t nj, double* out, hipStream_t st) {
+hipError_t launch_theta_debug(int kind, int k, int64_t m, uint64_t seed, int64_t i0, int64_t ni,
+                              int64_t j0, int64_t nj, double* out, hipStream_t st) {
   const int64_t total = ni * nj;
   if (total == 0) return hipSuccess;
-  theta_debug_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, st>>>(kind, k, seed, i0,
-                                                                                  ni, j0, nj, out);
+  theta_debug_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, st>>>(
+      kind, k, m, seed, i0, ni, j0, nj, out);
   return hipGetLastError();
 }
 

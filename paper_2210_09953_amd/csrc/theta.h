@@ -32,6 +32,8 @@ namespace rcq {
 constexpr uint32_t kTagGauss = 0x47415553u;  // "GAUS"
 constexpr uint32_t kTagRadem = 0x52414445u;  // "RADE"
 constexpr uint32_t kTagCount = 0x434F554Eu;  // "COUN"
+constexpr uint32_t kTagSrhtD = 0x53524844u;  // "SRHD"
+constexpr uint32_t kTagSrhtS = 0x53524853u;  // "SRHS"
 
 struct Words {
   uint32_t w0, w1, w2, w3;
@@ -182,6 +184,50 @@ __device__ __forceinline__ uint32_t radem_bit(const Words& w, int r) {
   const int q = r >> 5, t = (r & 31) >> 2, e = r & 3;
   const uint32_t word = (q == 0) ? w.w0 : (q == 1) ? w.w1 : (q == 2) ? w.w2 : w.w3;
   return (word >> (8 * e + t)) & 1u;
+}
+
+// SRHT, Theta = sqrt(m'/k) S H D (m' = 2^L >= m, X padded with zero rows):
+// D the diagonal of signs d_j, H the Sylvester-Hadamard matrix normalised by
+// 1/sqrt(m') (H_sj = (-1)^popcount(s & j)), S the sampling of k rows s_i,
+// uniform on [0, m') and independent.  Raw entry: d_j (-1)^popcount(s_i & j),
+// with 1/sqrt(k) on P as for the other dense kinds.  d_j of the 128 columns
+// of block blk are the bits of the words (blk, 0, SRHD) in radem_bit's
+// layout; s_i is the top L bits of the 64-bit word (i, 0, SRHS).
+__host__ __device__ inline int srht_log2(int64_t m) {
+  int L = 0;
+  while ((int64_t{1} << L) < m) ++L;
+  return L;
+}
+
+__device__ __forceinline__ uint64_t srht_row(uint64_t seed, int i, int L) {
+  const Words w = theta_words(seed, i, 0u, kTagSrhtS);
+  const uint64_t x = (static_cast<uint64_t>(w.w1) << 32) | w.w0;
+  return (L == 0) ? 0 : (x >> (64 - L));
+}
+
+// (-1)^popcount(s & r) for the 128 offsets r of a block, in radem_bit's
+// layout (bit 8e + t of word q is offset 32q + 4t + e): parity is linear in
+// r, so a word is a byte pattern over t, a byte mask over e and a constant
+// over q.
+__device__ __forceinline__ Words srht_walsh(uint64_t s) {
+  const uint32_t se = static_cast<uint32_t>(s) & 3u, st = (static_cast<uint32_t>(s) >> 2) & 7u;
+  const uint32_t sq = (static_cast<uint32_t>(s) >> 5) & 3u;
+  uint32_t bt = 0u, em = 0u;
+  for (uint32_t t = 0; t < 8; ++t) bt |= (__builtin_popcount(st & t) & 1u) << t;
+  for (uint32_t e = 0; e < 4; ++e)
+    if (__builtin_popcount(se & e) & 1u) em |= 0xFFu << (8 * e);
+  const uint32_t base = bt * 0x01010101u ^ em;
+  return {base, (sq & 1u) ? ~base : base, (sq & 2u) ? ~base : base,
+          (__builtin_popcount(sq) & 1u) ? ~base : base};
+}
+
+// SRHT words of Theta row i (sample s, Walsh pattern wal of s) for block blk.
+__device__ __forceinline__ Words srht_words(uint64_t seed, uint64_t s, const Words& wal,
+                                            int64_t blk) {
+  const Words d = theta_words(seed, blk, 0u, kTagSrhtD);
+  const uint32_t hi =
+      (__builtin_popcountll(s & (static_cast<uint64_t>(blk) << 7)) & 1) ? 0xFFFFFFFFu : 0u;
+  return {d.w0 ^ wal.w0 ^ hi, d.w1 ^ wal.w1 ^ hi, d.w2 ^ wal.w2 ^ hi, d.w3 ^ wal.w3 ^ hi};
 }
 
 // CountSketch bucket and sign of column j.

@@ -660,3 +660,53 @@ def test_strong_rrqr_bounds_on_a_graded_spectrum(orc, seed):
     XP = X[:, piv]
     err = np.linalg.norm(XP - Q @ R) / np.linalg.norm(XP)
     assert err <= 1e-6
+
+
+# ----------------------------------------------------------------------------- SRHT
+@pytest.mark.parametrize("m", [1000, 300, 1])
+def test_srht_theta_is_signed_sylvester_hadamard(orc, m):
+    """Theta's raw entries are d_j H[s_i, j] with H scipy's Sylvester-Hadamard
+    matrix of order m' = 2^ceil(log2 m), d_j = +-1 and s_i in [0, m')."""
+    k, seed = 40, 7
+    mp = 1 << orc.srht_log2(m)
+    assert mp >= m and (mp == 1 or mp < 2 * m)
+    th = orc.theta_block(orc.SRHT, k, m, seed, 0, k, 0, m)
+    d = orc.srht_signs(seed, m)
+    s = orc.srht_rows(seed, k, m)
+    assert np.all(np.abs(d) == 1) and np.all((0 <= s) & (s < mp))
+    assert np.array_equal(th, scipy.linalg.hadamard(mp)[s][:, :m] * d[None, :])
+    # a block away from the origin equals the same rows of the full block
+    if m == 1000:
+        assert np.array_equal(orc.theta_block(orc.SRHT, k, m, seed, 5, 20, 130, 300),
+                              th[5:25, 130:430])
+
+
+@pytest.mark.parametrize("m,n", [(1000, 12), (513, 5), (1, 3)])
+def test_srht_fast_transform_equals_the_dense_theta(orc, m, n):
+    """The oracle's SRHT sketch (signs, fast Walsh-Hadamard transform of the
+    zero-padded rows, sampling, 1/sqrt(k)) equals Theta X / sqrt(k) formed
+    from the closed-form entries."""
+    k = 3 * n
+    X = np.random.default_rng(m).standard_normal((m, n))
+    P = orc.sketch(orc.SRHT, X, k, 11)
+    th = orc.theta_block(orc.SRHT, k, m, 11, 0, k, 0, m)
+    assert np.allclose(P, th @ X / np.sqrt(k), rtol=0, atol=1e-13 * np.abs(X).sum(axis=0).max())
+
+
+def test_srht_is_an_embedding_and_rcholqr_is_stable(orc):
+    """Orthonormal U (m = 8192, n = 32): the singular values of Theta U lie in
+    [1 - eps, 1 + eps] with eps ~ 0.6 at k = 3n, as for the Gaussian
+    embedding; RCholeskyQR2 with the SRHT at kappa = 1e10 gives an orthonormal
+    Q to ~u and R as LAPACK's Householder R."""
+    U = synth.make_x(8192, 32, 1.0, seed=3)
+    sv = np.linalg.svd(orc.sketch(orc.SRHT, U, 96, 5), compute_uv=False)
+    assert sv.min() >= 0.3 and sv.max() <= 1.7
+    X = synth.make_x(8192, 32, 1e-10, seed=4)
+    out = orc.rcholqr(X, 96, 5, orc.SRHT, passes=2)
+    assert out["status"] == 0
+    Q, R = out["Q"], out["R"]
+    assert np.linalg.norm(Q.T @ Q - np.eye(32), 2) <= 1e-13
+    Rl = np.linalg.qr(X, mode="r")
+    Rl = np.sign(np.diag(Rl))[:, None] * Rl
+    for j in range(32):
+        assert np.linalg.norm(R[:, j] - Rl[:, j]) <= 1e-6 * np.linalg.norm(X[:, j])
