@@ -345,6 +345,8 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-reduced-leg", action="store_true",
                     help="skip the Reduced RCholeskyQR figure")
+    ap.add_argument("--no-srht-leg", action="store_true",
+                    help="skip the SRHT-sketch factorisation of the same X")
     ap.add_argument("--no-rr-leg", action="store_true",
                     help="skip the rank-revealing RCholeskyQR figure")
     ap.add_argument("--no-cpu", action="store_true")
@@ -419,6 +421,20 @@ def main():
         log(f"[bench] reduced (l={l}): {ms_r:.3f} ms/step {red['value']} GB/s "
             f"||S^T S - I|| = {orth_s:.2e}")
 
+    # The same factorisation with the SRHT sketch (the ±1 kinds share the
+    # int8 path).
+    srht = None
+    if not args.no_srht_leg and kind == rq.RADEMACHER:
+        ms_s, ph_s, Q_s, R_s = time_leg(torch, rq, X, k, rq.SRHT, prec_code, args.steps,
+                                        args.warmup)
+        orth_s2, res_s2 = quality(torch, X, Q_s, R_s)
+        srht = {"value": round(m * n * xbytes / (ms_s * 1e-3) / 1e9, 2), "unit": "GB/s",
+                "ms_per_step": round(ms_s, 4), "orth": orth_s2, "resid": res_s2,
+                "phases_ms": {p: round(v, 4) for p, v in ph_s.items()}}
+        log(f"[bench] srht: {ms_s:.3f} ms/step {srht['value']} GB/s orth={orth_s2:.2e} "
+            f"resid={res_s2:.2e} sketch={ph_s.get('sketch', 0.0):.3f} ms")
+        del Q_s, R_s
+
     # Rank-revealing RCholeskyQR on the same X.
     rrf = None
     if not args.no_rr_leg:
@@ -482,6 +498,7 @@ def main():
         "phase_rooflines": phase_roof,
         "fp64": fp64,
         "reduced": red,
+        "srht": srht,
         "rank_revealing": rrf,
         "cpu_baseline": cpu,
     }

@@ -341,7 +341,10 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
       float fq = 0.f;
       const int pr = tid % Tg, psb = tid / Tg;  // this thread's Philox draw
       PhiloxState ph;
-      uint32_t shi = 0u;  // SRHT: the block's parity term
+      // SRHT sample packed in one register: s >> 7 in bits 0..24, s & 127 in
+      // 25..31 (s < 2^32 here: the launch checks m' <= 2^32)
+      const uint32_t spk = static_cast<uint32_t>(srow >> 7) |
+                           (static_cast<uint32_t>(srow & 127u) << 25);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -365,7 +368,6 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
                                srht ? 0u : static_cast<uint32_t>(theta0 + pr),
                                srht ? kTagSrhtD : kTagRadem, static_cast<uint32_t>(seed),
                                static_cast<uint32_t>(seed >> 32)};
-              shi = (srht && (__builtin_popcountll(srow & (blk << 7)) & 1)) ? 0xFFFFFFFFu : 0u;
             }
             if (j < 5) {
               philox_round(ph);
@@ -374,7 +376,9 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
             if (j == 5) {
               uint32_t* z = zb + (cur ^ 1) * zb_sz + (psb * Tg + pr) * kQZs;
               if (srht) {
-                const Words wl = srht_walsh(srow);
+                const uint32_t blk32 = static_cast<uint32_t>(((r0 + S) >> 7) + psb);
+                const uint32_t shi = (__builtin_popcount(spk & 0x1FFFFFFu & blk32) & 1) ? ~0u : 0u;
+                const Words wl = srht_walsh(spk >> 25);
                 z[0] = ph.c0 ^ wl.w0 ^ shi;
                 z[1] = ph.c1 ^ wl.w1 ^ shi;
                 z[2] = ph.c2 ^ wl.w2 ^ shi;
@@ -516,6 +520,7 @@ hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_
   const int tt = p.full ? kQMainTT : 4;
   if ((64 * p.wt * p.wc) % (16 * tt * p.wt) != 0) return hipErrorInvalidValue;
   const bool sr = kind == kSRHT;
+  if (sr && p.full && srht_l > 32) return hipErrorInvalidValue;  // X would exceed 500 GB
   if (p.ktiles != pl.ktiles || p.kpad != pl.kpad || p.npad != pl.npad ||
       (pl.rows_per_split % (kQBlock * p.sb)) != 0 || (pl.nsplit % 8) != 0 ||
       pl.rows_per_split > (int64_t{1} << 23))
