@@ -181,6 +181,39 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
                double f, void* Q, int64_t ldq, double* R, int64_t ldr, int* piv,
                int* rank, void* ws, size_t ws_bytes, void* stream);
 
+/* Column-oriented RCholeskyQR (Algorithm 4, Section 3.2), one block per
+ * call: with Q_{1:j0}, S_{1:j0} and R_{1:j0,1:j0} from the calls for the
+ * previous blocks (j0 = 0 for the first), factor the next b columns X_b
+ * (which an application such as a block Krylov method builds from Q_{1:j0}):
+ *   P_b = Theta X_b (the same Theta as for the whole matrix);
+ *   R_{1:j0,b} = S_{1:j0}^T P_b (the least-squares solution for orthonormal
+ *   S); [S_b, R_bb] = QR(P_b - S_{1:j0} R_{1:j0,b}) (Householder, FP64);
+ *   Q_b = (X_b - Q_{1:j0} R_{1:j0,b}) R_bb^{-1} by the tall forward
+ *   substitution.  Block by block this computes what Algorithm 2 computes
+ *   on the whole matrix.
+ *
+ *  Xb     [in]  m x b, ld ldx >= m, FP64 or FP32 as the precision; may be
+ *               Q's own columns j0..j0+b-1 (then nothing is copied).
+ *  j0, b  columns already factored and the block width; j0 + b <= 256,
+ *         j0 + b <= k <= 1024, m >= j0 + b.
+ *  seed, sketch_kind, precision   as rcholqr_factor (the same for every
+ *         block of one factorisation).
+ *  Q      [in/out] m x (j0 + b), ld ldq: columns 0..j0-1 in (left as they
+ *         are), columns j0.. out.
+ *  S      [in/out] k x (j0 + b) FP64, ld lds >= k: columns 0..j0-1 in.
+ *  R      [in/out] (j0 + b) x (j0 + b) FP64 upper, ld ldr: columns 0..j0-1
+ *         in; the new columns (rows 0..j0+b-1) out.
+ *  ws     rcholqr_col_block_workspace_bytes(m, j0, b, k, kind, precision)
+ *         bytes; status word as rcholqr_factor (1: the remainder of the
+ *         block's sketch is rank deficient).
+ * Returns 0, -i for invalid argument i (1-based), or RCHOLQR_ERR_HIP. */
+size_t rcholqr_col_block_workspace_bytes(int64_t m, int64_t j0, int64_t b, int64_t k,
+                                         int sketch_kind, int precision);
+int rcholqr_col_block(const void* Xb, int64_t m, int64_t j0, int64_t b, int64_t ldx,
+                      int64_t k, uint64_t seed, int sketch_kind, int precision, void* Q,
+                      int64_t ldq, double* S, int64_t lds, double* R, int64_t ldr,
+                      void* ws, size_t ws_bytes, void* stream);
+
 /* Read the status word of a workspace used by a completed call
  * (synchronises the current device).  *info receives 0, 1, 2 or 1000 + j.
  * Returns 0 or RCHOLQR_ERR_HIP. */

@@ -11,6 +11,7 @@ Cholesky QR factorizations":
 * ``trsm_rows``         -- Algorithm 2 step 3, row-wise forward substitution
 * ``gram``/``cholesky_upper``/``triu_product`` -- Algorithm 3 steps 2-3
 * ``rcholqr``           -- Algorithm 2 (passes=1) / Algorithm 3 (passes=2)
+* ``col_rcholqr``       -- Algorithm 4 (column-oriented RCholeskyQR, Section 3.2)
 * ``reduced_rcholqr``   -- Algorithm 5 (Reduced RCholeskyQR, Section 3.3)
 * ``qrcp``/``strong_rrqr``/``rr_rcholqr`` -- Algorithm 7 (rank-revealing
                            RCholeskyQR, Section 4); its RRQR step is QR with
@@ -282,6 +283,39 @@ def rcholqr(X, k, seed, kind=GAUSSIAN, passes=2, want_s=False):
                            _ptr(Rs), _ptr(Rp))
     return dict(Q=Q, R=R, Rs=Rs, Rp=Rp if passes == 2 else None, S=S,
                 status=int(st))
+
+
+def col_rcholqr(blocks, k, seed, kind=GAUSSIAN):
+    """Algorithm 4 (column-oriented RCholeskyQR, Section 3.2) over the column
+    blocks X_(1), ..., X_(p) of X (given up front here; in an application each
+    comes from the Q of the previous ones): P_i = Theta X_i; R_{1:i-1,i} the
+    least-squares solution of S_{1:i-1} R = P_i (numpy's lstsq); [S_i, R_ii]
+    the Householder QR of P_i - S_{1:i-1} R_{1:i-1,i}; Q_i = (X_i -
+    Q_{1:i-1} R_{1:i-1,i}) R_ii^{-1} by the row-wise forward substitution.
+    Returns dict(Q, S, R)."""
+    blocks = [_f64(b) for b in blocks]
+    m = blocks[0].shape[0]
+    n = sum(b.shape[1] for b in blocks)
+    Q = np.zeros((m, n), order="F")
+    S = np.zeros((k, n), order="F")
+    R = np.zeros((n, n), order="F")
+    j0 = 0
+    for Xi in blocks:
+        b = Xi.shape[1]
+        Pi = sketch(kind, Xi, k, seed)
+        if j0:
+            Rc = np.linalg.lstsq(S[:, :j0], Pi, rcond=None)[0]
+            R[:j0, j0:j0 + b] = Rc
+            W = Pi - S[:, :j0] @ Rc
+            Y = Xi - Q[:, :j0] @ Rc
+        else:
+            W, Y = Pi, Xi
+        Rii, Si, _ = householder_qr(np.asfortranarray(W))
+        S[:, j0:j0 + b] = Si
+        R[j0:j0 + b, j0:j0 + b] = Rii
+        Q[:, j0:j0 + b] = trsm_rows(np.asfortranarray(Y), Rii)
+        j0 += b
+    return dict(Q=Q, S=S, R=R)
 
 
 def extractor(kind, k, l, m, seed):

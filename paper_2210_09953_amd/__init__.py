@@ -12,13 +12,13 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, F64, F32, MIXED,
                       LibraryMissing, RCholQRError, lib, lib_path,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
                       status, error_string, fortran, empty_fortran, PHASES,
-                      profile_enable, profile_read, backward, BatchedFactor, Problem,
+                      profile_enable, profile_read, backward, BatchedFactor, Problem, ColumnQR,
                       device_copy, reduced, rr)
 from .autograd import RCholQR2, rcholqr2
 
-__all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "F64", "F32", "MIXED",
+__all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "F64", "F32", "MIXED",
            "LibraryMissing", "RCholQRError", "lib", "lib_path",
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",
            "profile_enable", "profile_read", "backward", "RCholQR2", "rcholqr2", "device_copy",
-           "BatchedFactor", "Problem", "reduced", "rr"]
+           "BatchedFactor", "Problem", "ColumnQR", "reduced", "rr"]

@@ -79,6 +79,11 @@ def lib():
     L.rcholqr_reduced.argtypes = [vp, i64, i64, i64, i64, i64, u64, i32, i32, dp, i64, dp, i64,
                                   dp, i64, vp, sz, vp]
     L.rcholqr_reduced.restype = i32
+    L.rcholqr_col_block_workspace_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
+    L.rcholqr_col_block_workspace_bytes.restype = sz
+    L.rcholqr_col_block.argtypes = [vp, i64, i64, i64, i64, i64, u64, i32, i32, vp, i64, dp, i64,
+                                    dp, i64, vp, sz, vp]
+    L.rcholqr_col_block.restype = i32
     L.rcholqr_rr_workspace_bytes.argtypes = [i64, i64, i64, i32, i32, i32]
     L.rcholqr_rr_workspace_bytes.restype = sz
     L.rcholqr_rr.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, i32, ctypes.c_double,
@@ -246,6 +251,42 @@ def rr(X, k, seed, kind=GAUSSIAN, precision=None, tau=1e-12, passes=1, f=1.5, ws
     _check(code, "rcholqr_rr")
     r = int(rank.item())
     return Q[:, :r], R[:r, :], piv, r
+
+
+class ColumnQR:
+    """Column-oriented RCholeskyQR (Algorithm 4): append blocks of columns
+    one call at a time; Q, S and R grow in buffers sized for n columns.
+    After the blocks of j columns, Q[:, :j], S[:, :j] and R[:j, :j] hold the
+    factorisation of the columns seen."""
+
+    def __init__(self, m, n, k, seed, kind=GAUSSIAN, precision=F64, device="cuda"):
+        self.m, self.n, self.k, self.seed, self.kind, self.precision = m, n, k, seed, kind, precision
+        dt = _dtype_for(precision)
+        self.Q = empty_fortran(m, n, dt, device)
+        self.S = empty_fortran(k, n, torch.float64, device)
+        self.R = torch.zeros((n, n), dtype=torch.float64, device=device).t().contiguous().t()
+        self.j = 0
+        self.ws = None
+
+    def append(self, Xb):
+        """Factor the next block X_b (m x b) against the columns so far."""
+        Xb = fortran(Xb)
+        b = Xb.shape[1]
+        if Xb.shape[0] != self.m or self.j + b > self.n:
+            raise ValueError("block does not fit")
+        need = int(lib().rcholqr_col_block_workspace_bytes(self.m, self.j, b, self.k, self.kind,
+                                                           self.precision))
+        if need == 0:
+            raise RCholQRError(-1, "invalid problem size")
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=Xb.device)
+        code = lib().rcholqr_col_block(_ptr(Xb), self.m, self.j, b, _ld(Xb), self.k,
+                                       int(self.seed), self.kind, self.precision, _ptr(self.Q),
+                                       _ld(self.Q), _ptr(self.S), _ld(self.S), _ptr(self.R),
+                                       _ld(self.R), _ptr(self.ws), self.ws.numel(), _stream())
+        _check(code, "rcholqr_col_block")
+        self.j += b
+        return self.Q[:, :self.j], self.R[:self.j, :self.j]
 
 
 def status(ws):

@@ -654,6 +654,73 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   return 0;
 }
 
+size_t rcholqr_col_block_workspace_bytes(int64_t m, int64_t j0, int64_t b, int64_t k,
+                                         int sketch_kind, int precision) {
+  const int64_t nt = j0 + b;
+  if (j0 < 0 || b < 1 || !valid_dims(m, nt, k) || sketch_kind < 0 || sketch_kind > 3 ||
+      precision < 0 || precision > 2)
+    return 0;
+  const Layout Lb = make_layout(m, b, k, sketch_kind, 1, precision);
+  const Layout Ln = make_layout(m, nt, k, sketch_kind, 1, precision);
+  return align256(Lb.total) + align256(static_cast<size_t>(nt) * nt * sizeof(double)) +
+         (Ln.Tinv - Ln.pan);
+}
+
+int rcholqr_col_block(const void* Xb, int64_t m, int64_t j0, int64_t b, int64_t ldx, int64_t k,
+                      uint64_t seed, int sketch_kind, int precision, void* Q, int64_t ldq,
+                      double* S, int64_t lds, double* R, int64_t ldr, void* ws,
+                      size_t ws_bytes, void* stream) {
+  const int64_t nt = j0 + b;
+  if (!Xb) return -1;
+  if (j0 < 0) return -3;
+  if (b < 1 || nt > kMaxN) return -4;
+  if (m < nt) return -2;
+  if (ldx < m) return -5;
+  if (k < nt || k > kMaxK) return -6;
+  if (sketch_kind < 0 || sketch_kind > 3) return -8;
+  if (precision < 0 || precision > 2) return -9;
+  if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -9;
+  if (!Q) return -10;
+  if (ldq < m) return -11;
+  if (!S) return -12;
+  if (lds < k) return -13;
+  if (!R) return -14;
+  if (ldr < nt) return -15;
+  if (!ws) return -16;
+  if (ws_bytes < rcholqr_col_block_workspace_bytes(m, j0, b, k, sketch_kind, precision))
+    return -17;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f32 = precision != kPrecF64;
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  const int bi = static_cast<int>(b), ji = static_cast<int>(j0), ni = static_cast<int>(nt);
+  const int ki = static_cast<int>(k);
+  const Layout Lb = make_layout(m, b, k, sketch_kind, 1, precision);
+  double* P = at<double>(ws, Lb.P);
+  double* T = at<double>(ws, align256(Lb.total));
+  void* pan = at<void>(ws, align256(Lb.total) + align256(static_cast<size_t>(nt) * nt * sizeof(double)));
+  int* status = at<int>(ws, Lb.status);
+  // step 2: P_b = Theta X_b (the same Theta as for the whole X)
+  if (precision == kPrecMixed)
+    RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(Xb), m, bi, ldx, ki, seed, Lb.sp,
+                                at<double>(ws, Lb.part), P, k, st, sketch_kind));
+  else
+    RCQ_TRY(launch_sketch(Xb, f32, m, bi, ldx, ki, sketch_kind, seed, Lb.sp,
+                          at<double>(ws, Lb.part), at<uint32_t>(ws, Lb.keys), P, k, st));
+  // steps 3-4: coefficients on the previous S, then the QR of the remainder
+  RCQ_TRY(launch_col_project(S, lds, ji, P, ki, bi, R, ldr, st));
+  RCQ_TRY(launch_householder(P, ki, bi, at<double>(ws, Lb.v0), at<double>(ws, Lb.beta),
+                             at<double>(ws, Lb.T), S + j0 * lds, lds, at<double>(ws, Lb.Rs),
+                             R + j0 + j0 * ldr, ldr, status, st));
+  // step 5: X_b into its columns of Q, then [Q_1:j0, X_b] T^{-1} in place
+  char* qb = static_cast<char*>(Q) + static_cast<size_t>(j0) * ldq * esz;
+  if (static_cast<const void*>(qb) != Xb)
+    RCQ_TRY(hipMemcpy2DAsync(qb, ldq * esz, Xb, ldx * esz, m * esz, b, hipMemcpyDeviceToDevice, st));
+  RCQ_TRY(launch_col_make_t(R, ldr, ji, ni, T, st));
+  RCQ_TRY(launch_make_panels(T, nt, ni, f32, pan, st));
+  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  return 0;
+}
+
 int rcholqr_status(const void* ws, int* info) {
   if (!ws || !info) return -1;
   if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;

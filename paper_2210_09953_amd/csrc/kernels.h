@@ -72,6 +72,14 @@ hipError_t launch_left_upper(const double* U, int64_t ldu, int r, double* R, int
 hipError_t launch_gather_cols(const void* X, bool f32, int64_t m, int n, int64_t ldx,
                               const int* piv, void* Q, int64_t ldq, hipStream_t st);
 
+// col.hip (column-oriented variant): R(0:j0, j0:j0+b) = S(:, 0:j0)^T P and
+// P <- P - S(:, 0:j0) R(0:j0, j0:j0+b) (P k x b, ld k); T (nt x nt) for the
+// tall step.
+hipError_t launch_col_project(const double* S, int64_t lds, int j0, double* P, int k, int b,
+                              double* R, int64_t ldr, hipStream_t st);
+hipError_t launch_col_make_t(const double* R, int64_t ldr, int j0, int nt, double* T,
+                             hipStream_t st);
+
 // small.hip
 hipError_t launch_householder(double* A, int k, int n, double* V, double* beta, double* T,
                               double* S, int64_t lds, double* Rs, double* R, int64_t ldr,

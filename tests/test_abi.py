@@ -24,7 +24,8 @@ def test_header_declares_entry_points():
               "rcholqr_factor_batched", "rcholqr_batched_status",
               "rcholqr_backward_workspace_bytes", "rcholqr_backward",
               "rcholqr_reduced_workspace_bytes", "rcholqr_reduced",
-              "rcholqr_rr_workspace_bytes", "rcholqr_rr"]:
+              "rcholqr_rr_workspace_bytes", "rcholqr_rr",
+              "rcholqr_col_block_workspace_bytes", "rcholqr_col_block"]:
         assert n in names
 
 
@@ -156,3 +157,37 @@ def test_rr_argument_errors_without_gpu():
     assert call(wsb=16) == -19
     need2 = L.rcholqr_rr_workspace_bytes(1000, 10, 30, rq.GAUSSIAN, rq.F64, 2)
     assert call(passes=2, wsb=need2 - 1) == -19
+
+
+def test_col_block_argument_errors_without_gpu():
+    """Column-oriented RCholeskyQR: sizes and pointers are checked first."""
+    import paper_2210_09953_amd as rq
+    L = rq.lib()
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert L.rcholqr_col_block_workspace_bytes(1000, 10, 6, 48, rq.GAUSSIAN, rq.F64) > 0
+    assert L.rcholqr_col_block_workspace_bytes(1000, 10, 6, 12, rq.GAUSSIAN, rq.F64) == 0
+    assert L.rcholqr_col_block_workspace_bytes(1000, 250, 7, 1024, rq.GAUSSIAN, rq.F64) == 0
+
+    def call(X=256, m=1000, j0=10, b=6, ldx=1000, k=48, kind=rq.GAUSSIAN, prec=rq.F64, Q=256,
+             ldq=1000, S=256, lds=48, R=256, ldr=16, ws=256, wsb=1 << 30):
+        return L.rcholqr_col_block(vp(X), m, j0, b, ldx, k, 1, kind, prec, vp(Q), ldq,
+                                   ctypes.cast(S, dp), lds, ctypes.cast(R, dp), ldr, vp(ws), wsb,
+                                   None)
+    assert call(X=0) == -1
+    assert call(m=12) == -2
+    assert call(j0=-1) == -3
+    assert call(b=0) == -4
+    assert call(j0=250, b=7) == -4
+    assert call(ldx=10) == -5
+    assert call(k=12) == -6
+    assert call(kind=9) == -8
+    assert call(prec=rq.MIXED) == -9
+    assert call(Q=0) == -10
+    assert call(ldq=10) == -11
+    assert call(S=0) == -12
+    assert call(lds=10) == -13
+    assert call(R=0) == -14
+    assert call(ldr=15) == -15
+    assert call(ws=0) == -16
+    assert call(wsb=16) == -17

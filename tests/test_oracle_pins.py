@@ -710,3 +710,25 @@ def test_srht_is_an_embedding_and_rcholqr_is_stable(orc):
     Rl = np.sign(np.diag(Rl))[:, None] * Rl
     for j in range(32):
         assert np.linalg.norm(R[:, j] - Rl[:, j]) <= 1e-6 * np.linalg.norm(X[:, j])
+
+
+# ----------------------------------------------------------------------------- Algorithm 4
+@pytest.mark.parametrize("widths,kind", [((16, 16, 16, 16), G), ((20, 7, 33), RD),
+                                         ((1,) * 24, G), ((40,), CS)])
+def test_col_rcholqr_equals_algorithm_2(orc, widths, kind):
+    """Section 3.2: block by block, Algorithm 4 computes what Algorithm 2
+    computes on the whole X (the C oracle's one-pass RCholeskyQR), up to
+    rounding: same Q, S and R for a well-conditioned X; p = n is the
+    column-by-column case."""
+    n = sum(widths)
+    m, k = 3000, 3 * n
+    X = synth.make_x(m, n, 1e-3, seed=13)
+    cuts = np.cumsum((0,) + widths)
+    out = orc.col_rcholqr([X[:, a:b] for a, b in zip(cuts[:-1], cuts[1:])], k, 4, kind)
+    ref = orc.rcholqr(X, k, 4, kind, passes=1, want_s=True)
+    assert np.linalg.norm(out["R"] - ref["R"]) <= 1e-12 * np.linalg.norm(ref["R"])
+    assert np.linalg.norm(out["Q"] - ref["Q"]) <= 1e-11 * np.linalg.norm(ref["Q"])
+    assert np.linalg.norm(out["S"] - ref["S"]) <= 1e-12 * np.linalg.norm(ref["S"])
+    # one projection per block: S keeps orthogonality to ~u kappa (kappa = 1e3)
+    assert np.linalg.norm(out["S"].T @ out["S"] - np.eye(n), 2) <= 1e-11
+    assert np.allclose(np.triu(out["R"]), out["R"], rtol=0, atol=0)
