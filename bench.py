@@ -274,6 +274,36 @@ def reduced_leg(torch, rq, X, k, l, kind, prec_code, steps, warmup, seed=1):
     return ms, orth_s, st
 
 
+def col_leg(torch, rq, X, k, kind, prec_code, steps, warmup, nblocks=4, seed=1):
+    """Column-oriented RCholeskyQR (Algorithm 4) of the same X in nblocks
+    equal column blocks, one C-ABI call per block (X_b read from X).
+    Returns ms per whole factorisation and cond(Q)."""
+    m, n = X.shape
+    w = n // nblocks
+    cq = rq.ColumnQR(m, n, k, seed, kind, prec_code)
+    # one workspace for the largest call (the last block)
+    cq.ws = torch.empty(int(rq.lib().rcholqr_col_block_workspace_bytes(m, n - w, w, k, kind,
+                                                                       prec_code)),
+                        dtype=torch.uint8, device="cuda")
+
+    def run():
+        cq.j = 0
+        for b in range(nblocks):
+            cq.append(X[:, b * w:(b + 1) * w])
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s = torch.linalg.svdvals(cq.Q.double().T @ cq.Q.double())
+    return ms, float(torch.sqrt(s[0] / s[-1]))
+
+
 def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, passes=1, seed=1):
     """Rank-revealing RCholeskyQR (Algorithm 7) on the same X.  Returns ms per
     call (the rank read after the timed region), the rank and cond(Q)."""
@@ -345,6 +375,8 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-reduced-leg", action="store_true",
                     help="skip the Reduced RCholeskyQR figure")
+    ap.add_argument("--no-col-leg", action="store_true",
+                    help="skip the column-oriented (four-block) factorisation of the same X")
     ap.add_argument("--no-srht-leg", action="store_true",
                     help="skip the SRHT-sketch factorisation of the same X")
     ap.add_argument("--no-rr-leg", action="store_true",
@@ -356,7 +388,8 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs into profiles/traffic_<workload>.md")
     ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
-                    "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg --copy-probe")
+                    "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg "
+                    "--no-reduced-leg --no-srht-leg --no-col-leg --copy-probe")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
@@ -435,6 +468,15 @@ def main():
             f"resid={res_s2:.2e} sketch={ph_s.get('sketch', 0.0):.3f} ms")
         del Q_s, R_s
 
+    # Column-oriented RCholeskyQR of the same X in four blocks.
+    col = None
+    if not args.no_col_leg and n % 4 == 0:
+        ms_c, cond_c = col_leg(torch, rq, X, k, kind, prec_code, args.steps, args.warmup)
+        col = {"value": round(m * n * xbytes / (ms_c * 1e-3) / 1e9, 2), "unit": "GB/s",
+               "ms_per_step": round(ms_c, 4), "blocks": 4, "cond_Q": cond_c}
+        log(f"[bench] column-oriented (4 blocks): {ms_c:.3f} ms/step {col['value']} GB/s "
+            f"cond(Q) {cond_c:.3f}")
+
     # Rank-revealing RCholeskyQR on the same X.
     rrf = None
     if not args.no_rr_leg:
@@ -499,6 +541,7 @@ def main():
         "fp64": fp64,
         "reduced": red,
         "srht": srht,
+        "column_oriented": col,
         "rank_revealing": rrf,
         "cpu_baseline": cpu,
     }
