@@ -170,3 +170,27 @@ def test_rr_strong_swaps_f64(rq, orc, m, n, seed, kind):
     assert r0 == ref0["rank"]
     assert np.array_equal(piv0[:r0], ref0["piv"][:r0])
     assert not np.array_equal(piv0[:r], piv[:r])
+
+
+def test_rr_degenerate_inputs(rq, orc):
+    """A zero X has rank 0 (D = 0, the normalised sketch stays zero); a zero
+    column is never kept ahead of a nonzero one; n = 1 keeps its column."""
+    import torch
+    m, n, k = 3000, 8, 24
+    Q, R, piv, r = rq.rr(_gpu(np.zeros((m, n))), k, 1, 0, tau=1e-12)
+    assert r == 0 == orc.rr_rcholqr(np.zeros((m, n)), k, 1, 0, tau=1e-12)["rank"]
+    assert Q.shape == (m, 0) and R.shape == (0, n)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((m, n))
+    X[:, 2] = 0.0
+    Q, R, piv, r = rq.rr(_gpu(X), k, 1, 0, tau=1e-12)
+    ref = orc.rr_rcholqr(X, k, 1, 0, tau=1e-12)
+    assert r == ref["rank"] == n - 1
+    piv = _np(piv)
+    assert 2 not in piv[:r] and np.array_equal(piv[:r], ref["piv"][:r])
+    # n = 1: R = ||Theta x|| (the sketched norm), Q = x / R
+    x1 = rng.standard_normal((m, 1))
+    Q, R, piv, r = rq.rr(_gpu(x1), 3, 1, 0, tau=1e-12)
+    ref = orc.rr_rcholqr(x1, 3, 1, 0, tau=1e-12)
+    assert r == 1 and abs(_np(R)[0, 0] - ref["R"][0, 0]) <= 1e-12 * ref["R"][0, 0]
+    assert np.linalg.norm(_np(Q) - x1 / ref["R"][0, 0]) <= 1e-12 * np.linalg.norm(_np(Q))

@@ -113,3 +113,14 @@ def test_srht_rank_revealing(rq, orc):
     assert r == ref["rank"] == rho
     assert np.array_equal(_np(piv)[:r], ref["piv"][:r])
     assert np.linalg.norm(_np(Q) - ref["Q"]) <= 1e-9 * np.linalg.norm(ref["Q"])
+
+
+def test_srht_mixed_sketch_at_the_largest_k(rq, orc):
+    """k = 1024 (the library's largest) with n = 256 runs the main int8 tiles
+    with the most Theta row tiles."""
+    m, n, k = 6000, 256, 1024
+    X32 = synth.make_x(m, n, 1e-3, seed=5, dtype=np.float32)
+    P = _np(rq.sketch(_gpu(X32), k, 8, kind=rq.SRHT, precision=rq.MIXED))
+    X = X32.astype(np.float64)
+    err = np.linalg.norm(P - orc.sketch(orc.SRHT, X, k, 8), axis=0)
+    assert np.all(err <= 2.0 * math.sqrt(m) * 2.0 ** -21 * np.abs(X).max(axis=0))
