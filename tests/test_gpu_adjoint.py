@@ -30,7 +30,8 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("m,n,kind", [(3000, 24, 0), (2001, 16, 1), (777, 50, 2), (1000, 1, 0)])
+@pytest.mark.parametrize("m,n,kind", [(3000, 24, 0), (2001, 16, 1), (777, 50, 2), (1000, 1, 0),
+                                      (2500, 20, 3)])
 def test_backward_matches_oracle_f64(rq, orc, m, n, kind):
     X = synth.make_x(m, n, 1e-3, seed=11)
     dQ, dR = synth.make_cotangents(m, n, seed=12)

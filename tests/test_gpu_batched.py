@@ -36,7 +36,8 @@ def _instances(count, seed, m_hi, dtype):
 
 
 @pytest.mark.parametrize("kind,precision,dtype", [(0, 0, np.float64), (1, 2, np.float32),
-                                                  (2, 1, np.float32)])
+                                                  (2, 1, np.float32), (3, 2, np.float32),
+                                                  (3, 0, np.float64)])
 def test_batched_equals_single_calls(rq, kind, precision, dtype):
     import torch
     shapes, Xs = _instances(11, 3, 30000, dtype)
