@@ -494,6 +494,21 @@ def main():
                            "orth": orth2}
         log(f"[bench] rank-revealing, 2 passes: {ms2:.3f} ms/step {rrf['two_pass']['value']} "
             f"GB/s rank {r2} ||Q^T Q - I|| = {orth2:.2e}")
+        # the same shape at rank 64 (X's first 64 columns times a seeded
+        # Gaussian 64 x n): the tall steps touch only the kept columns
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        G = torch.randn(64, n, dtype=torch.float64, device="cuda", generator=g)
+        Xl = rq.fortran((X[:, :64].double() @ G).to(X.dtype))
+        del G
+        ms_l, r_l, cond_l, _ = rr_leg(torch, rq, Xl, k, kind, prec_code, args.steps,
+                                      args.warmup, 1e-5)
+        del Xl
+        rrf["rank_64"] = {"value": round(m * n * xbytes / (ms_l * 1e-3) / 1e9, 2),
+                          "unit": "GB/s", "ms_per_step": round(ms_l, 4), "tau": 1e-5,
+                          "rank": r_l, "cond_Q": cond_l}
+        log(f"[bench] rank-revealing, X of rank 64: {ms_l:.3f} ms/step "
+            f"{rrf['rank_64']['value']} GB/s rank {r_l} cond(Q) {cond_l:.3f}")
 
     fp64 = None
     if not args.no_fp64_leg and prec != "f64":

@@ -159,17 +159,17 @@ int rcholqr_reduced(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
  * Q <- Q R'^{-1}, R <- R' R (Algorithm 3 steps 2-4).
  *
  *  X, m, n, ldx, k, seed, sketch_kind, precision  as rcholqr_factor.
- *  passes 1 (Algorithm 7) or 2 (with the Cholesky QR pass).  passes = 2
- *         reads r back to the host: the call then waits for the stream.
+ *  passes 1 (Algorithm 7) or 2 (with the Cholesky QR pass).
  *  tau    truncation tolerance (>= 0).
  *  f      strong RRQR parameter: 0 (column pivoting alone) or > 1 (the
  *         paper's experiments use 1.5).
  *  Q      [out] m x n buffer (ld ldq >= m, FP64 or FP32 as X): columns 0..r-1
- *         hold Q; columns r.. hold the dropped columns of X Pi (unscaled).
+ *         hold Q; columns r.. are not written.  The call reads r back to the
+ *         host before the tall steps (they touch only the r kept columns), so
+ *         it waits for the stream once.
  *  R      [out] n x n FP64 (ld ldr): rows 0..r-1 hold R, rows r.. are zero.
  *  piv    [out] n int32 on the device: column j of X Pi is column piv[j] of X.
- *  rank   [out] one int32 on the device: r (with passes = 1 read it after
- *         the stream has finished; that call never synchronises).
+ *  rank   [out] one int32 on the device: r.
  *  ws     rcholqr_rr_workspace_bytes(m, n, k, kind, precision, passes)
  *         bytes; status word 0, 2 for non-finite X, or 1000 + j when the
  *         second pass's Cholesky breaks down at column j.

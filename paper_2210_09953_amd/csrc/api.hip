@@ -625,17 +625,20 @@ int rcholqr_rr(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
                              at<double>(ws, L.T), nullptr, k, Rsw, nullptr, ldr, status, st));
   RCQ_TRY(launch_rr_steps(X, f32, m, ni, ldx, P, ki, Rsw, tau, f, extra, R, ldr, piv, rank,
                           status, &Rsolve, st, 1));
-  RCQ_TRY(launch_gather_cols(X, f32, m, ni, ldx, piv, Q, ldq, st));
-  void* pan = at<void>(ws, L.pan);
-  RCQ_TRY(launch_make_panels(Rsolve, n, ni, f32, pan, st));
-  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
-  if (passes == 1) return 0;
-  // RRRCholeskyQR2: one Cholesky QR pass (Algorithm 3 steps 2-4) over the r
-  // kept columns of Q; r is read back first (the only synchronisation).
+  // r is read back (the call's one synchronisation) so that step 4 touches
+  // only the r kept columns: X Pi_{:,1:r} gathered into Q, solved in place
+  // with the leading r x r block of the solve's factor (about m r^2 work).
   int r = 0;
   RCQ_TRY(hipMemcpyAsync(&r, rank, sizeof(int), hipMemcpyDeviceToHost, st));
   RCQ_TRY(hipStreamSynchronize(st));
   if (r < 1 || r > ni) return 0;
+  RCQ_TRY(launch_gather_cols(X, f32, m, r, ldx, piv, Q, ldq, st));
+  void* pan = at<void>(ws, L.pan);
+  RCQ_TRY(launch_make_panels(Rsolve, n, r, f32, pan, st));
+  RCQ_TRY(launch_trsm(Q, f32, m, r, ldq, pan, Q, ldq, st));
+  if (passes == 1) return 0;
+  // RRRCholeskyQR2: one Cholesky QR pass (Algorithm 3 steps 2-4) over the r
+  // kept columns of Q.
   const GramPlan gp = make_layout(m, r, r, kGaussian, 2, precision).gp;
   double* G = at<double>(ws, L.G);
   RCQ_TRY(launch_gram(Q, f32, m, r, ldq, gp, at<double>(ws, gram_off), st));
