@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void colnorm_scale_kernel(const double* __rest
 // pivoted order, positive diagonal: rows flipped with alpha), the same
 // factor row-major in Rw, piv.
 constexpr int kQcpThreads = 4 * kMaxN;
+constexpr int kQcRows = 16;  // rows per thread kept in registers within a step
 
 __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restrict__ Rp, int n,
                                                            double* __restrict__ W,
@@ -156,21 +157,24 @@ __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restr
     const bool upd = col && !placed && !is_p;
     placed = placed || is_p;
     const int is = j + ((q - j) & 3);  // this thread's first row >= j
+    // the first kQcRows of this thread's rows stay in registers from the
+    // products to the update (one read of W per row and step for them)
+    double wc[kQcRows];
     {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (upd) {
-        int i = is;
-        if (i == j) {
-          a0 = v0 * W[static_cast<int64_t>(j) * n + c];
-          i += 4;
+#pragma unroll
+        for (int u = 0; u < kQcRows; ++u) {
+          const int i = is + 4 * u;
+          const double w = (i < n) ? W[static_cast<int64_t>(i) * n + c] : 0.0;
+          wc[u] = w;
+          const double t = ((i < n) ? ((i == j) ? v0 : v[i]) : 0.0) * w;
+          if ((u & 3) == 0) a0 += t;
+          else if ((u & 3) == 1) a1 += t;
+          else if ((u & 3) == 2) a2 += t;
+          else a3 += t;
         }
-        for (; i + 12 < n; i += 16) {
-          a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
-          a1 += v[i + 4] * W[static_cast<int64_t>(i + 4) * n + c];
-          a2 += v[i + 8] * W[static_cast<int64_t>(i + 8) * n + c];
-          a3 += v[i + 12] * W[static_cast<int64_t>(i + 12) * n + c];
-        }
-        for (; i < n; i += 4) a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
+        for (int i = is + 4 * kQcRows; i < n; i += 4) a0 += v[i] * W[static_cast<int64_t>(i) * n + c];
       }
       dotp[q][c] = (a0 + a1) + (a2 + a3);
     }
@@ -179,20 +183,21 @@ __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restr
       double s0 = 0.0, s1 = 0.0;
       if (upd) {
         const double f = beta * (((dotp[0][c] + dotp[1][c]) + dotp[2][c]) + dotp[3][c]);
-        int i = is;
-        if (i == j) {  // row j is final after this step and leaves the norm
-          W[static_cast<int64_t>(j) * n + c] -= f * v0;
-          i += 4;
+#pragma unroll
+        for (int u = 0; u < kQcRows; ++u) {
+          const int i = is + 4 * u;
+          if (i < n) {
+            const double x = wc[u] - f * ((i == j) ? v0 : v[i]);
+            W[static_cast<int64_t>(i) * n + c] = x;
+            // row j is final after this step and leaves the norm
+            const double x2 = (i > j) ? x * x : 0.0;
+            if (u & 1)
+              s1 += x2;
+            else
+              s0 += x2;
+          }
         }
-        for (; i + 4 < n; i += 8) {
-          const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
-          const double y = W[static_cast<int64_t>(i + 4) * n + c] - f * v[i + 4];
-          W[static_cast<int64_t>(i) * n + c] = x;
-          W[static_cast<int64_t>(i + 4) * n + c] = y;
-          s0 += x * x;
-          s1 += y * y;
-        }
-        for (; i < n; i += 4) {
+        for (int i = is + 4 * kQcRows; i < n; i += 4) {
           const double x = W[static_cast<int64_t>(i) * n + c] - f * v[i];
           W[static_cast<int64_t>(i) * n + c] = x;
           s0 += x * x;
