@@ -221,7 +221,8 @@ __global__ __launch_bounds__(kQcpThreads) void qrcp_kernel(const double* __restr
 }
 
 // Step 3, the rank: least r with ||Rt_{r:,r:}||_F <= tau ||Rt||_2, the
-// 2-norm by 64 power-iteration steps on Rt^T Rt (kept in *sigma_out for the
+// 2-norm by at most 64 power-iteration steps on Rt^T Rt, fewer once the
+// estimate has settled (kept in *sigma_out for the
 // strong RRQR step).  The status word keeps only the non-finite flag (rank
 // deficiency is expected).
 // Rt is read column-major for the products Rt x and row-major (Rw) for
@@ -276,9 +277,13 @@ __global__ __launch_bounds__(kFinThreads) void rr_rank_kernel(
   __syncthreads();
   double sigma = 0.0;
   for (int it = 0; it < 64; ++it) {
-    // y = Rt x, x = Rt^T y / ||Rt^T y||
+    // y = Rt x, x = Rt^T y / ||Rt^T y||; stop once ||Rt x|| has settled to
+    // 1e-12 relative (every thread holds the same block sums, so all stop
+    // together)
     const double yy = mul_rt();
+    const double prev = sigma;
     sigma = sqrt(yy);  // ||Rt x|| with ||x|| = 1 after the first step
+    if (it >= 8 && fabs(sigma - prev) <= 1e-12 * sigma) break;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (live) {
       // quarter q of column t of Rt times y: rows c0 .. min(c1, t + 1)
