@@ -320,8 +320,28 @@ int orc_householder_qr(int64_t k, int64_t n, const double* P, int64_t ldp,
   double* A = (double*)malloc((size_t)(k * n) * sizeof(double));
   double* V = (double*)calloc((size_t)(k * n), sizeof(double));
   double* beta = (double*)calloc((size_t)n, sizeof(double));
-  for (int64_t c = 0; c < n; ++c)
-    for (int64_t i = 0; i < k; ++i) A[i + c * k] = P[i + c * ldp];
+  /* Each column enters scaled by 2^-e_c (e_c: the exponent of its largest
+   * magnitude; 0 for a zero or non-finite column), as LAPACK's reflector
+   * generation guards its norm, so that the sums of squares below cannot
+   * underflow or overflow.  Householder QR commutes with a power-of-two
+   * column scaling (QR(P D) = Q (R D)) without changing any rounding in the
+   * normal range; R's columns are scaled back at the end. */
+  int* cexp = (int*)calloc((size_t)n, sizeof(int));
+  for (int64_t c = 0; c < n; ++c) {
+    double mx = 0.0;
+    int finite = 1;
+    for (int64_t i = 0; i < k; ++i) {
+      double a = fabs(P[i + c * ldp]);
+      if (!isfinite(a)) finite = 0;
+      else if (a > mx) mx = a;
+    }
+    if (finite && mx > 0.0) {
+      int ex = 0;
+      (void)frexp(mx, &ex);
+      cexp[c] = ex - 1;
+    }
+    for (int64_t i = 0; i < k; ++i) A[i + c * k] = ldexp(P[i + c * ldp], -cexp[c]);
+  }
   for (int64_t j = 0; j < n; ++j) {
     double nrm2 = 0.0;
     for (int64_t i = j; i < k; ++i) nrm2 += A[i + j * k] * A[i + j * k];
@@ -349,7 +369,7 @@ int orc_householder_qr(int64_t k, int64_t n, const double* P, int64_t ldp,
   }
   for (int64_t c = 0; c < n; ++c)
     for (int64_t r = 0; r < n; ++r)
-      R[r + c * ldr] = (r <= c) ? d[r] * A[r + c * k] : 0.0;
+      R[r + c * ldr] = (r <= c) ? ldexp(d[r] * A[r + c * k], cexp[c]) : 0.0;
   for (int64_t j = 0; j < n; ++j) {
     double rjj = R[j + j * ldr];
     if (!(rjj > 0.0) || !isfinite(rjj)) status = 1;
@@ -369,6 +389,7 @@ int orc_householder_qr(int64_t k, int64_t n, const double* P, int64_t ldp,
     for (int64_t c = 0; c < n; ++c)
       for (int64_t i = 0; i < k; ++i) S[i + c * lds] *= d[c];
   }
+  free(cexp);
   free(d);
   free(beta);
   free(V);

@@ -91,7 +91,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   L.P = off; off += align256(static_cast<size_t>(k) * n * sizeof(double));
   L.v0 = off; off += align256(static_cast<size_t>(n) * sizeof(double));
   L.beta = off; off += align256(static_cast<size_t>(n) * sizeof(double));
-  L.T = off; off += align256(static_cast<size_t>(ceil_div(n, kHhPanel)) * kHhPanel * kHhPanel * sizeof(double));
+  L.T = off; off += align256(hh_t_bytes(static_cast<int>(n)));
   L.Rs = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   (void)esz;
   {

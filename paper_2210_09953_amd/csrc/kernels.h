@@ -81,6 +81,12 @@ hipError_t launch_col_make_t(const double* R, int64_t ldr, int j0, int nt, doubl
                              hipStream_t st);
 
 // small.hip
+// Bytes of the T argument of launch_householder: the panels' 16 x 16 T
+// blocks and the n column exponents of its column scaling.
+inline size_t hh_t_bytes(int n) {
+  return static_cast<size_t>((n + kHhPanel - 1) / kHhPanel) * kHhPanel * kHhPanel * sizeof(double) +
+         static_cast<size_t>(n) * sizeof(int);
+}
 hipError_t launch_householder(double* A, int k, int n, double* V, double* beta, double* T,
                               double* S, int64_t lds, double* Rs, double* R, int64_t ldr,
                               int* status, hipStream_t st);

@@ -256,8 +256,45 @@ __global__ void set_identity_kernel(double* S, int64_t lds, int k, int n) {
 // cover R, the rest cover S.
 __global__ void reset_status_kernel(int* status) { *status = 0; }
 
+// Column scaling before the factorisation: column c of A (k x n, ld k) is
+// multiplied by 2^-e_c, e_c the exponent of its largest magnitude (0 for a
+// zero or non-finite column), so that the sums of squares inside the
+// reflectors neither underflow nor overflow.  Power-of-two scaling changes
+// no rounding in the normal range and Householder QR commutes with it
+// (QR(A D) = Q (R D)), so R is the same bits; hh_finalize_kernel multiplies
+// column c of R back by 2^e_c.  One workgroup per column.
+__global__ __launch_bounds__(256) void hh_colscale_kernel(double* __restrict__ A, int k,
+                                                          int* __restrict__ cexp) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double* col = A + static_cast<int64_t>(c) * k;
+  double mx = 0.0;
+  bool bad = false;
+  for (int i = threadIdx.x; i < k; i += 256) {
+    const double a = fabs(col[i]);
+    bad |= !isfinite(a);
+    mx = fmax(mx, a);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  const bool anybad = __syncthreads_or(bad);
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  int e = 0;
+  if (!anybad && mx > 0.0) {
+    int ex = 0;
+    (void)frexp(mx, &ex);
+    e = ex - 1;  // mx 2^-e in [1, 2)
+  }
+  if (threadIdx.x == 0) cexp[c] = e;
+  if (e != 0)
+    for (int i = threadIdx.x; i < k; i += 256) col[i] = ldexp(col[i], -e);
+}
+
 __global__ __launch_bounds__(256) void hh_finalize_kernel(const double* __restrict__ A, int k,
-                                                          int n, double* __restrict__ Rs,
+                                                          int n, const int* __restrict__ cexp,
+                                                          double* __restrict__ Rs,
                                                           double* __restrict__ R, int64_t ldr,
                                                           double* __restrict__ S, int64_t lds,
                                                           int nb_r, int* __restrict__ status) {
@@ -272,7 +309,7 @@ __global__ __launch_bounds__(256) void hh_finalize_kernel(const double* __restri
       double v = 0.0;
       if (r <= c) {
         const double d = (A[r + static_cast<int64_t>(r) * k] < 0.0) ? -1.0 : 1.0;
-        v = d * A[r + static_cast<int64_t>(c) * k];
+        v = ldexp(d * A[r + static_cast<int64_t>(c) * k], cexp[c]);
         if (!isfinite(v)) code = 2;
         else if (r == c && !(v > 0.0)) code = 1;
       }
@@ -320,6 +357,10 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
   reset_status_kernel<<<1, 1, 0, st>>>(status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int npan = static_cast<int>(ceil_div(n, kHhPanel));
+  // the column exponents live after the panels' T blocks (hh_t_bytes)
+  int* cexp = reinterpret_cast<int*>(T + static_cast<int64_t>(npan) * kHhPanel * kHhPanel);
+  hh_colscale_kernel<<<n, 256, 0, st>>>(A, k, cexp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // Rows per lane of the one-wave-per-column kernels, from the panel height.
 #define RCQ_HH_RPL(L, STMT)                            \
   do {                                                 \
@@ -366,7 +407,8 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
 #undef RCQ_HH_RPL
   const int nb_r = static_cast<int>(ceil_div(n * n, 256));
   const int nb_s = S ? static_cast<int>(ceil_div(static_cast<int64_t>(k) * n, 256)) : 0;
-  hh_finalize_kernel<<<nb_r + nb_s, 256, 0, st>>>(A, k, n, Rs, R, ldr, S, lds, nb_r, status);
+  hh_finalize_kernel<<<nb_r + nb_s, 256, 0, st>>>(A, k, n, cexp, Rs, R, ldr, S, lds, nb_r,
+                                                  status);
   return hipGetLastError();
 }
 

@@ -238,6 +238,26 @@ def test_householder_matches_lapack(orc, k, n):
     assert np.linalg.norm(P - S @ R) <= 10 * k * n * U64 * np.linalg.norm(P)
 
 
+def test_householder_extreme_column_scales(orc):
+    """Columns of magnitude 1e-200 and 1e+200 (sums of squares that underflow
+    or overflow in FP64): R matches LAPACK's (whose reflectors guard their
+    norms) column by column, and equals the R of the rescaled matrix exactly
+    (a power-of-two column scaling commutes with Householder QR)."""
+    rng = np.random.default_rng(31)
+    P = np.asfortranarray(rng.standard_normal((60, 12)))
+    e = np.array([0, -664, 0, 664, -10, 0, 300, -700, 0, 0, 2, -1])   # 2^-664 ~ 1e-200
+    Ps = np.asfortranarray(P * np.ldexp(1.0, e)[None, :])
+    R, S, st = orc.householder_qr(Ps)
+    assert st == 0
+    R0, S0, st0 = orc.householder_qr(P)
+    assert st0 == 0
+    assert np.array_equal(R, R0 * np.ldexp(1.0, e)[None, :])
+    assert np.array_equal(S, S0)
+    _, Rr = _lapack_qr_posdiag(Ps)
+    for c in range(12):
+        assert np.linalg.norm(R[:, c] - Rr[:, c]) <= 1e-13 * np.linalg.norm(Rr[:, c])
+
+
 def test_householder_zero_column_flags_rank(orc):
     P = np.asfortranarray(np.random.default_rng(9).standard_normal((20, 4)))
     P[:, 2] = 0.0
