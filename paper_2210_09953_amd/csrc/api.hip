@@ -97,9 +97,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   {
     const int64_t pb = panel_elems(static_cast<int>(n)) * static_cast<int64_t>(sizeof(double));
     int64_t p3 = bf3_panel_bytes(static_cast<int>(n));
-    // + 1 KiB: the solve stages its last subpanel in whole KiB
-    if (trsm_bf3_panel_bytes(static_cast<int>(n)) + 1024 > p3)
-      p3 = trsm_bf3_panel_bytes(static_cast<int>(n)) + 1024;
+    // the solve's panels, the 1 KiB its staging may read past them, flags
+    if (trsm_bf3_ws_bytes(static_cast<int>(n)) > p3) p3 = trsm_bf3_ws_bytes(static_cast<int>(n));
     L.pan = off; off += align256(static_cast<size_t>(pb > p3 ? pb : p3));
   }
   L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
@@ -389,7 +388,7 @@ BwdLayout make_bwd_layout(int64_t m, int64_t n) {
   int64_t pe = panel_elems(ni) > dense_panel_elems(ni) ? panel_elems(ni) : dense_panel_elems(ni);
   pe *= static_cast<int64_t>(sizeof(double));
   if (bf3_panel_bytes(ni) > pe) pe = bf3_panel_bytes(ni);
-  if (trsm_bf3_panel_bytes(ni) + 1024 > pe) pe = trsm_bf3_panel_bytes(ni) + 1024;
+  if (trsm_bf3_ws_bytes(ni) > pe) pe = trsm_bf3_ws_bytes(ni);
   L.pan = off; off += align256(static_cast<size_t>(pe));
   L.Tinv = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));
   L.Rw = off; off += align256(static_cast<size_t>(n) * n * sizeof(double));

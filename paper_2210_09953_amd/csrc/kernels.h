@@ -128,11 +128,20 @@ inline int64_t dense_panel_elems(int n) {
 }
 
 // Byte offset of subpanel b in the FP32 solve's bf16 x 3 panels: subpanel
-// b' holds (b'+1)/2 chunks of 3072 bytes and a 1536-byte diagonal inverse.
+// b' holds (b'+1)/2 chunks of 3072 bytes and a 3072-byte diagonal part (the
+// block's inverse and the block itself, 1536 bytes each).
 __host__ __device__ inline int64_t trsm_bf3_panel_offset(int b) {
-  return 3072 * static_cast<int64_t>(b / 2) * ((b + 1) / 2) + 1536 * static_cast<int64_t>(b);
+  return 3072 * static_cast<int64_t>(b / 2) * ((b + 1) / 2) + 3072 * static_cast<int64_t>(b);
 }
-inline int64_t trsm_bf3_panel_bytes(int n) { return trsm_bf3_panel_offset((n + 15) / 16); }
+__host__ __device__ inline int64_t trsm_bf3_panel_bytes(int n) {
+  return trsm_bf3_panel_offset((n + 15) / 16);
+}
+// The solve's refinement flags (one int per subpanel, at most 16) sit past
+// the panels and the 1 KiB the staging may read beyond them.
+__host__ __device__ inline int64_t trsm_bf3_flags_offset(int n) {
+  return trsm_bf3_panel_bytes(n) + 1024;
+}
+inline int64_t trsm_bf3_ws_bytes(int n) { return trsm_bf3_flags_offset(n) + 64; }
 
 inline int64_t panel_elems(int n) {
   const int64_t nb = (n + 15) / 16;

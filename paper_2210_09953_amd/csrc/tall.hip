@@ -584,7 +584,14 @@ __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int
 // 16 x 16 diagonal block (formed in FP64 by make_trsm_bf3_panels_kernel).
 // Both products split their FP32 operands exactly into three bf16 parts and
 // take the six significant products (as in trmm_bf3_kernel), so each is as
-// accurate as an FP32 product.  The transposed setup (panel columns x rows)
+// accurate as an FP32 product.  Applying Tb costs a backward error of about
+// u || |Tb| |Rbb| || |D| instead of substitution's u |Q_b| |Rbb| (Higham Thm
+// 8.5, the bound Section 5.1 builds on); when the panels flag a block whose
+// || |Tb| |Rbb| || is large, every block takes one refinement step, E += Tb^T
+// (D - Rbb^T E), with the residual from the six significant products (FP32
+// accurate) and the correction from the three leading ones: the backward
+// error is then u |D| + O(u^2 || |Tb| |Rbb| ||^2) |D|, as for substitution
+// while u cond(Rbb) << 1.  The transposed setup (panel columns x rows)
 // makes the solved block, as the 16x16 matrix cores return it, directly the
 // operand of the later updates: a wave keeps its 16 rows of Q split in
 // registers (two subpanels per 32-wide chunk, in the column order the panels
@@ -594,8 +601,11 @@ __global__ __launch_bounds__(64 * kTallWaves) void trmm_bf3_kernel(float* Q, int
 // its rows before it writes).
 typedef short s4b_t __attribute__((ext_vector_type(4)));
 
-// Bytes of subpanel b of the solve's panels ((b+1)/2 chunks, diagonal inverse).
-__host__ __device__ constexpr int trsm_bf3_psize(int b) { return ((b + 1) / 2) * 3072 + 1536; }
+// Bytes of subpanel b of the solve's panels that are staged: (b+1)/2 chunks
+// and the diagonal block's inverse, plus the block itself when refining.
+__host__ __device__ constexpr int trsm_bf3_psize(int b, bool rf) {
+  return ((b + 1) / 2) * 3072 + (rf ? 3072 : 1536);
+}
 
 // FULL: whole tiles of 16 kTallWaves rows below m, n = 16 NB, NB >= 4 (no
 // bounds checks, so the wait counts are exact).  When NB % 4 == 0 the panel
@@ -604,13 +614,17 @@ __host__ __device__ constexpr int trsm_bf3_psize(int b) { return ((b + 1) / 2) *
 // first two panels (and X subpanels) are staged during the last two of the
 // current one.  Otherwise a workgroup solves tile blk0 + blockIdx.x, with
 // bounds checks unless FULL.
-template <int NB, bool FULL>
+//
+// The refinement is a separate instance (RF): both are launched, and the one
+// that does not match the panels' flags returns at once, so that the plain
+// instance keeps its registers.
+template <int NB, bool FULL, bool RF>
 __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* X, int64_t m, int n,
                                                        int64_t ldx,
                                                        const unsigned char* __restrict__ pan3,
                                                        float* Q, int64_t ldq, int64_t blk0) {
   constexpr int NCH = (NB + 1) / 2;
-  constexpr int PMAX = (NB / 2) * 3072 + 1536;
+  constexpr int PMAX = trsm_bf3_psize(NB - 1, RF);
   constexpr int SLOT = dma_kib(PMAX) * 1024;
   constexpr bool persist = FULL && NB % 4 == 0;
   constexpr int NSL = persist ? 4 : 3;
@@ -658,7 +672,7 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
   };
   u4b_t qb[NCH][3];
   auto stage = [&](int b, int sl) {
-    dma_panel(panv + trsm_bf3_panel_offset(b), trsm_bf3_psize(b), ring + SLOT * sl,
+    dma_panel(panv + trsm_bf3_panel_offset(b), trsm_bf3_psize(b, RF), ring + SLOT * sl,
               ring + NSL * SLOT, wave, lane);
   };
   // bf16 planes of four FP32 values, two per 32-bit word (element 0 low).
@@ -677,6 +691,15 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
     const uint2 u = make_uint2(w[0], w[1]);
     return __builtin_bit_cast(s4b_t, u);
   };
+  // One refinement flag per subpanel: any set one refines every block.
+  bool refine = false;
+  {
+    const int* fl = reinterpret_cast<const int*>(pan3 + trsm_bf3_flags_offset(n));
+#pragma unroll
+    for (int b = 0; b < NB; ++b) refine |= fl[b] != 0;
+    refine = __builtin_amdgcn_readfirstlane(refine ? 1 : 0) != 0;
+  }
+  if (refine != RF) return;
   stage(0, 0);
   load_x(tile, 0, 0);
   if (NB > 1) {
@@ -700,7 +723,7 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
       // harmless repeat of this tile's on the last one).
       if (full) {
         constexpr bool staged = (b + 1 < NB) || persist;  // at subpanel b - 1
-        constexpr int d1 = staged ? dma_per_wave(trsm_bf3_psize((b + 1) % NB)) + 1 : 0;
+        constexpr int d1 = staged ? dma_per_wave(trsm_bf3_psize((b + 1) % NB, RF)) + 1 : 0;
         if (b >= 2) {
           wait_vmcnt<d1 + 8>();
         } else if (first) {
@@ -774,6 +797,28 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
       E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
       E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
       E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
+      if (RF) {
+        // -Rbb^T E (smallest products first), then the residual and the
+        // correction Tb^T r from its two leading planes.
+        uint32_t fh[2], fd[2], fl[2];
+        split4(E, fh, fd, fl);
+        const s4b_t rh = __builtin_bit_cast(s4b_t, pd[192]);
+        const s4b_t rd = __builtin_bit_cast(s4b_t, pd[256]);
+        const s4b_t rl = __builtin_bit_cast(s4b_t, pd[320]);
+        f4 F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rl, as_s4(fh), F, 0, 0, 0);
+        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fl), F, 0, 0, 0);
+        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fh), F, 0, 0, 0);
+        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fd), F, 0, 0, 0);
+        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fh), F, 0, 0, 0);
+        const f4 res = D + F;
+        uint32_t gh[2], gd[2], gl[2];
+        split4(res, gh, gd, gl);
+        f4 C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(gh), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gd), C, 0, 0, 0);
+        C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gh), C, 0, 0, 0);
+        E += C;
+      }
       float* qout = Q + row;
       if (full) {
         float* qo = qout + static_cast<int64_t>(4 * lg) * ldqv;
@@ -827,14 +872,20 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
     const float* x = static_cast<const float*>(X);
     float* q = static_cast<float*>(Q);
     const unsigned char* p3 = static_cast<const unsigned char*>(pan);
-#define RCQ_S3_CASE(NBV)                                                                   \
-  case NBV:                                                                                \
+#define RCQ_S3_RF(NBV, RFV)                                                                \
+  do {                                                                                     \
     if (nfull > 0)                                                                         \
-      trsm_bf3_kernel<NBV, true><<<static_cast<unsigned>(gfull), 64 * kTallWaves, 0, st>>>( \
-          x, m, n, ldx, p3, q, ldq, 0);                                                    \
+      trsm_bf3_kernel<NBV, true, RFV><<<static_cast<unsigned>(gfull), 64 * kTallWaves, 0,  \
+                                        st>>>(x, m, n, ldx, p3, q, ldq, 0);                \
     if (tiles > nfull)                                                                     \
-      trsm_bf3_kernel<NBV, false><<<static_cast<unsigned>(tiles - nfull), 64 * kTallWaves, \
-                                    0, st>>>(x, m, n, ldx, p3, q, ldq, nfull);             \
+      trsm_bf3_kernel<NBV, false, RFV><<<static_cast<unsigned>(tiles - nfull),             \
+                                         64 * kTallWaves, 0, st>>>(x, m, n, ldx, p3, q,    \
+                                                                   ldq, nfull);            \
+  } while (0)
+#define RCQ_S3_CASE(NBV)  \
+  case NBV:               \
+    RCQ_S3_RF(NBV, false); \
+    RCQ_S3_RF(NBV, true);  \
     break;
     switch (nb) {
       RCQ_S3_CASE(1) RCQ_S3_CASE(2) RCQ_S3_CASE(3) RCQ_S3_CASE(4) RCQ_S3_CASE(5) RCQ_S3_CASE(6)
@@ -843,6 +894,7 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
       default: return hipErrorInvalidValue;
     }
 #undef RCQ_S3_CASE
+#undef RCQ_S3_RF
     return hipGetLastError();
   }
   return trsm_dispatch<double>(nb, static_cast<const double*>(X), m, n, ldx,
@@ -1061,9 +1113,12 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
 // as accurate as an FP32 product; the six bf16 products of a pair cost less
 // than one FP32 matrix-core product.  The matrix cores sum one 32-row step
 // from zero (a long accumulation inside the bf16 matrix-core instruction
-// drifts: ||Q^T Q - I|| ~ 1e-5 was measured at 4e6 rows); steps are added in
-// FP32 with round-to-nearest vector adds and folded into the workgroup's
-// FP64 partial every kGrFlush rows, as in gram_kernel.
+// drifts: ||Q^T Q - I|| ~ 1e-5 was measured at 4e6 rows), and each step's
+// FP32 result is added into FP64 accumulators held in registers.  A row
+// split's sums therefore carry one FP32 rounding per step relative to that
+// step's own terms: a column whose norm sits in a few rows (one large entry)
+// loses nothing to the later, smaller steps, as it would in an FP32 running
+// sum.  The partial is written once, at the end of the split.
 //
 // One workgroup owns one row range and the whole upper triangle, in 64 x 64
 // tiles: one wave per off-diagonal tile, one wave per diagonal tile (two
@@ -1114,12 +1169,15 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
   double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
 
-  // Accumulators: off-diagonal sub-tile (a, b) at 4 a + b; diagonal tile t,
-  // sub-tile (a <= b) at 10 t + (rank of (a, b) in row order).
-  f4 acc[G::kAcc];
+  // FP64 accumulators: off-diagonal sub-tile (a, b) at 4 a + b; diagonal
+  // tile t, sub-tile (a <= b) at 10 t + (rank of (a, b) in row order).
+  d4 acc[G::kAcc];
 #pragma unroll
-  for (int i = 0; i < G::kAcc; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-  bool first = true;
+  for (int i = 0; i < G::kAcc; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  auto add_step = [](d4& a, const f4& c) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[v] += static_cast<double>(c[v]);
+  };
   auto flush = [&]() {
     if (offd) {
       int64_t lo = (64 * ti + drow<float>(lg, 0)) + static_cast<int64_t>(64 * tj + l16) * npg;
@@ -1133,9 +1191,7 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
           for (int v = 0; v < 4; ++v) {
             double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
                         static_cast<int64_t>(16 * b) * npg;
-            const double val = static_cast<double>(acc[4 * a + b][v]);
-            *p = first ? val : *p + val;
-            acc[4 * a + b][v] = 0.f;
+            *p = acc[4 * a + b][v];
             if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);
           }
     } else {
@@ -1155,15 +1211,12 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
               for (int v = 0; v < 4; ++v) {
                 double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
                             static_cast<int64_t>(16 * b) * npg;
-                const double val = static_cast<double>(acc[idx][v]);
-                *p = first ? val : *p + val;
-                acc[idx][v] = 0.f;
+                *p = acc[idx][v];
                 if (v == 3) __builtin_amdgcn_sched_barrier(0);
               }
         }
       }
     }
-    first = false;
   };
 
   // Loads: task t = (column t / 4, rows 8 (t % 4) ..); kPer tasks per thread.
@@ -1220,7 +1273,6 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
     stage_in(qs3);
   }
   __syncthreads();
-  int64_t since = 0;
   int cur = 0;
   for (int64_t r0 = r_begin; r0 < r_end; r0 += kG3Rows) {
     const bool more = r0 + kG3Rows < r_end;
@@ -1256,7 +1308,7 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
 #pragma unroll
         for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], c4[b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[4 * a + b] += c4[b];
+        for (int b = 0; b < 4; ++b) add_step(acc[4 * a + b], c4[b]);
       }
     } else {
 #pragma unroll
@@ -1284,7 +1336,7 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
           RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(od[a], oh[b], c10[i_], 0, 0, 0))
           RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], od[b], c10[i_], 0, 0, 0))
           RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], oh[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(acc[10 * t + i_] += c10[i_])
+          RCQ_G3_TRI(add_step(acc[10 * t + i_], c10[i_]))
 #undef RCQ_G3_TRI
         }
       }
@@ -1292,11 +1344,6 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
     if (more) stage_in(qs3 + (cur ^ 1) * G::kBuf);
     __syncthreads();
     cur ^= 1;
-    since += kG3Rows;
-    if (since >= kGrFlush) {
-      flush();
-      since = 0;
-    }
   }
   flush();
 }
