@@ -325,6 +325,33 @@ int rcholqr_profile_read(double* ms);
  * not a multiple of 16, RCHOLQR_ERR_HIP if the launch failed. */
 int rcholqr_device_copy(const void* src, void* dst, size_t bytes, void* stream);
 
+/* rcholqr_factor for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch sequence and kernels as rcholqr_factor with passes, kind and
+ * precision as there (so the same Q and R, bit for bit), but the workspace
+ * is a library-owned device array of rcholqr_noalloc_max_bytes() bytes
+ * (256 MiB; every GPU the library runs on holds its own copy until the
+ * process ends), not a caller buffer.  The call allocates, frees and
+ * clears nothing: every word the kernels read is written first in the same
+ * call (the status word included).
+ *
+ *  X, m, n, ldx, k, seed, sketch_kind, passes, precision, Q, ldq, R, ldr
+ *         as rcholqr_factor (no S, R_s or R' outputs).
+ * Returns 0, -i for invalid argument i (1-based), RCHOLQR_ERR_NOALLOC_SIZE
+ * when the problem's workspace (rcholqr_workspace_bytes) exceeds the array,
+ * or RCHOLQR_ERR_HIP.  Calls on one GPU share its array and each keeps the
+ * last call's contents: calls that overlap in time on one GPU (two streams,
+ * two host threads) race and give undefined results; serialise them.
+ * rcholqr_noalloc_status() reads the status word of the last completed
+ * call on the current device (it synchronises the device). */
+#define RCHOLQR_ERR_NOALLOC_SIZE (-3000)
+size_t rcholqr_noalloc_max_bytes(void);
+int rcholqr_factor_noalloc(const void* X, int64_t m, int64_t n, int64_t ldx,
+                           int64_t k, uint64_t seed, int sketch_kind, int passes,
+                           int precision, void* Q, int64_t ldq, double* R,
+                           int64_t ldr, void* stream);
+int rcholqr_noalloc_status(int* info);
+
 /* Human-readable text for a return code or status value. */
 const char* rcholqr_error_string(int code);
 

@@ -13,7 +13,8 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, F64, F32, MIXED,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
                       status, error_string, fortran, empty_fortran, PHASES,
                       profile_enable, profile_read, backward, BatchedFactor, Problem, ColumnQR,
-                      device_copy, reduced, rr)
+                      device_copy, reduced, rr, factor_noalloc, noalloc_status,
+                      noalloc_max_bytes)
 from .autograd import RCholQR2, rcholqr2
 
 __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "F64", "F32", "MIXED",
@@ -21,4 +22,5 @@ __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "F64", "F32", "MIXED
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",
            "profile_enable", "profile_read", "backward", "RCholQR2", "rcholqr2", "device_copy",
-           "BatchedFactor", "Problem", "ColumnQR", "reduced", "rr"]
+           "BatchedFactor", "Problem", "ColumnQR", "reduced", "rr", "factor_noalloc",
+           "noalloc_status", "noalloc_max_bytes"]

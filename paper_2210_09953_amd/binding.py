@@ -92,6 +92,13 @@ def lib():
     L.rcholqr_rr.restype = i32
     L.rcholqr_device_copy.argtypes = [vp, vp, sz, vp]
     L.rcholqr_device_copy.restype = i32
+    L.rcholqr_noalloc_max_bytes.argtypes = []
+    L.rcholqr_noalloc_max_bytes.restype = sz
+    L.rcholqr_factor_noalloc.argtypes = [vp, i64, i64, i64, i64, u64, i32, i32, i32, vp, i64,
+                                         dp, i64, vp]
+    L.rcholqr_factor_noalloc.restype = i32
+    L.rcholqr_noalloc_status.argtypes = [ctypes.POINTER(i32)]
+    L.rcholqr_noalloc_status.restype = i32
     L.rcholqr_error_string.argtypes = [i32]
     L.rcholqr_error_string.restype = ctypes.c_char_p
     _LIB = L
@@ -185,6 +192,39 @@ def factor(X, k, seed, kind=GAUSSIAN, passes=2, precision=None, want_s=False,
     if want_s or want_factors:
         return Q, R, dict(S=S, Rs=Rs, Rp=Rp, ws=ws)
     return Q, R
+
+
+def noalloc_max_bytes():
+    return int(lib().rcholqr_noalloc_max_bytes())
+
+
+def factor_noalloc(X, k, seed, kind=GAUSSIAN, passes=2, precision=None, Q=None, R=None):
+    """factor() through rcholqr_factor_noalloc: the library's own device
+    array is the workspace (no workspace tensor; Q and R are allocated here
+    unless given).  Returns (Q, R); noalloc_status() reads the status."""
+    if precision is None:
+        precision = F64 if X.dtype == torch.float64 else F32
+    X = fortran(X)
+    m, n = X.shape
+    dt = _dtype_for(precision)
+    if X.dtype != dt:
+        raise TypeError(f"X must be {dt} for precision {precision}")
+    if Q is None:
+        Q = empty_fortran(m, n, dt, X.device)
+    if R is None:
+        R = empty_fortran(n, n, torch.float64, X.device)
+    code = lib().rcholqr_factor_noalloc(_ptr(X), m, n, _ld(X), k, int(seed), kind, passes,
+                                        precision, _ptr(Q), _ld(Q), _ptr(R), _ld(R), _stream())
+    _check(code, "rcholqr_factor_noalloc")
+    return Q, R
+
+
+def noalloc_status():
+    """Status word of the last completed rcholqr_factor_noalloc call on the
+    current device (synchronises)."""
+    info = ctypes.c_int(0)
+    _check(lib().rcholqr_noalloc_status(ctypes.byref(info)), "rcholqr_noalloc_status")
+    return int(info.value)
 
 
 def reduced(X, k, l, seed, kind=RADEMACHER, precision=None, want_s=False, ws=None):

@@ -11,6 +11,7 @@
 //                                                                 Q = Q1 R'^{-1}
 #include <math.h>
 #include <algorithm>
+#include <mutex>
 #include <string.h>
 
 #include "../../include/rcholqr.h"
@@ -723,6 +724,70 @@ int rcholqr_col_block(const void* Xb, int64_t m, int64_t j0, int64_t b, int64_t 
   return 0;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// rcholqr_factor_noalloc: rcholqr_factor with its workspace in a
+// library-owned device array.  `scratch` names a host-side stand-in in host
+// code; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever passed to kernels.
+namespace {
+constexpr size_t kScratchBytes = size_t{256} << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// The current device's scratch address (resolved on its first use there).
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RCHOLQR_ERR_HIP;
+  ScratchSlot& sl = g_scratch[dev];
+  std::call_once(sl.once, [&sl]() {
+    void* p = nullptr;
+    sl.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (sl.err == hipSuccess) sl.ptr = p;
+  });
+  if (sl.err != hipSuccess || sl.ptr == nullptr) return RCHOLQR_ERR_HIP;
+  *out = sl.ptr;
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+size_t rcholqr_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int rcholqr_factor_noalloc(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k,
+                           uint64_t seed, int sketch_kind, int passes, int precision, void* Q,
+                           int64_t ldq, double* R, int64_t ldr, void* stream) {
+  const int bad = check_factor_args(X, m, n, ldx, k, sketch_kind, passes, precision, Q, ldq, R,
+                                    ldr, nullptr, 0);
+  if (bad) return bad;
+  const Layout L = make_layout(m, n, k, sketch_kind, passes, precision);
+  if (L.total > kScratchBytes) return RCHOLQR_ERR_NOALLOC_SIZE;
+  void* ws = nullptr;
+  const int rc = scratch_of_current_device(&ws);
+  if (rc != 0) return rc;
+  return factor_one(X, m, n, ldx, k, seed, sketch_kind, passes, precision, Q, ldq, R, ldr, nullptr,
+                    0, nullptr, nullptr, ws, L, static_cast<hipStream_t>(stream), true);
+}
+
+int rcholqr_noalloc_status(int* info) {
+  if (!info) return -1;
+  void* ws = nullptr;
+  const int rc = scratch_of_current_device(&ws);
+  if (rc != 0) return rc;
+  if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
+  if (hipMemcpy(info, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return RCHOLQR_ERR_HIP;
+  return 0;
+}
+
 int rcholqr_status(const void* ws, int* info) {
   if (!ws || !info) return -1;
   if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
@@ -797,6 +862,8 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx, const double*
 const char* rcholqr_error_string(int code) {
   if (code == 0) return "success";
   if (code == RCHOLQR_ERR_HIP) return "HIP launch or runtime error";
+  if (code == RCHOLQR_ERR_NOALLOC_SIZE)
+    return "problem needs more workspace than the no-allocation entry point holds";
   if (code < 0) return "invalid argument (the -code-th argument, 1-based)";
   if (code == RCHOLQR_SKETCH_RANK) return "zero diagonal in the sketch R (rank-deficient X or failed embedding)";
   if (code == RCHOLQR_NONFINITE) return "non-finite value in X";
