@@ -16,6 +16,12 @@ constexpr int kWave = 64;
 // D(16x16): element v holds D[drow(lg, v)][l16], where the row index is
 // lg + 4 v for the FP64 product and 4 lg + v for the FP32 one (measured on
 // gfx950 with a one-hot probe).
+// Wave index within the workgroup as a wave-uniform (scalar) value, so that
+// branches on it are scalar branches and not exec-masked divergent code.
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
 __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }

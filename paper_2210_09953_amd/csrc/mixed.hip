@@ -78,7 +78,11 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
     double* __restrict__ part, int srht_l) {
   constexpr int S = kQBlock * SB;  // rows per stage
   constexpr int KS = S / 64;       // matrix-core steps per stage
-  constexpr int LD = S + 16;       // LDS bytes per column of a digit plane
+  // LDS bytes per column of a digit plane: 2 mod 16 chunks of 16 bytes, so
+  // that a matrix-core operand read (16 columns x 4 row chunks of 16 bytes)
+  // is free of bank conflicts on gfx950 (a stride of 1 mod 16 chunks costs 4
+  // extra cycles per read, measured).
+  constexpr int LD = S + 32;
   constexpr int G = S / 16;        // quantiser row groups per column
   extern __shared__ __align__(16) unsigned char smem[];
   const int Tg = wt * TT * 16, Cg = wc * CT * 16;
@@ -103,8 +107,13 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
   const int l16 = lane & 15, lg = lane >> 4;
   const int wrow = wave % wt, wcol = wave / wt;
   const int c0 = h * Cg, theta0 = tgi * Tg;
-  const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
-  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  // Split s takes the stages s, s + nsplit, s + 2 nsplit, ...: at any time
+  // the running workgroups read one contiguous band of rows (long runs per
+  // column).  rows_per_split bounds the rows a split sums (int32 range).
+  (void)rows_per_split;
+  const int64_t sstride = static_cast<int64_t>(gridDim.x / (ktiles * nh)) * S;
+  const int64_t r_begin = static_cast<int64_t>(s) * S;
+  const int64_t r_end = m;
   const int ntask = G * Cg;  // quantiser task: 16 rows (group g) of one column
   const bool vec = ((ldx & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
 
@@ -125,11 +134,13 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
   for (int sl = 0; sl < NSL; ++sl) {
     sq[sl] = kQUnset;
     const int task = tid + sl * nthr;
-    // The four column groups of a wave take columns 4 apart (a 4 x 4
-    // transpose within each 16 columns), so that their digit writes fall
-    // in distinct LDS banks.
+    // The four column groups of a wave take columns 2 apart (within each
+    // 16 columns, bits b3 b2 b1 b0 of the group become b3 b1 b0 b2), so that
+    // their digit writes (column stride 72 words) fall in distinct banks.
     const int cg = task / G;
-    qcol[sl] = (G == 16) ? ((cg & ~15) | ((cg & 3) << 2) | ((cg >> 2) & 3)) : cg;
+    qcol[sl] = (G == 16)
+                   ? ((cg & ~15) | ((cg & 3) << 1) | ((cg >> 2) & 1) | (cg & 8))
+                   : cg;
     qg[sl] = task % G;
     const int c = (c0 + qcol[sl] < n) ? c0 + qcol[sl] : n - 1;
     qsrc[sl] = X + static_cast<int64_t>(c) * ldx + 4 * qg[sl];
@@ -310,8 +321,8 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
     draw(r0, 0);
   }
   __syncthreads();
-  if (r0 + S < r_end) load_stage(r0 + S);
-  for (; r0 < r_end; r0 += S, cur ^= 1) {
+  if (r0 + sstride < r_end) load_stage(r0 + sstride);
+  for (; r0 < r_end; r0 += sstride, cur ^= 1) {
     // Columns whose scale grew for this stage: fold at the old scale.
 #pragma unroll
     for (int b = 0; b < CT; ++b) {
@@ -358,10 +369,10 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
             if (j >= 1 && j <= 4) qdigits(ks, j - 1, fq, cur ^ 1);
             // This slot's registers are free again: fetch its rows of the
             // stage after next, a whole stage ahead of their use.
-            if (j == 5) load_slot(ks, r0 + 2 * S);
+            if (j == 5) load_slot(ks, r0 + 2 * sstride);
           } else if (ks == NSL) {
             if (j == 0) {
-              const uint64_t blk = static_cast<uint64_t>((r0 + S) >> 7) + psb;
+              const uint64_t blk = static_cast<uint64_t>((r0 + sstride) >> 7) + psb;
               // Rademacher: words (blk, row, RADE); SRHT: the signs (blk, 0, SRHD),
               // then the row's Walsh pattern and parity term (srht_words)
               ph = PhiloxState{static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
@@ -376,7 +387,7 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
             if (j == 5) {
               uint32_t* z = zb + (cur ^ 1) * zb_sz + (psb * Tg + pr) * kQZs;
               if (srht) {
-                const uint32_t blk32 = static_cast<uint32_t>(((r0 + S) >> 7) + psb);
+                const uint32_t blk32 = static_cast<uint32_t>(((r0 + sstride) >> 7) + psb);
                 const uint32_t shi = (__builtin_popcount(spk & 0x1FFFFFFu & blk32) & 1) ? ~0u : 0u;
                 const Words wl = srht_walsh(spk >> 25);
                 z[0] = ph.c0 ^ wl.w0 ^ shi;
@@ -413,16 +424,16 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
         }
         if (ks < NSL) {
           quantise(ks, cur ^ 1);
-          load_slot(ks, r0 + 2 * S);
+          load_slot(ks, r0 + 2 * sstride);
         }
       }
 #pragma unroll
       for (int sl = KS; sl < NSL; ++sl) {
         quantise(sl, cur ^ 1);
-        load_slot(sl, r0 + 2 * S);
+        load_slot(sl, r0 + 2 * sstride);
       }
     }
-    if (!FULL) draw(r0 + S, cur ^ 1);
+    if (!FULL) draw(r0 + sstride, cur ^ 1);
     if (orv >> 24) *badflag = 1;
     __syncthreads();
   }
@@ -479,7 +490,7 @@ static I8Plan i8_plan(int k, int n) {
 }
 
 static size_t i8_lds_bytes(const I8Plan& p) {
-  const int tg = 16 * p.tt * p.wt, cg = 16 * p.ct * p.wc, ld = kQBlock * p.sb + 16;
+  const int tg = 16 * p.tt * p.wt, cg = 16 * p.ct * p.wc, ld = kQBlock * p.sb + 32;
   return static_cast<size_t>(2 * 3 * cg * ld + 2 * tg * p.sb * kQZs * 4 + 2 * cg * 4 + 16);
 }
 

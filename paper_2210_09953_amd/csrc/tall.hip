@@ -1120,24 +1120,30 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
 // loses nothing to the later, smaller steps, as it would in an FP32 running
 // sum.  The partial is written once, at the end of the split.
 //
-// One workgroup owns one row range and the whole upper triangle, in 64 x 64
-// tiles: one wave per off-diagonal tile, one wave per diagonal tile (two
-// for n > 192; only the 10 upper 16 x 16 sub-tiles of a diagonal tile are
-// formed), so every row of Q is fetched and split exactly once.  For
-// n = 256: 6 + 2 = 8 waves, at most 36 sub-tile products per SIMD and stage.  Stages of 32 rows are
-// double buffered in LDS as three bf16 planes laid out as the matrix-core
-// operands: 16-byte chunks (8 rows of one column), chunk-major with a
-// 2-chunk pad, so that the operand reads (16 consecutive columns) and the
-// split's writes (2 columns x 4 row groups per 8 lanes) hit distinct banks.
+// One workgroup owns one set of rows and the whole upper triangle, in 64 x 64
+// tiles: two waves per off-diagonal tile (32 rows each), one wave per
+// diagonal tile (only its 10 upper 16 x 16 sub-tiles are formed), so every
+// row of Q is fetched and split exactly once and no wave holds more than 10
+// FP64 sub-tile accumulators (16 waves for n = 256, four per SIMD).  Stages of 32 rows are double buffered in LDS
+// as three bf16 planes laid out as the matrix-core operands: 16-byte chunks
+// (8 rows of one column), chunk-major with a row of chunks per 8 rows; the
+// operand reads (16 consecutive columns per lane group) and the split's
+// writes (16 consecutive columns per 16 lanes) are free of bank conflicts.
 // The next stage's loads are issued before the current stage's products.
 template <int NB64>
 struct TriGram {
   static constexpr int kOff = NB64 * (NB64 - 1) / 2;  // off-diagonal 64 x 64 tiles
-  static constexpr int kDpw = NB64 == 4 ? 2 : 1;      // diagonal tiles per wave
-  static constexpr int kWaves = kOff + (NB64 + kDpw - 1) / kDpw;
-  static constexpr int kAcc = 10 * kDpw > 16 ? 10 * kDpw : 16;
+  // Two waves per off-diagonal tile (row blocks 0-1 and 2-3: 8 sub-tiles
+  // each), one per diagonal tile (its 10 upper sub-tiles): at most 10 FP64
+  // sub-tile accumulators (80 registers) per wave, 16 waves for n = 256.
+  static constexpr int kWaves = 2 * kOff + NB64;
+  static constexpr int kAcc = 10;
   static constexpr int kCols = 64 * NB64;
-  static constexpr int kStr = kCols + 2;               // chunk row stride (16-byte units)
+  // Chunk row stride (16-byte units): a multiple of 16 chunks, so that an
+  // operand read (16 consecutive chunks per lane group, the four groups a
+  // stride apart) is free of bank conflicts on gfx950 (a stride of 2 mod 16
+  // costs 4 extra cycles per read, measured).
+  static constexpr int kStr = kCols;
   static constexpr int kBuf = 3 * 4 * kStr;            // chunks per stage buffer
   static constexpr int kTasks = 4 * kCols;             // 8-row pieces per stage
   static constexpr int kPer = (kTasks + 64 * kWaves - 1) / (64 * kWaves);
@@ -1153,24 +1159,29 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
   const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const bool offd = wave < G::kOff;
-  // Off-diagonal wave: tile (ti, tj), ti < tj.  Diagonal wave: tiles
-  // d0 .. d0 + ndiag - 1.
+  const bool offd = wave < 2 * G::kOff;
+  // Off-diagonal wave: tile (ti, tj), ti < tj, row blocks 2 half, 2 half + 1.
+  // Diagonal wave: tile td.
   int ti = 0, tj = 0;
   for (int j = 1, c = 0; j < NB64; ++j)
     for (int i = 0; i < j; ++i, ++c)
-      if (c == wave) {
+      if (c == (wave >> 1)) {
         ti = i;
         tj = j;
       }
-  const int d0 = G::kDpw * (wave - G::kOff);
-  const int ndiag = offd ? 0 : ((d0 + G::kDpw <= NB64) ? G::kDpw : NB64 - d0);
-  const int64_t r_begin = static_cast<int64_t>(s) * rows_per_split;
-  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+  const int half = wave & 1;
+  const int td = wave - 2 * G::kOff;
+  // Workgroup s takes the 32-row stages s, s + G, s + 2G, ... (G = the
+  // grid): at any time the workgroups read one contiguous band of rows.  Its
+  // partial sums these stages in that order.
+  (void)rows_per_split;
+  const int64_t nstage = (m + kG3Rows - 1) / kG3Rows;
+  const int64_t sstep = gridDim.x;
+  const int64_t r_end = m;
   double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
 
-  // FP64 accumulators: off-diagonal sub-tile (a, b) at 4 a + b; diagonal
-  // tile t, sub-tile (a <= b) at 10 t + (rank of (a, b) in row order).
+  // FP64 accumulators.  Off-diagonal wave: sub-tile (2 half + aa, b) at
+  // 4 aa + b.  Diagonal wave: sub-tile (a <= b) at its rank in row order.
   d4 acc[G::kAcc];
 #pragma unroll
   for (int i = 0; i < G::kAcc; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
@@ -1180,53 +1191,47 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
   };
   auto flush = [&]() {
     if (offd) {
-      int64_t lo = (64 * ti + drow<float>(lg, 0)) + static_cast<int64_t>(64 * tj + l16) * npg;
+      int64_t lo = (64 * ti + 32 * half + drow<float>(lg, 0)) +
+                   static_cast<int64_t>(64 * tj + l16) * npg;
       asm volatile("" : "+v"(lo));
       double* base = dst + lo;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
+            double* p = base + (16 * aa + (drow<float>(lg, v) - drow<float>(lg, 0))) +
                         static_cast<int64_t>(16 * b) * npg;
-            *p = acc[4 * a + b][v];
-            if (v == 3 && b == 3) __builtin_amdgcn_sched_barrier(0);
+            *p = acc[4 * aa + b][v];
           }
     } else {
+      int64_t lo = (64 * td + drow<float>(lg, 0)) + static_cast<int64_t>(64 * td + l16) * npg;
+      asm volatile("" : "+v"(lo));
+      double* base = dst + lo;
+      int idx = 0;
 #pragma unroll
-      for (int t = 0; t < G::kDpw; ++t) {
-        if (t < ndiag) {
-          const int td = d0 + t;
-          int64_t lo = (64 * td + drow<float>(lg, 0)) + static_cast<int64_t>(64 * td + l16) * npg;
-          asm volatile("" : "+v"(lo));
-          double* base = dst + lo;
-          int idx = 10 * t;
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
+        for (int b = a; b < 4; ++b, ++idx)
 #pragma unroll
-            for (int b = a; b < 4; ++b, ++idx)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
-                            static_cast<int64_t>(16 * b) * npg;
-                *p = acc[idx][v];
-                if (v == 3) __builtin_amdgcn_sched_barrier(0);
-              }
-        }
-      }
+          for (int v = 0; v < 4; ++v) {
+            double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
+                        static_cast<int64_t>(16 * b) * npg;
+            *p = acc[idx][v];
+          }
     }
   };
 
-  // Loads: task t = (column t / 4, rows 8 (t % 4) ..); kPer tasks per thread.
+  // Loads: task t = (column 16 (t / 64) + t % 16, rows 8 ((t / 16) % 4) ..),
+  // kPer tasks per thread: lane groups of 16 write 16 consecutive chunks.
   float pre[G::kPer][8];
   const bool vec = ((ldq & 3) == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int q = 0; q < G::kPer; ++q) {
       const int t = threadIdx.x + 64 * G::kWaves * q;
-      const int c = t >> 2, g = t & 3;
+      const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
       const int64_t r = r0 + 8 * g;
       const bool live = t < G::kTasks && c < n;
       const float* src = Q + static_cast<int64_t>(live ? c : 0) * ldq + r;
@@ -1246,7 +1251,7 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
     for (int q = 0; q < G::kPer; ++q) {
       const int t = threadIdx.x + 64 * G::kWaves * q;
       if (t < G::kTasks) {
-        const int c = t >> 2, g = t & 3;
+        const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
         uint32_t hp[8], dp[8], lp[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) split3(pre[q][e], hp[e], dp[e], lp[e]);
@@ -1268,76 +1273,63 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
   auto opnd = [&](const u4v_t* buf, int p, int c0) {
     return __builtin_bit_cast(bf8, buf[(p * 4 + lg) * G::kStr + c0 + l16]);
   };
-  if (r_begin < r_end) {
-    fetch(r_begin);
+  // Six significant bf16 products of a sub-tile, from zero, smallest first.
+  auto prod6 = [](const bf8& ah, const bf8& ad, const bf8& al, const bf8& bh, const bf8& bd,
+                  const bf8& bl) {
+    f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bd, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  };
+  if (s < nstage) {
+    fetch(static_cast<int64_t>(s) * kG3Rows);
     stage_in(qs3);
   }
   __syncthreads();
   int cur = 0;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kG3Rows) {
-    const bool more = r0 + kG3Rows < r_end;
-    if (more) fetch(r0 + kG3Rows);
+  for (int64_t j = s; j < nstage; j += sstep) {
+    const bool more = j + sstep < nstage;
+    if (more) fetch((j + sstep) * kG3Rows);
     const u4v_t* buf = qs3 + cur * G::kBuf;
     if (offd) {
-      bf8 bh[4], bd[4], bl[4];
+      // The wave's two row blocks held, the four column blocks streamed.
+      bf8 ah[2], ad[2], al[2];
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa) {
+        const int c0 = 64 * ti + 32 * half + 16 * aa;
+        ah[aa] = opnd(buf, 0, c0);
+        ad[aa] = opnd(buf, 1, c0);
+        al[aa] = opnd(buf, 2, c0);
+      }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        bh[b] = opnd(buf, 0, 64 * tj + 16 * b);
-        bd[b] = opnd(buf, 1, 64 * tj + 16 * b);
-        bl[b] = opnd(buf, 2, 64 * tj + 16 * b);
-      }
+        // one column block in flight (bounds the live operand registers)
+        __builtin_amdgcn_sched_barrier(0);
+        const bf8 bh = opnd(buf, 0, 64 * tj + 16 * b);
+        const bf8 bd = opnd(buf, 1, 64 * tj + 16 * b);
+        const bf8 bl = opnd(buf, 2, 64 * tj + 16 * b);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const bf8 ah = opnd(buf, 0, 64 * ti + 16 * a);
-        const bf8 ad = opnd(buf, 1, 64 * ti + 16 * a);
-        const bf8 al = opnd(buf, 2, 64 * ti + 16 * a);
-        // Four independent chains (one per column sub-tile), each from zero,
-        // smallest products first.
-        f4 c4[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bd[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], c4[b], 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd[b], c4[b], 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c4[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], c4[b], 0, 0, 0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) add_step(acc[4 * a + b], c4[b]);
+        for (int aa = 0; aa < 2; ++aa)
+          add_step(acc[4 * aa + b], prod6(ah[aa], ad[aa], al[aa], bh, bd, bl));
       }
     } else {
+      // Diagonal tile: sub-tile (a, b), a <= b, one column block b at a time
+      // with its row blocks a streamed from LDS.
+      const int c0 = 64 * td;
 #pragma unroll
-      for (int t = 0; t < G::kDpw; ++t) {
-        if (t < ndiag) {
-          const int c0 = 64 * (d0 + t);
-          bf8 oh[4], od[4], ol[4];
+      for (int b = 0; b < 4; ++b) {
+        const bf8 bh = opnd(buf, 0, c0 + 16 * b);
+        const bf8 bd = opnd(buf, 1, c0 + 16 * b);
+        const bf8 bl = opnd(buf, 2, c0 + 16 * b);
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            oh[b] = opnd(buf, 0, c0 + 16 * b);
-            od[b] = opnd(buf, 1, c0 + 16 * b);
-            ol[b] = opnd(buf, 2, c0 + 16 * b);
-          }
-          // The 10 upper sub-tiles as 10 independent chains.
-          f4 c10[10];
-#define RCQ_G3_TRI(STMT)                                                      \
-  {                                                                           \
-    int i_ = 0;                                                               \
-    _Pragma("unroll") for (int a = 0; a < 4; ++a)                             \
-    _Pragma("unroll") for (int b = a; b < 4; ++b, ++i_) { STMT; }             \
-  }
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(od[a], od[b], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0))
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ol[a], oh[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], ol[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(od[a], oh[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], od[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(c10[i_] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oh[a], oh[b], c10[i_], 0, 0, 0))
-          RCQ_G3_TRI(add_step(acc[10 * t + i_], c10[i_]))
-#undef RCQ_G3_TRI
+        for (int a = 0; a <= b; ++a) {
+          const bf8 xh = (a == b) ? bh : opnd(buf, 0, c0 + 16 * a);
+          const bf8 xd = (a == b) ? bd : opnd(buf, 1, c0 + 16 * a);
+          const bf8 xl = (a == b) ? bl : opnd(buf, 2, c0 + 16 * a);
+          // rank of (a, b) in row order
+          add_step(acc[4 * a - a * (a - 1) / 2 + (b - a)], prod6(xh, xd, xl, bh, bd, bl));
         }
       }
     }
