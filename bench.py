@@ -343,6 +343,29 @@ def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, passes=1, seed=
     return ms, r, float(torch.sqrt(s[0] / s[-1])), orth
 
 
+def host_cpu():
+    """lscpu's model, sockets, cores per socket and threads per core of this
+    host, and the CPUs this process may run on (affinity)."""
+    info = {}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket":
+                "cores_per_socket", "Thread(s) per core": "threads_per_core", "CPU(s)": "cpus"}
+        for line in out.splitlines():
+            if ":" not in line:
+                continue
+            k, v = (t.strip() for t in line.split(":", 1))
+            if k in keys and keys[k] not in info:
+                info[keys[k]] = int(v) if v.isdigit() else v
+    except Exception as e:  # lscpu missing: report what Python knows
+        info["lscpu_error"] = str(e)
+    if "sockets" in info and "cores_per_socket" in info:
+        info["physical_cores"] = info["sockets"] * info["cores_per_socket"]
+    info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
 def cpu_baseline(Xs_np, k, kind_code, budget_s=15.0):
     """FP64 CPU oracle (test infrastructure) on the first rows of X.
 
@@ -534,7 +557,7 @@ def main():
         log(f"[bench] cpu baseline (FP64 oracle) on up to {ms_rows} rows")
         m1, t, threads, st = cpu_baseline(Xs, k, kind, args.cpu_budget)
         cpu = {"value": round(m1 * n * xbytes / t / 1e9, 4), "unit": "GB/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "host": host_cpu(),
                "sample": f"first {m1} rows of X (n={n}, k={k}, {W['kind']}, 2 passes, FP64), "
                          f"{t:.1f} s, status {st}"}
         log(f"[bench] cpu: {cpu}")

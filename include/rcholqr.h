@@ -52,7 +52,13 @@ enum rcholqr_sketch_kind {
   RCHOLQR_GAUSSIAN = 0,
   RCHOLQR_RADEMACHER = 1,
   RCHOLQR_COUNTSKETCH = 2,
-  RCHOLQR_SRHT = 3
+  RCHOLQR_SRHT = 3,
+  /* Test only, rcholqr_factor (and rcholqr_factor_noalloc) alone: Theta = I
+   * with k = m (so m <= 1024), F64 or F32 precision.  Algorithm 2 then
+   * reduces to Householder QR of X itself: R_s is the R of X with a
+   * positive diagonal and Q = X R_s^{-1} its thin Q, which LAPACK's QR
+   * fixes up to rounding. */
+  RCHOLQR_IDENTITY_TESTONLY = 99
 };
 
 /* Working precision of the dominant (tall) operations.
@@ -255,7 +261,9 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx,
  * out over an internal pool of 8 non-blocking streams forked from and
  * joined back to `stream` with events, performs no allocation, memset or
  * synchronisation, and can therefore be captured into a HIP graph and
- * replayed (the pool is created on the first call, outside any capture).
+ * replayed (each device's pool is created on the first call on that device,
+ * outside any capture; calls on one device from several host threads at
+ * once must be serialised by the caller, since they share its pool).
  * Returns 0, -i for an invalid argument i, RCHOLQR_ERR_BATCH_ENTRY - j if
  * problem j is invalid, or RCHOLQR_ERR_HIP. */
 typedef struct rcholqr_problem {

@@ -8,7 +8,7 @@ raise: there is no fallback implementation.
 
 Matrices are column-major: an (m, n) tensor with stride (1, ld), ld >= m.
 """
-from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, F64, F32, MIXED,
+from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, IDENTITY_TESTONLY, F64, F32, MIXED,
                       LibraryMissing, RCholQRError, lib, lib_path,
                       workspace_bytes, factor, sketch, debug_theta, trsm,
                       status, error_string, fortran, empty_fortran, PHASES,
@@ -17,7 +17,7 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, F64, F32, MIXED,
                       noalloc_max_bytes)
 from .autograd import RCholQR2, rcholqr2
 
-__all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "F64", "F32", "MIXED",
+__all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "IDENTITY_TESTONLY", "F64", "F32", "MIXED",
            "LibraryMissing", "RCholQRError", "lib", "lib_path",
            "workspace_bytes", "factor", "sketch", "debug_theta", "trsm",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",

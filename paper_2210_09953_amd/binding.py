@@ -5,6 +5,7 @@ import os
 import torch
 
 GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT = 0, 1, 2, 3
+IDENTITY_TESTONLY = 99  # Theta = I, k = m (rcholqr_factor only; a test reduction)
 F64, F32, MIXED = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

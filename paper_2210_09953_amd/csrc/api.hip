@@ -30,6 +30,10 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+// Sketch kinds of rcholqr_factor: the four embeddings, and Theta = I
+// (test only; k = m, not with the mixed precision).
+bool valid_kind(int kind) { return (kind >= 0 && kind <= 3) || kind == kIdentity; }
+
 bool valid_dims(int64_t m, int64_t n, int64_t k) {
   return n >= 1 && n <= kMaxN && m >= n && k >= n && k <= kMaxK;
 }
@@ -38,7 +42,13 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
   Layout L{};
   SketchPlan& sp = L.sp;
   sp.npad = static_cast<int>(round_up(n, 16));
-  if (prec == kPrecMixed) {
+  if (kind == kIdentity) {
+    // Theta = I: P is X itself, no partial sums.
+    sp.nsplit = 0;
+    sp.ktiles = 0;
+    sp.kpad = static_cast<int>(k);
+    sp.rows_per_split = m;
+  } else if (prec == kPrecMixed) {
     // int8 matrix-core sketch (mixed.hip) chooses its own tiles and splits.
     mixed_sketch_plan(m, static_cast<int>(k), static_cast<int>(n), sp);
   } else if (kind == kCountSketch) {
@@ -166,9 +176,10 @@ extern "C" {
 
 size_t rcholqr_workspace_bytes(int64_t m, int64_t n, int64_t k, int sketch_kind, int passes,
                                int precision) {
-  if (!valid_dims(m, n, k) || sketch_kind < 0 || sketch_kind > 3 || passes < 1 || passes > 2 ||
+  if (!valid_dims(m, n, k) || !valid_kind(sketch_kind) || passes < 1 || passes > 2 ||
       precision < 0 || precision > 2)
     return 0;
+  if (sketch_kind == kIdentity && (k != m || precision == kPrecMixed)) return 0;
   return make_layout(m, n, k, sketch_kind, passes, precision).total;
 }
 
@@ -185,7 +196,8 @@ int check_factor_args(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t 
   if (m < n) return -2;
   if (ldx < m) return -4;
   if (k < n || k > kMaxK) return -5;
-  if (sketch_kind < 0 || sketch_kind > 3) return -7;
+  if (!valid_kind(sketch_kind)) return -7;
+  if (sketch_kind == kIdentity && k != m) return -5;
   if (passes < 1 || passes > 2) return -8;
   if (precision < 0 || precision > 2) return -9;
   if (precision == kPrecMixed && sketch_kind != kRademacher && sketch_kind != kSRHT) return -9;
@@ -209,7 +221,9 @@ int factor_one(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   double* Rsw = at<double>(ws, L.Rs);
   void* pan = at<void>(ws, L.pan);
   if (profile) prof_begin(st);
-  if (precision == kPrecMixed)
+  if (sketch_kind == kIdentity)
+    RCQ_TRY(launch_sketch_identity(X, f32, m, ni, ldx, P, k, st));
+  else if (precision == kPrecMixed)
     RCQ_TRY(launch_sketch_mixed(static_cast<const float*>(X), m, ni, ldx, ki, seed, L.sp,
                                 at<double>(ws, L.part), P, k, st, sketch_kind));
   else
@@ -254,25 +268,35 @@ int factor_one(const void* X, int64_t m, int64_t n, int64_t ldx, int64_t k, uint
   return 0;
 }
 
-// Streams and fork/join events of the batched entry point (created once,
-// default priority, non-blocking; no device memory is allocated).
+// Streams and fork/join events of the batched entry point, one set per
+// device (created on the first call on that device, with it current;
+// default priority, non-blocking; no device memory is allocated).  Creation
+// is serialised; calls that use one device's pool from several host threads
+// at once must be serialised by the caller (they share the fork/join events).
 constexpr int kPool = 8;
+constexpr int kPoolDevices = 64;
 struct Pool {
   bool ready = false;
   hipStream_t s[kPool];
   hipEvent_t fork, join[kPool];
 };
-Pool g_pool;
+Pool g_pool[kPoolDevices];
+std::mutex g_pool_mutex;
 
-int ensure_pool() {
-  if (g_pool.ready) return 0;
+// The current device's pool (created if needed), or nullptr on failure.
+Pool* ensure_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPoolDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  Pool& p = g_pool[dev];
+  if (p.ready) return &p;
   for (int i = 0; i < kPool; ++i) {
-    if (hipStreamCreateWithFlags(&g_pool.s[i], hipStreamNonBlocking) != hipSuccess) return RCHOLQR_ERR_HIP;
-    if (hipEventCreateWithFlags(&g_pool.join[i], hipEventDisableTiming) != hipSuccess) return RCHOLQR_ERR_HIP;
+    if (hipStreamCreateWithFlags(&p.s[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
   }
-  if (hipEventCreateWithFlags(&g_pool.fork, hipEventDisableTiming) != hipSuccess) return RCHOLQR_ERR_HIP;
-  g_pool.ready = true;
-  return 0;
+  if (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  p.ready = true;
+  return &p;
 }
 
 size_t batched_offset(const rcholqr_problem* probs, int i, int kind, int passes, int precision) {
@@ -337,11 +361,12 @@ int rcholqr_factor_batched(const rcholqr_problem* probs, int batch, int sketch_k
   }
   if (!ws) return -6;
   if (ws_bytes < batched_offset(probs, batch, sketch_kind, passes, precision)) return -7;
-  if (ensure_pool() != 0) return RCHOLQR_ERR_HIP;
+  Pool* pool = ensure_pool();
+  if (!pool) return RCHOLQR_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int used = batch < kPool ? batch : kPool;
-  RCQ_TRY(hipEventRecord(g_pool.fork, st));
-  for (int q = 0; q < used; ++q) RCQ_TRY(hipStreamWaitEvent(g_pool.s[q], g_pool.fork, 0));
+  RCQ_TRY(hipEventRecord(pool->fork, st));
+  for (int q = 0; q < used; ++q) RCQ_TRY(hipStreamWaitEvent(pool->s[q], pool->fork, 0));
   size_t off = 0;
   int rc = 0;
   for (int i = 0; i < batch && rc == 0; ++i) {
@@ -349,14 +374,14 @@ int rcholqr_factor_batched(const rcholqr_problem* probs, int batch, int sketch_k
     const Layout L = make_layout(p.m, p.n, p.k, sketch_kind, passes, precision);
     rc = factor_one(p.X, p.m, p.n, p.ldx, p.k, p.seed, sketch_kind, passes, precision, p.Q,
                     p.ldq, p.R, p.ldr, nullptr, 0, nullptr, nullptr,
-                    static_cast<char*>(ws) + off, L, g_pool.s[i % kPool], false);
+                    static_cast<char*>(ws) + off, L, pool->s[i % kPool], false);
     off += align256(L.total);
   }
   // Join every forked stream even after a failed launch, so that a stream
   // capture in progress is left well formed.
   for (int q = 0; q < used; ++q) {
-    RCQ_TRY(hipEventRecord(g_pool.join[q], g_pool.s[q]));
-    RCQ_TRY(hipStreamWaitEvent(st, g_pool.join[q], 0));
+    RCQ_TRY(hipEventRecord(pool->join[q], pool->s[q]));
+    RCQ_TRY(hipStreamWaitEvent(st, pool->join[q], 0));
   }
   return rc;
 }

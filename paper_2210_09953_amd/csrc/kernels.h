@@ -10,6 +10,8 @@ constexpr int kGaussian = 0;
 constexpr int kRademacher = 1;
 constexpr int kCountSketch = 2;
 constexpr int kSRHT = 3;
+// Test-only embedding Theta = I (k = m): the sketch is X itself.
+constexpr int kIdentity = 99;
 
 constexpr int kPrecF64 = 0;
 constexpr int kPrecF32 = 1;
@@ -41,6 +43,9 @@ hipError_t launch_theta_debug(int kind, int k, int64_t m, uint64_t seed, int64_t
 hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx, int k,
                          int kind, uint64_t seed, const SketchPlan& pl, double* part,
                          uint32_t* keys, double* P, int64_t ldp, hipStream_t st);
+// Theta = I: P = X promoted to FP64 (k = m rows).
+hipError_t launch_sketch_identity(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx,
+                                  double* P, int64_t ldp, hipStream_t st);
 hipError_t launch_sketch_reduce(const double* part, const SketchPlan& pl, int k, int n,
                                 double scale, double* P, int64_t ldp, hipStream_t st);
 // The split partials of the sketch without the reduction (rows 0..k-1 of

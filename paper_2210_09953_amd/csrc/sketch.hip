@@ -345,6 +345,26 @@ hipError_t launch_sketch(const void* X, bool x_is_f32, int64_t m, int n, int64_t
   return launch_sketch_reduce(part, pl, k, n, scale, P, ldp, st);
 }
 
+// Theta = I (the test-only embedding): P = X, FP32 values promoted exactly.
+template <typename TX>
+__global__ void sketch_identity_kernel(const TX* __restrict__ X, int64_t m, int n, int64_t ldx,
+                                       double* __restrict__ P, int64_t ldp) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx % m, c = idx / m;
+  P[i + c * ldp] = static_cast<double>(X[i + c * ldx]);
+}
+
+hipError_t launch_sketch_identity(const void* X, bool x_is_f32, int64_t m, int n, int64_t ldx,
+                                  double* P, int64_t ldp, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>(ceil_div(m * n, 256));
+  if (x_is_f32)
+    sketch_identity_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(X), m, n, ldx, P, ldp);
+  else
+    sketch_identity_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(X), m, n, ldx, P, ldp);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_reduce(const double* part, const SketchPlan& pl, int k, int n,
                                 double scale, double* P, int64_t ldp, hipStream_t st) {
   const int64_t total = static_cast<int64_t>(k) * n;
