@@ -343,6 +343,73 @@ def rr_leg(torch, rq, X, k, kind, prec_code, steps, warmup, tau, passes=1, seed=
     return ms, r, float(torch.sqrt(s[0] / s[-1])), orth
 
 
+def batched_leg(torch, rq, synth, steps, warmup, count=512):
+    """The persistent batched engine on the batched configuration; value =
+    GB/s of X (sum m n 4 bytes per call); roofline = HBM with the 2-pass
+    algorithmic traffic 5 sum(m n) 4 bytes (read X for the sketch, read X and
+    write Q1 in the solve, read Q1 and write Q in the product; the Gram reads
+    the chunk it just wrote, from cache)."""
+    shapes = synth.batched_shapes(count, seed=0)
+    Xs = [synth.make_x_torch(mm, nn, 1e-4, seed=1000 + i, dtype=torch.float32)
+          for i, (mm, nn, _) in enumerate(shapes)]
+    eng = rq.BatchedEngine(Xs, [kk for _, _, kk in shapes], [1 + i for i in range(count)],
+                           passes=2)
+    for _ in range(warmup):
+        eng.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        eng.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = eng.status()
+    worst = 0.0
+    for i in range(0, count, 16):  # every 16th problem: ||Q^T Q - I||_2
+        Q = eng.Qs[i].double()
+        nn = Q.shape[1]
+        worst = max(worst, torch.linalg.matrix_norm(
+            Q.T @ Q - torch.eye(nn, device=Q.device, dtype=torch.float64), 2).item())
+    # the same launch replayed from a HIP graph
+    eng.capture()
+    eng.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        eng.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    # for comparison: the same problems through rcholqr_factor_batched (one
+    # single-problem launch sequence per problem over the stream pool)
+    pool = rq.BatchedFactor(Xs, [kk for _, _, kk in shapes], [1 + i for i in range(count)],
+                            kind=rq.RADEMACHER, passes=2, precision=rq.MIXED)
+    for _ in range(max(1, warmup)):
+        pool.run()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        pool.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_pool = e0.elapsed_time(e1) / steps
+    del pool
+    xbytes = sum(mm * nn for mm, nn, _ in shapes) * 4
+    achieved = 5 * xbytes / (ms * 1e-3) / 1e9
+    out = {"value": round(xbytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+           "ms_per_step": round(ms, 4), "ms_graph_replay": round(ms_graph, 4),
+           "stream_pool_ms": round(ms_pool, 4), "problems": count, "x_bytes": xbytes,
+           "chunk_rows": eng.chunk, "statuses_nonzero": sum(1 for v in st if v != 0),
+           "worst_orth": worst,
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
+                        "algorithmic_bytes": 5 * xbytes}}
+    del eng, Xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def host_cpu():
     """lscpu's model, sockets, cores per socket and threads per core of this
     host, and the CPUs this process may run on (affinity)."""
@@ -404,6 +471,8 @@ def main():
                     help="skip the SRHT-sketch factorisation of the same X")
     ap.add_argument("--no-rr-leg", action="store_true",
                     help="skip the rank-revealing RCholeskyQR figure")
+    ap.add_argument("--no-batched-leg", action="store_true",
+                    help="skip the 512-problem batched-engine figure")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -412,7 +481,7 @@ def main():
                     help="turn two rocprofv3 --pmc runs into profiles/traffic_<workload>.md")
     ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
                     "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg "
-                    "--no-reduced-leg --no-srht-leg --no-col-leg --copy-probe")
+                    "--no-reduced-leg --no-srht-leg --no-col-leg --no-batched-leg --copy-probe")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
@@ -549,6 +618,16 @@ def main():
         log(f"[bench] f64: {ms64:.3f} ms/step orth={orth64:.2e} resid={res64:.2e} dR={dR:.2e}")
         del Q64, X64
 
+    # The batched configuration on the persistent batched engine: 512
+    # problems, m uniform in [2000, 200000], n in {16, 32, 64, 96, 128},
+    # k = 3n, sigma 1 -> 1e-4, FP32, Rademacher, 2 passes, one launch each.
+    batched = None
+    if not args.no_batched_leg:
+        batched = batched_leg(torch, rq, synth, args.steps, args.warmup)
+        log(f"[bench] batched engine: {batched['ms_per_step']:.3f} ms/step "
+            f"{batched['value']} GB/s, HBM frac {batched['roofline']['frac']}, "
+            f"worst orth {batched['worst_orth']:.2e}")
+
     cpu = None
     if not args.no_cpu:
         ms_rows = min(m, 1 << 21)
@@ -582,6 +661,7 @@ def main():
         "column_oriented": col,
         "rank_revealing": rrf,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

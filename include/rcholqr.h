@@ -85,6 +85,7 @@ enum rcholqr_precision {
 #define RCHOLQR_SKETCH_RANK 1    /* zero diagonal in the sketch R (X rank deficient or Theta failed to embed) */
 #define RCHOLQR_NONFINITE 2      /* non-finite value in X (seen through the sketch) */
 #define RCHOLQR_CHOL_BREAKDOWN 1000 /* + j: non-positive pivot at column j (0-based) of chol(Q^T Q) */
+#define RCHOLQR_BATCH_INVALID 3  /* batched engine: the problem was refused (see its checks) */
 
 #define RCHOLQR_ERR_HIP (-1000)
 
@@ -286,6 +287,67 @@ int rcholqr_factor_batched(const rcholqr_problem* probs, int batch,
 int rcholqr_batched_status(const rcholqr_problem* probs, int batch,
                            int sketch_kind, int passes, int precision,
                            const void* ws, int* info);
+
+/* Persistent batched engine: many independent problems in ONE kernel
+ * launch (plus a one-block setup launch), with no per-problem launches, no
+ * allocation, no memset and no host synchronisation, so the call can be
+ * captured into a HIP graph and replayed.  Workgroups (as many as are
+ * resident at once) take tasks from a queue in device memory:
+ *   sketch chunks (P_c = Theta X_c for row chunks c and 64 Theta rows at a
+ *   time), then per problem the FP64 Householder QR of P = sum_c P_c and
+ *   the solve panels, then solve chunks (Q1 = X R_s^{-1}, and for 2 passes
+ *   the chunk's Gram G_c), then per problem the FP64 Cholesky of
+ *   G = sum_c G_c with R = R' R_s, then product chunks (Q = Q1 R'^{-1}).
+ * A task waits (bounded spin) for its problem's previous phase; every
+ * reduction has a fixed order, so results are reproducible run to run.
+ * Problems: FP32 X and Q (column-major), FP64 R; n in {16, 32, ..., 128},
+ * k a multiple of 16 with n <= k <= 384, m >= n; sketch RCHOLQR_RADEMACHER
+ * (the same Theta, bit for bit, as rcholqr_factor with that seed); passes 1
+ * or 2.  X, Q and R are read and written as in rcholqr_factor (Q must not
+ * overlap X).  The products of X with the +-1 entries are exact (X split
+ * into three bf16 parts) and summed in FP32 per 32 rows, then in FP64; the
+ * solves and the Gram run on FP32 matrix cores (exact products), the small
+ * steps in FP64.
+ *
+ *  probs_dev   DEVICE array of `batch` descriptors (the same struct as the
+ *              stream-pool entry); a problem outside the rules above gets
+ *              status RCHOLQR_BATCH_INVALID and is skipped.
+ *  chunk_rows  rows per tall task, a positive multiple of 128; 0 takes the
+ *              value rcholqr_batched_engine_chunk(max n) returns (the
+ *              tuned one once rcholqr_init has loaded a tuning file).
+ *  ws          at least rcholqr_batched_engine_workspace_bytes(probs_host,
+ *              batch, passes, chunk_rows) bytes, computed from a HOST copy
+ *              of the same descriptors with the same chunk_rows; a smaller
+ *              buffer makes every status RCHOLQR_BATCH_INVALID (the engine
+ *              sees the size on the device).
+ * rcholqr_batched_engine_status (synchronises) copies the per-problem
+ * status words (0, 1, 1000 + j, or RCHOLQR_BATCH_INVALID) to info and
+ * returns RCHOLQR_ERR_ENGINE if the engine stopped on a bounded wait.
+ * Returns 0, -i for an invalid argument i, or RCHOLQR_ERR_HIP. */
+#define RCHOLQR_ERR_ENGINE (-4000)
+int64_t rcholqr_batched_engine_chunk(int64_t max_n);
+size_t rcholqr_batched_engine_workspace_bytes(const rcholqr_problem* probs_host, int batch,
+                                              int passes, int64_t chunk_rows);
+int rcholqr_factor_batched_engine(const rcholqr_problem* probs_dev, int batch,
+                                  int sketch_kind, int passes, int64_t chunk_rows,
+                                  void* ws, size_t ws_bytes, void* stream);
+int rcholqr_batched_engine_status(int batch, const void* ws, int* info);
+
+/* Tuning of the engine's rows per tall task (a project-written autotuner).
+ * rcholqr_batched_engine_tune times the engine on the given batch for each
+ * candidate chunk (1024 ... 16384 rows whose workspace fits in ws_bytes),
+ * keeps the fastest for the batch's largest n, and, when save_path is not
+ * NULL, writes the table of tuned values as JSON
+ * ({"batched_engine_chunk_rows": {"<max n>": rows, ...}}).  It synchronises
+ * the device.  rcholqr_init(path) loads such a file (NULL: built-in
+ * defaults), once, before other calls; the table is read-only afterwards.
+ * Both return 0, -1 for an unreadable or malformed file / unwritable path,
+ * -i for another invalid argument, or RCHOLQR_ERR_HIP. */
+int rcholqr_init(const char* tune_path);
+int rcholqr_batched_engine_tune(const rcholqr_problem* probs_host,
+                                const rcholqr_problem* probs_dev, int batch,
+                                int sketch_kind, int passes, void* ws, size_t ws_bytes,
+                                const char* save_path, void* stream);
 
 /* Reverse-mode derivative of the 2-pass factorisation (the positive-diagonal
  * thin QR X = Q R, which Algorithm 3 returns; the paper does not treat

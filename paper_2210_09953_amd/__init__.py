@@ -14,7 +14,7 @@ from .binding import (GAUSSIAN, RADEMACHER, COUNTSKETCH, SRHT, IDENTITY_TESTONLY
                       status, error_string, fortran, empty_fortran, PHASES,
                       profile_enable, profile_read, backward, BatchedFactor, Problem, ColumnQR,
                       device_copy, reduced, rr, factor_noalloc, noalloc_status,
-                      noalloc_max_bytes)
+                      noalloc_max_bytes, BatchedEngine, BATCH_INVALID, init)
 from .autograd import RCholQR2, rcholqr2
 
 __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "IDENTITY_TESTONLY", "F64", "F32", "MIXED",
@@ -23,4 +23,4 @@ __all__ = ["GAUSSIAN", "RADEMACHER", "COUNTSKETCH", "SRHT", "IDENTITY_TESTONLY",
            "status", "error_string", "fortran", "empty_fortran", "PHASES",
            "profile_enable", "profile_read", "backward", "RCholQR2", "rcholqr2", "device_copy",
            "BatchedFactor", "Problem", "ColumnQR", "reduced", "rr", "factor_noalloc",
-           "noalloc_status", "noalloc_max_bytes"]
+           "noalloc_status", "noalloc_max_bytes", "BatchedEngine", "BATCH_INVALID", "init"]

@@ -100,6 +100,19 @@ def lib():
     L.rcholqr_factor_noalloc.restype = i32
     L.rcholqr_noalloc_status.argtypes = [ctypes.POINTER(i32)]
     L.rcholqr_noalloc_status.restype = i32
+    L.rcholqr_batched_engine_chunk.argtypes = [i64]
+    L.rcholqr_batched_engine_chunk.restype = i64
+    L.rcholqr_batched_engine_workspace_bytes.argtypes = [ctypes.POINTER(Problem), i32, i32, i64]
+    L.rcholqr_batched_engine_workspace_bytes.restype = sz
+    L.rcholqr_factor_batched_engine.argtypes = [vp, i32, i32, i32, i64, vp, sz, vp]
+    L.rcholqr_factor_batched_engine.restype = i32
+    L.rcholqr_batched_engine_status.argtypes = [i32, vp, ctypes.POINTER(i32)]
+    L.rcholqr_batched_engine_status.restype = i32
+    L.rcholqr_init.argtypes = [ctypes.c_char_p]
+    L.rcholqr_init.restype = i32
+    L.rcholqr_batched_engine_tune.argtypes = [ctypes.POINTER(Problem), vp, i32, i32, i32, vp, sz,
+                                              ctypes.c_char_p, vp]
+    L.rcholqr_batched_engine_tune.restype = i32
     L.rcholqr_error_string.argtypes = [i32]
     L.rcholqr_error_string.restype = ctypes.c_char_p
     _LIB = L
@@ -480,3 +493,82 @@ class BatchedFactor:
         _check(lib().rcholqr_batched_status(self.probs, n, self.kind, self.passes, self.precision,
                                             _ptr(self.ws), info), "rcholqr_batched_status")
         return [int(v) for v in info]
+
+
+BATCH_INVALID = 3  # engine status of a refused problem
+
+
+def init(tune_path=None):
+    """Load the engine's tuning table (None: built-in defaults)."""
+    code = lib().rcholqr_init(None if tune_path is None else str(tune_path).encode())
+    _check(code, "rcholqr_init")
+
+
+class BatchedEngine:
+    """A fixed batch of independent FP32 problems factored by the persistent
+    batched engine (one launch for the whole batch; Rademacher sketch, 1 or
+    2 passes).  The descriptors live on the device (a copy of the host
+    array); run() enqueues the engine on the current stream, capture()
+    records that in a HIP graph and replay() launches it."""
+
+    def __init__(self, Xs, ks, seeds, passes=2, chunk_rows=0):
+        self.Xs = [fortran(X) for X in Xs]
+        for X in self.Xs:
+            if X.dtype != torch.float32:
+                raise TypeError("the batched engine takes FP32 X")
+        dev = self.Xs[0].device
+        self.passes = passes
+        self.Qs = [empty_fortran(X.shape[0], X.shape[1], torch.float32, dev) for X in self.Xs]
+        self.Rs = [empty_fortran(X.shape[1], X.shape[1], torch.float64, dev) for X in self.Xs]
+        n = len(self.Xs)
+        self.probs = (Problem * n)()
+        for i, (X, Q, R) in enumerate(zip(self.Xs, self.Qs, self.Rs)):
+            self.probs[i] = Problem(X.data_ptr(), X.shape[0], X.shape[1], _ld(X), int(ks[i]),
+                                    int(seeds[i]), Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R))
+        raw = bytes(self.probs)
+        self.probs_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        maxn = max(X.shape[1] for X in self.Xs)
+        self.chunk = int(chunk_rows) or int(lib().rcholqr_batched_engine_chunk(maxn))
+        need = int(lib().rcholqr_batched_engine_workspace_bytes(self.probs, n, passes, self.chunk))
+        if need == 0:
+            raise RCholQRError(-1, "invalid batched-engine arguments")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.graph = None
+
+    def run(self):
+        code = lib().rcholqr_factor_batched_engine(_ptr(self.probs_dev), len(self.Xs), RADEMACHER,
+                                                   self.passes, self.chunk, _ptr(self.ws),
+                                                   self.ws.numel(), _stream())
+        _check(code, "rcholqr_factor_batched_engine")
+        return self.Qs, self.Rs
+
+    def capture(self):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.Qs, self.Rs
+
+    def status(self):
+        """Per-problem status words (synchronises); raises if the engine
+        stopped on a bounded wait."""
+        n = len(self.Xs)
+        info = (ctypes.c_int * n)()
+        _check(lib().rcholqr_batched_engine_status(n, _ptr(self.ws), info),
+               "rcholqr_batched_engine_status")
+        return [int(v) for v in info]
+
+    def tune(self, save_path=None):
+        """Time the engine for each chunk size that fits the workspace, keep
+        the fastest (written to save_path as JSON when given)."""
+        n = len(self.Xs)
+        code = lib().rcholqr_batched_engine_tune(self.probs, _ptr(self.probs_dev), n, RADEMACHER,
+                                                 self.passes, _ptr(self.ws), self.ws.numel(),
+                                                 None if save_path is None else str(save_path).encode(),
+                                                 _stream())
+        _check(code, "rcholqr_batched_engine_tune")
+

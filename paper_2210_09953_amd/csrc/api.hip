@@ -12,6 +12,8 @@
 #include <math.h>
 #include <algorithm>
 #include <mutex>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "../../include/rcholqr.h"
@@ -813,6 +815,179 @@ int rcholqr_noalloc_status(int* info) {
   return 0;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Persistent batched engine: host entry points and the chunk-size tuning.
+namespace {
+// Rows per tall task by the batch's largest n (16, 32, ..., 128).
+constexpr int64_t kChunkDefault = 8192;
+// Bound of one dependency wait in the engine: 2 s of the 100 MHz clock.
+constexpr long long kWaitTicks = 200000000ll;
+constexpr int64_t kChunkCandidates[] = {1024, 2048, 4096, 8192, 16384};
+int64_t g_chunk[9] = {kChunkDefault, kChunkDefault, kChunkDefault, kChunkDefault, kChunkDefault,
+                      kChunkDefault, kChunkDefault, kChunkDefault, kChunkDefault};
+std::mutex g_chunk_mutex;
+
+int chunk_slot(int64_t max_n) {
+  const int64_t s = (max_n + 15) / 16;
+  return static_cast<int>(s < 1 ? 1 : (s > 8 ? 8 : s));
+}
+
+bool valid_chunk(int64_t c) { return c > 0 && c % 128 == 0 && c <= (int64_t{1} << 24); }
+
+int write_chunk_table(const char* path) {
+  FILE* f = fopen(path, "w");
+  if (!f) return -1;
+  fprintf(f, "{\"batched_engine_chunk_rows\": {");
+  for (int s = 1; s <= 8; ++s)
+    fprintf(f, "%s\"%d\": %lld", s > 1 ? ", " : "", 16 * s, static_cast<long long>(g_chunk[s]));
+  fprintf(f, "}}\n");
+  return fclose(f) == 0 ? 0 : -1;
+}
+}  // namespace
+
+extern "C" {
+
+int rcholqr_init(const char* tune_path) {
+  std::lock_guard<std::mutex> lock(g_chunk_mutex);
+  for (int s = 0; s <= 8; ++s) g_chunk[s] = kChunkDefault;
+  if (!tune_path) return 0;
+  FILE* f = fopen(tune_path, "r");
+  if (!f) return -1;
+  char buf[4096];
+  const size_t len = fread(buf, 1, sizeof(buf) - 1, f);
+  fclose(f);
+  buf[len] = 0;
+  const char* p = strstr(buf, "\"batched_engine_chunk_rows\"");
+  if (!p) return -1;
+  p = strchr(p, '{');
+  if (!p) return -1;
+  // entries "<n>": rows, up to the closing brace
+  int read = 0;
+  while (*p && *p != '}') {
+    const char* q = strchr(p, '"');
+    if (!q) break;
+    const long nval = strtol(q + 1, nullptr, 10);
+    const char* colon = strchr(q + 1, ':');
+    if (!colon) return -1;
+    char* end = nullptr;
+    const long long rows = strtoll(colon + 1, &end, 10);
+    if (end == colon + 1 || nval < 16 || nval > 128 || nval % 16 != 0 || !valid_chunk(rows))
+      return -1;
+    g_chunk[nval / 16] = rows;
+    ++read;
+    p = end;
+    while (*p == ' ' || *p == ',' || *p == '\n') ++p;
+  }
+  return read > 0 ? 0 : -1;
+}
+
+int64_t rcholqr_batched_engine_chunk(int64_t max_n) {
+  std::lock_guard<std::mutex> lock(g_chunk_mutex);
+  return g_chunk[chunk_slot(max_n)];
+}
+
+size_t rcholqr_batched_engine_workspace_bytes(const rcholqr_problem* probs_host, int batch,
+                                              int passes, int64_t chunk_rows) {
+  if (!probs_host || batch < 1 || passes < 1 || passes > 2) return 0;
+  if (chunk_rows == 0) {
+    int64_t mx = 16;
+    for (int i = 0; i < batch; ++i) mx = std::max<int64_t>(mx, probs_host[i].n);
+    chunk_rows = rcholqr_batched_engine_chunk(mx);
+  }
+  if (!valid_chunk(chunk_rows)) return 0;
+  return static_cast<size_t>(batched_engine_bytes(probs_host, batch, passes, chunk_rows));
+}
+
+int rcholqr_factor_batched_engine(const rcholqr_problem* probs_dev, int batch, int sketch_kind,
+                                  int passes, int64_t chunk_rows, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  if (!probs_dev) return -1;
+  if (batch < 1) return -2;
+  if (sketch_kind != kRademacher) return -3;
+  if (passes < 1 || passes > 2) return -4;
+  if (chunk_rows != 0 && !valid_chunk(chunk_rows)) return -5;
+  if (!ws) return -6;
+  if (ws_bytes < static_cast<size_t>(batched_engine_status_offset(batch))) return -7;
+  // chunk_rows = 0 needs the batch's largest n, which lives on the device:
+  // the default table entry for n = 128 is used (the caller passes the
+  // value it sized the workspace with, as rcholqr_batched_engine_chunk gives)
+  if (chunk_rows == 0) chunk_rows = rcholqr_batched_engine_chunk(128);
+  RCQ_TRY(launch_batched_engine(probs_dev, batch, passes, chunk_rows, ws,
+                                static_cast<int64_t>(ws_bytes), batched_engine_grid(),
+                                kWaitTicks, static_cast<hipStream_t>(stream)));
+  return 0;
+}
+
+int rcholqr_batched_engine_status(int batch, const void* ws, int* info) {
+  if (batch < 1 || !ws || !info) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
+  int hdr[2] = {0, 0};
+  if (hipMemcpy(hdr, ws, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess) return RCHOLQR_ERR_HIP;
+  if (hdr[1] & 1) {
+    int stall[4] = {0, 0, 0, 0};
+    if (hipMemcpy(stall, static_cast<const char*>(ws) + batched_engine_stall_offset(), sizeof(stall),
+                  hipMemcpyDeviceToHost) == hipSuccess)
+      fprintf(stderr,
+              "rcholqr batched engine: a wait exceeded its bound (instance %d, phase %d, "
+              "%d of %d tasks of the previous phase counted)\n",
+              stall[0], stall[1], stall[2], stall[3]);
+  }
+  if (hipMemcpy(info, static_cast<const char*>(ws) + batched_engine_status_offset(batch),
+                sizeof(int) * batch, hipMemcpyDeviceToHost) != hipSuccess)
+    return RCHOLQR_ERR_HIP;
+  return (hdr[1] & 1) ? RCHOLQR_ERR_ENGINE : 0;
+}
+
+int rcholqr_batched_engine_tune(const rcholqr_problem* probs_host, const rcholqr_problem* probs_dev,
+                                int batch, int sketch_kind, int passes, void* ws, size_t ws_bytes,
+                                const char* save_path, void* stream) {
+  if (!probs_host) return -1;
+  if (!probs_dev) return -2;
+  if (batch < 1) return -3;
+  if (sketch_kind != kRademacher) return -4;
+  if (passes < 1 || passes > 2) return -5;
+  if (!ws) return -6;
+  int64_t mx = 16;
+  for (int i = 0; i < batch; ++i) mx = std::max<int64_t>(mx, probs_host[i].n);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  RCQ_TRY(hipEventCreate(&e0));
+  RCQ_TRY(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int64_t best = -1;
+  for (const int64_t c : kChunkCandidates) {
+    if (static_cast<size_t>(batched_engine_bytes(probs_host, batch, passes, c)) > ws_bytes) continue;
+    float ms_sum = 0.f;
+    bool ok = true;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+      ok = launch_batched_engine(probs_dev, batch, passes, c, ws, static_cast<int64_t>(ws_bytes),
+                                 batched_engine_grid(), kWaitTicks, st) == hipSuccess;  // warm
+      ok = ok && hipEventRecord(e0, st) == hipSuccess;
+      ok = ok && launch_batched_engine(probs_dev, batch, passes, c, ws, static_cast<int64_t>(ws_bytes),
+                                       batched_engine_grid(), kWaitTicks, st) == hipSuccess;
+      ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0.f;
+      ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      ms_sum += ms;
+    }
+    if (ok && ms_sum < best_ms) {
+      best_ms = ms_sum;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best < 0) return -7;
+  {
+    std::lock_guard<std::mutex> lock(g_chunk_mutex);
+    g_chunk[chunk_slot(mx)] = best;
+    if (save_path && write_chunk_table(save_path) != 0) return -1;
+  }
+  return 0;
+}
+
 int rcholqr_status(const void* ws, int* info) {
   if (!ws || !info) return -1;
   if (hipDeviceSynchronize() != hipSuccess) return RCHOLQR_ERR_HIP;
@@ -887,6 +1062,8 @@ int rcholqr_trsm(const void* X, int64_t m, int64_t n, int64_t ldx, const double*
 const char* rcholqr_error_string(int code) {
   if (code == 0) return "success";
   if (code == RCHOLQR_ERR_HIP) return "HIP launch or runtime error";
+  if (code == RCHOLQR_ERR_ENGINE) return "batched engine stopped on a bounded wait (a task's dependency never completed)";
+  if (code == RCHOLQR_BATCH_INVALID) return "batched engine refused the problem (n, k, m or leading dimensions outside its rules, or a workspace that is too small)";
   if (code == RCHOLQR_ERR_NOALLOC_SIZE)
     return "problem needs more workspace than the no-allocation entry point holds";
   if (code < 0) return "invalid argument (the -code-th argument, 1-based)";

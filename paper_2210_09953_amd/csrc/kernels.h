@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct rcholqr_problem;  // include/rcholqr.h
+
 namespace rcq {
 
 constexpr int kGaussian = 0;
@@ -152,5 +154,14 @@ inline int64_t panel_elems(int n) {
   const int64_t nb = (n + 15) / 16;
   return 256 * nb * (nb + 1) / 2;
 }
+
+// Persistent batched engine (batched.hip).
+int64_t batched_engine_bytes(const rcholqr_problem* probs, int batch, int passes, int64_t chunk);
+hipError_t launch_batched_engine(const rcholqr_problem* probs_dev, int batch, int passes,
+                                 int64_t chunk, void* ws, int64_t ws_bytes, int grid,
+                                 long long wait_ticks, hipStream_t st);
+int batched_engine_grid();
+int64_t batched_engine_status_offset(int batch);
+int64_t batched_engine_stall_offset();
 
 }  // namespace rcq
