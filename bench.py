@@ -481,7 +481,8 @@ def main():
                     help="turn two rocprofv3 --pmc runs into profiles/traffic_<workload>.md")
     ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
                     "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg "
-                    "--no-reduced-leg --no-srht-leg --no-col-leg --no-batched-leg --copy-probe")
+                    "--no-reduced-leg --no-srht-leg --no-col-leg --no-rr-leg --no-batched-leg "
+                    "--copy-probe")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
