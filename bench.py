@@ -473,6 +473,8 @@ def main():
                     help="skip the rank-revealing RCholeskyQR figure")
     ap.add_argument("--no-batched-leg", action="store_true",
                     help="skip the 512-problem batched-engine figure")
+    ap.add_argument("--no-1m-leg", action="store_true",
+                    help="skip the mixed m = 1e6 figure (and its oracle comparison)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -482,7 +484,7 @@ def main():
     ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
                     "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg "
                     "--no-reduced-leg --no-srht-leg --no-col-leg --no-rr-leg --no-batched-leg "
-                    "--copy-probe")
+                    "--no-1m-leg --copy-probe")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
@@ -629,6 +631,29 @@ def main():
             f"{batched['value']} GB/s, HBM frac {batched['roofline']['frac']}, "
             f"worst orth {batched['worst_orth']:.2e}")
 
+    # The benchmark spec's size, m = 1e6 (n, k, kind as the value leg), where the
+    # fixed-size small steps weigh more; its Q and R are compared with the
+    # FP64 oracle in the CPU section below.
+    leg1m = None
+    X1np = Q1np = R1np = None
+    if not args.no_1m_leg and prec == "mixed" and m > 1_000_000:
+        m1m = 1_000_000
+        X1 = synth.make_x_torch(m1m, n, W["sigma"], seed=1, dtype=xdt, device="cuda")
+        ms1, ph1, Q1, R1 = time_leg(torch, rq, X1, k, kind, prec_code, args.steps, args.warmup)
+        orth1, res1 = quality(torch, X1, Q1, R1)
+        small = ph1.get("small_qr", 0.0) + ph1.get("cholesky", 0.0)
+        leg1m = {"value": round(m1m * n * xbytes / (ms1 * 1e-3) / 1e9, 2), "unit": "GB/s",
+                 "ms_per_step": round(ms1, 4), "m": m1m, "orth": orth1, "resid": res1,
+                 "phases_ms": {p: round(v, 4) for p, v in ph1.items()},
+                 "small_steps_share": round(small / ms1, 3)}
+        log(f"[bench] mixed m=1e6: {ms1:.3f} ms/step {leg1m['value']} GB/s orth={orth1:.2e} "
+            f"small steps {small:.3f} ms")
+        if not args.no_cpu:
+            X1np = np.asfortranarray(X1.double().cpu().numpy())
+            Q1np = Q1.double().cpu().numpy()
+            R1np = R1.cpu().numpy()
+        del X1, Q1, R1
+
     cpu = None
     if not args.no_cpu:
         ms_rows = min(m, 1 << 21)
@@ -641,6 +666,18 @@ def main():
                "sample": f"first {m1} rows of X (n={n}, k={k}, {W['kind']}, 2 passes, FP64), "
                          f"{t:.1f} s, status {st}"}
         log(f"[bench] cpu: {cpu}")
+        if X1np is not None:
+            # the m = 1e6 leg against the FP64 oracle on the same FP32 values
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.rcholqr(X1np, k, 1, kind, passes=2)
+            t_or = time.perf_counter() - t0
+            dR = float(np.linalg.norm(R1np - ref["R"]) / np.linalg.norm(ref["R"]))
+            dQ = float(np.linalg.norm(Q1np - ref["Q"]) / np.linalg.norm(ref["Q"]))
+            leg1m["oracle"] = {"rel_dR": dR, "rel_dQ": dQ, "status": int(ref["status"]),
+                               "seconds": round(t_or, 1)}
+            log(f"[bench] m=1e6 vs oracle: |dR|/|R| {dR:.2e} |dQ|/|Q| {dQ:.2e} ({t_or:.1f} s)")
+            del X1np, Q1np, R1np, ref
 
     out = {
         "metric": "GB/s of X factored + ||Q^T Q - I||: mixed vs FP64 RCholQR, 1 MI355X",
@@ -663,6 +700,7 @@ def main():
         "rank_revealing": rrf,
         "cpu_baseline": cpu,
         "batched": batched,
+        "mixed_1m": leg1m,
     }
     print(json.dumps(out), flush=True)
 
