@@ -410,6 +410,50 @@ def batched_leg(torch, rq, synth, steps, warmup, count=512):
     return out
 
 
+def adjoint_leg(torch, rq, synth, steps, warmup, m=1_000_000, n=128):
+    """The differentiation configuration: 2-pass forward (FP32 X, Gaussian
+    sketch, k = 3n) and the adjoint dX from dQ ~ N(0, 1) (m x n) and an
+    upper triangular dR ~ N(0, 1), the first-pass Q recomputed by the
+    backward's own kernels.  value = GB/s of X (m n 4 bytes) per
+    forward + backward."""
+    k = 3 * n
+    X = synth.make_x_torch(m, n, 1e-6, seed=2, dtype=torch.float32)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    dQ = rq.fortran(torch.randn(n, m, dtype=torch.float32, device="cuda", generator=g).T)
+    dR = torch.triu(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g))
+    ws_f = torch.empty(rq.workspace_bytes(m, n, k, rq.GAUSSIAN, 2, rq.F32), dtype=torch.uint8,
+                       device="cuda")
+    ws_b = torch.empty(int(rq.lib().rcholqr_backward_workspace_bytes(m, n, rq.F32)),
+                       dtype=torch.uint8, device="cuda")
+    fwd = lambda: rq.factor(X, k, 1, rq.GAUSSIAN, 2, rq.F32, ws=ws_f, want_factors=True)
+    Q, R, ex = fwd()
+    dX = rq.backward(X, ex["Rs"], ex["Rp"], dQ, dR, precision=rq.F32, ws=ws_b)
+    for _ in range(warmup):
+        Q, R, ex = fwd()
+        dX = rq.backward(X, ex["Rs"], ex["Rp"], dQ, dR, precision=rq.F32, dX=dX, ws=ws_b)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f = t_b = 0.0
+    for _ in range(steps):
+        e[0].record()
+        Q, R, ex = fwd()
+        e[1].record()
+        dX = rq.backward(X, ex["Rs"], ex["Rp"], dQ, dR, precision=rq.F32, dX=dX, ws=ws_b)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_f += e[0].elapsed_time(e[1])
+        t_b += e[1].elapsed_time(e[2])
+    t_f, t_b = t_f / steps, t_b / steps
+    finite = bool(torch.isfinite(dX).all().item())
+    out = {"value": round(m * n * 4 / ((t_f + t_b) * 1e-3) / 1e9, 2), "unit": "GB/s",
+           "ms_forward": round(t_f, 4), "ms_backward": round(t_b, 4), "m": m, "n": n, "k": k,
+           "sketch": "gaussian", "precision": "f32", "dX_finite": finite}
+    del X, dQ, dR, Q, R, ex, dX, ws_f, ws_b
+    torch.cuda.empty_cache()
+    return out
+
+
 def host_cpu():
     """lscpu's model, sockets, cores per socket and threads per core of this
     host, and the CPUs this process may run on (affinity)."""
@@ -475,6 +519,8 @@ def main():
                     help="skip the 512-problem batched-engine figure")
     ap.add_argument("--no-1m-leg", action="store_true",
                     help="skip the mixed m = 1e6 figure (and its oracle comparison)")
+    ap.add_argument("--no-adjoint-leg", action="store_true",
+                    help="skip the forward + adjoint figure (m = 1e6, n = 128, FP32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -484,7 +530,7 @@ def main():
     ap.add_argument("--pmc-command", default="rocprofv3 --pmc COUNTER -d DIR -o run -- "
                     "python3 bench.py --steps 2 --warmup 1 --no-cpu --no-fp64-leg "
                     "--no-reduced-leg --no-srht-leg --no-col-leg --no-rr-leg --no-batched-leg "
-                    "--no-1m-leg --copy-probe")
+                    "--no-1m-leg --no-adjoint-leg --copy-probe")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, args.summarize_pmc[0], args.summarize_pmc[1],
@@ -654,6 +700,12 @@ def main():
             R1np = R1.cpu().numpy()
         del X1, Q1, R1
 
+    adj = None
+    if not args.no_adjoint_leg:
+        adj = adjoint_leg(torch, rq, synth, args.steps, args.warmup)
+        log(f"[bench] adjoint (1e6 x 128, FP32): forward {adj['ms_forward']:.3f} ms, "
+            f"backward {adj['ms_backward']:.3f} ms, {adj['value']} GB/s")
+
     cpu = None
     if not args.no_cpu:
         ms_rows = min(m, 1 << 21)
@@ -701,6 +753,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "mixed_1m": leg1m,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 

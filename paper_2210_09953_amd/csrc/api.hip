@@ -741,13 +741,27 @@ int rcholqr_col_block(const void* Xb, int64_t m, int64_t j0, int64_t b, int64_t 
   RCQ_TRY(launch_householder(P, ki, bi, at<double>(ws, Lb.v0), at<double>(ws, Lb.beta),
                              at<double>(ws, Lb.T), S + j0 * lds, lds, at<double>(ws, Lb.Rs),
                              R + j0 + j0 * ldr, ldr, status, st));
-  // step 5: X_b into its columns of Q, then [Q_1:j0, X_b] T^{-1} in place
+  // step 5: Q_b = (X_b - Q_{1:j0} R_{1:j0,b}) R_bb^{-1}, Q_{1:j0} read and
+  // never rewritten: one pass of the tall solve over [Q_{1:j0}, X_b] with T
+  // (the identity on columns 0..j0-1, R's columns after) that takes its
+  // leading 16 s0 columns as solved.  A j0 that is not a multiple of 16
+  // shares a 16-column subpanel with X_b: X_b is copied into Q first and that
+  // subpanel solved in place (its old columns meet the identity, which
+  // reproduces them).
   char* qb = static_cast<char*>(Q) + static_cast<size_t>(j0) * ldq * esz;
-  if (static_cast<const void*>(qb) != Xb)
-    RCQ_TRY(hipMemcpy2DAsync(qb, ldq * esz, Xb, ldx * esz, m * esz, b, hipMemcpyDeviceToDevice, st));
+  const int s0 = ji / 16;
+  const void* xs = Xb;
+  int64_t ldxs = ldx;
+  if (ji % 16 != 0 || static_cast<const void*>(qb) == Xb) {
+    if (static_cast<const void*>(qb) != Xb)
+      RCQ_TRY(hipMemcpy2DAsync(qb, ldq * esz, Xb, ldx * esz, m * esz, b, hipMemcpyDeviceToDevice,
+                               st));
+    xs = static_cast<const char*>(Q) + static_cast<size_t>(16 * s0) * ldq * esz;
+    ldxs = ldq;
+  }
   RCQ_TRY(launch_col_make_t(R, ldr, ji, ni, T, st));
   RCQ_TRY(launch_make_panels(T, nt, ni, f32, pan, st));
-  RCQ_TRY(launch_trsm(Q, f32, m, ni, ldq, pan, Q, ldq, st));
+  RCQ_TRY(launch_trsm_append(xs, f32, m, ni, ldxs, pan, Q, ldq, s0, st));
   return 0;
 }
 

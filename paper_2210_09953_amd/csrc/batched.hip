@@ -45,7 +45,6 @@ namespace rcq {
 typedef unsigned int u4v_t __attribute__((ext_vector_type(4)));
 
 constexpr int kBThreads = 256;
-constexpr int kBSteps = 32;      // rows per sketch / Gram step
 constexpr int kMaxKB = 384;      // largest k the engine takes
 // X and Q are addressed with 32-bit byte offsets (buffer instructions):
 // each holds at most 2^30 elements (4 GiB) with its leading dimension.

@@ -120,6 +120,11 @@ hipError_t launch_gram_reduce(const double* gpart, const GramPlan& gp, int n, do
 // tall.hip
 hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, const void* pan,
                        void* Q, int64_t ldq, hipStream_t st);
+// Q = [Q_{1:16 s0}, X] R^{-1} where the first 16 s0 columns of Q are already
+// solved (R's leading block the identity): they are read, not written; X
+// (ld ldx) holds columns 16 s0 .. n-1; pan as for launch_trsm.
+hipError_t launch_trsm_append(const void* X, bool f32, int64_t m, int n, int64_t ldx,
+                              const void* pan, void* Q, int64_t ldq, int s0, hipStream_t st);
 hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq,
                        const GramPlan& gp, double* gpart, hipStream_t st);
 hipError_t launch_trmm(void* Q, bool f32, int64_t m, int n, int64_t ldq, const void* pan,

@@ -43,11 +43,12 @@ __device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& d, uint32
 }
 constexpr int kG3Rows = 32;  // Gram rows per stage = K of one bf16 matrix-core step
 
-template <typename T, int NB>
+template <typename T, int NB, bool SK = false>
 __global__ __launch_bounds__(256) void trsm_kernel(const T* X, int64_t m, int n, int64_t ldx,
-                                                   const T* __restrict__ pan, T* Q, int64_t ldq) {
+                                                   const T* __restrict__ pan, T* Q, int64_t ldq,
+                                                   int s0 = 0) {
   __shared__ TrsmLds<T, NB> sh;
-  trsm_block<T, NB>(X, m, n, ldx, pan, Q, ldq, blockIdx.x, sh);
+  trsm_block<T, NB, SK>(X, m, n, ldx, pan, Q, ldq, blockIdx.x, sh, s0);
 }
 
 template <typename T>
@@ -373,6 +374,12 @@ __host__ __device__ constexpr int trsm_bf3_psize(int b, bool rf) {
   return ((b + 1) / 2) * 3072 + (rf ? 3072 : 1536);
 }
 
+// SK (the column-oriented update): subpanels 0..s0-1 are already solved and
+// sit in Q; they are read from there as the operand of the later updates,
+// neither solved again nor stored.  X then points at the first column of
+// subpanel s0 (the new columns), and subpanel b >= s0 is read from its column
+// 16 (b - s0).  Without SK, s0 is ignored and X holds all n columns.
+//
 // FULL: whole tiles of 16 kTallWaves rows below m, n = 16 NB, NB >= 4 (no
 // bounds checks, so the wait counts are exact).  When NB % 4 == 0 the panel
 // ring has four slots, a tile's panels fill whole ring cycles, and each
@@ -384,11 +391,12 @@ __host__ __device__ constexpr int trsm_bf3_psize(int b, bool rf) {
 // The refinement is a separate instance (RF): both are launched, and the one
 // that does not match the panels' flags returns at once, so that the plain
 // instance keeps its registers.
-template <int NB, bool FULL, bool RF>
+template <int NB, bool FULL, bool RF, bool SK = false>
 __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* X, int64_t m, int n,
                                                        int64_t ldx,
                                                        const unsigned char* __restrict__ pan3,
-                                                       float* Q, int64_t ldq, int64_t blk0) {
+                                                       float* Q, int64_t ldq, int64_t blk0,
+                                                       int s0 = 0) {
   constexpr int NCH = (NB + 1) / 2;
   constexpr int PMAX = trsm_bf3_psize(NB - 1, RF);
   constexpr int SLOT = dma_kib(PMAX) * 1024;
@@ -423,16 +431,25 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
   const unsigned char* panv = pan3;
   const int xcol = 4 * ((lane >> 2) & 3) + (lane >> 4);
   auto load_x = [&](int64_t t, int b, int sl) {
+    // subpanel b's first column and stride (solved ones from Q under SK)
+    const float* src = X + static_cast<int64_t>(16 * b) * ldxv;
+    int64_t ld = ldxv;
+    if constexpr (SK) {
+      const bool solved = b < s0;
+      ld = solved ? ldqv : ldxv;
+      src = solved ? Q + static_cast<int64_t>(16 * b) * ldqv
+                   : X + static_cast<int64_t>(16 * (b - s0)) * ldxv;
+    }
     if (full) {
-      dma16(X + t * kTile + wave * 16 + 4 * (lane & 3) + static_cast<int64_t>(16 * b + xcol) * ldxv,
+      dma16(src + t * kTile + wave * 16 + 4 * (lane & 3) + static_cast<int64_t>(xcol) * ld,
             xslot(sl));
     } else {
       const int64_t r = t * kTile + wave * 16 + l16;
-      const float* xrow = X + (r < m ? r : m - 1);
+      const float* xrow = src + (r < m ? r : m - 1);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = 16 * b + 4 * lg + v;
-        xd[b][v] = xrow[static_cast<int64_t>(col < n ? col : n - 1) * ldxv];
+        const int col = 4 * lg + v;
+        xd[b][v] = xrow[static_cast<int64_t>(col < n - 16 * b ? col : n - 1 - 16 * b) * ld];
       }
     }
   };
@@ -490,7 +507,23 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
       if (full) {
         constexpr bool staged = (b + 1 < NB) || persist;  // at subpanel b - 1
         constexpr int d1 = staged ? dma_per_wave(trsm_bf3_psize((b + 1) % NB, RF)) + 1 : 0;
-        if (b >= 2) {
+        if (SK) {
+          // Subpanels below s0 store nothing: count the store groups of the
+          // two subpanels before b (of the previous tile, for b < 2 after
+          // the first), or of subpanel 0 for b = 1 on the first tile.
+          int ns;
+          if (b >= 2 || !first)
+            ns = static_cast<int>((b + NB - 2) % NB >= s0) + static_cast<int>((b + NB - 1) % NB >= s0);
+          else
+            ns = (b == 0) ? 0 : static_cast<int>(s0 == 0);
+          ns = __builtin_amdgcn_readfirstlane(ns);
+          if (ns == 2)
+            wait_vmcnt<d1 + 8>();
+          else if (ns == 1)
+            wait_vmcnt<d1 + 4>();
+          else
+            wait_vmcnt<d1>();
+        } else if (b >= 2) {
           wait_vmcnt<d1 + 8>();
         } else if (first) {
           wait_vmcnt<(b == 0) ? d1 : d1 + 4>();
@@ -520,81 +553,84 @@ __global__ __launch_bounds__(64 * kTallWaves) void trsm_bf3_kernel(const float* 
         for (int v = 0; v < 4; ++v) xd[b][v] = xl[64 * v];
       }
       f4 D = f4{xd[b][0], xd[b][1], xd[b][2], xd[b][3]};
-      if (nc > 0) {
-        // One chain per chunk, each from zero; products grouped by R plane:
-        // d with d, h; l with h; h with l, d, h.
-        f4 c4[NCH];
+      f4 E = D;  // a solved subpanel (SK, b < s0) as read
+      if (!(SK && b < s0)) {
+        if (nc > 0) {
+          // One chain per chunk, each from zero; products grouped by R plane:
+          // d with d, h; l with h; h with l, d, h.
+          f4 c4[NCH];
 #pragma unroll
-        for (int p = 0; p < NCH; ++p) c4[p] = f4{0.f, 0.f, 0.f, 0.f};
+          for (int p = 0; p < NCH; ++p) c4[p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tp = 1; tp < 4; ++tp) {
-          const int tpl = tp % 3;  // planes in the order d, l, h
-          bf8 tv[NCH];
+          for (int tp = 1; tp < 4; ++tp) {
+            const int tpl = tp % 3;  // planes in the order d, l, h
+            bf8 tv[NCH];
+#pragma unroll
+            for (int p = 0; p < NCH; ++p)
+              if (p < nc) tv[p] = __builtin_bit_cast(bf8, pa[(3 * p + tpl) * 64]);
+            const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
+#pragma unroll
+            for (int iq = 0; iq < 3; ++iq)
+              if (iq < nq) {
+                const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
+#pragma unroll
+                for (int p = 0; p < NCH; ++p)
+                  if (p < nc)
+                    c4[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        tv[p], __builtin_bit_cast(bf8, qb[p][qp]), c4[p], 0, 0, 0);
+              }
+          }
 #pragma unroll
           for (int p = 0; p < NCH; ++p)
-            if (p < nc) tv[p] = __builtin_bit_cast(bf8, pa[(3 * p + tpl) * 64]);
-          const int nq = (tpl == 1) ? 2 : (tpl == 2 ? 1 : 3);
-#pragma unroll
-          for (int iq = 0; iq < 3; ++iq)
-            if (iq < nq) {
-              const int qp = (tpl == 1) ? (iq == 0 ? 1 : 0) : (tpl == 2 ? 0 : 2 - iq);
-#pragma unroll
-              for (int p = 0; p < NCH; ++p)
-                if (p < nc)
-                  c4[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                      tv[p], __builtin_bit_cast(bf8, qb[p][qp]), c4[p], 0, 0, 0);
-            }
+            if (p < nc) D += c4[p];
         }
+        // Diagonal block: Q_b = Tb^T D on 16x16x16 matrix cores; D as returned
+        // is the B operand (K = 4 lg + v).
+        uint32_t dh[2], dd[2], dl[2];
+        split4(D, dh, dd, dl);
+        const uint2* pd = reinterpret_cast<const uint2*>(slot + 3072 * nc) + lane;
+        const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
+        const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
+        const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(tl, as_s4(dh), E, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dl), E, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
+        if (RF) {
+          // -Rbb^T E (smallest products first), then the residual and the
+          // correction Tb^T r from its two leading planes.
+          uint32_t fh[2], fd[2], fl[2];
+          split4(E, fh, fd, fl);
+          const s4b_t rh = __builtin_bit_cast(s4b_t, pd[192]);
+          const s4b_t rd = __builtin_bit_cast(s4b_t, pd[256]);
+          const s4b_t rl = __builtin_bit_cast(s4b_t, pd[320]);
+          f4 F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+          F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rl, as_s4(fh), F, 0, 0, 0);
+          F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fl), F, 0, 0, 0);
+          F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fh), F, 0, 0, 0);
+          F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fd), F, 0, 0, 0);
+          F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fh), F, 0, 0, 0);
+          const f4 res = D + F;
+          uint32_t gh[2], gd[2], gl[2];
+          split4(res, gh, gd, gl);
+          f4 C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(gh), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+          C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gd), C, 0, 0, 0);
+          C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gh), C, 0, 0, 0);
+          E += C;
+        }
+        float* qout = Q + row;
+        if (full) {
+          float* qo = qout + static_cast<int64_t>(4 * lg) * ldqv;
 #pragma unroll
-        for (int p = 0; p < NCH; ++p)
-          if (p < nc) D += c4[p];
-      }
-      // Diagonal block: Q_b = Tb^T D on 16x16x16 matrix cores; D as returned
-      // is the B operand (K = 4 lg + v).
-      uint32_t dh[2], dd[2], dl[2];
-      split4(D, dh, dd, dl);
-      const uint2* pd = reinterpret_cast<const uint2*>(slot + 3072 * nc) + lane;
-      const s4b_t th = __builtin_bit_cast(s4b_t, pd[0]);
-      const s4b_t td = __builtin_bit_cast(s4b_t, pd[64]);
-      const s4b_t tl = __builtin_bit_cast(s4b_t, pd[128]);
-      f4 E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(tl, as_s4(dh), E, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dl), E, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(dh), E, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dd), E, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(dh), E, 0, 0, 0);
-      if (RF) {
-        // -Rbb^T E (smallest products first), then the residual and the
-        // correction Tb^T r from its two leading planes.
-        uint32_t fh[2], fd[2], fl[2];
-        split4(E, fh, fd, fl);
-        const s4b_t rh = __builtin_bit_cast(s4b_t, pd[192]);
-        const s4b_t rd = __builtin_bit_cast(s4b_t, pd[256]);
-        const s4b_t rl = __builtin_bit_cast(s4b_t, pd[320]);
-        f4 F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fd), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rl, as_s4(fh), F, 0, 0, 0);
-        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fl), F, 0, 0, 0);
-        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rd, as_s4(fh), F, 0, 0, 0);
-        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fd), F, 0, 0, 0);
-        F = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rh, as_s4(fh), F, 0, 0, 0);
-        const f4 res = D + F;
-        uint32_t gh[2], gd[2], gl[2];
-        split4(res, gh, gd, gl);
-        f4 C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(td, as_s4(gh), f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gd), C, 0, 0, 0);
-        C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(th, as_s4(gh), C, 0, 0, 0);
-        E += C;
-      }
-      float* qout = Q + row;
-      if (full) {
-        float* qo = qout + static_cast<int64_t>(4 * lg) * ldqv;
+          for (int v = 0; v < 4; ++v) qo[static_cast<int64_t>(16 * b + v) * ldqv] = E[v];
+        } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qo[static_cast<int64_t>(16 * b + v) * ldqv] = E[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int col = 16 * b + 4 * lg + v;
-          if (row < m && col < n) qout[static_cast<int64_t>(col) * ldqv] = E[v];
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * b + 4 * lg + v;
+            if (row < m && col < n) qout[static_cast<int64_t>(col) * ldqv] = E[v];
+          }
         }
       }
       // Keep Q_b split for the later updates: words 0-1 of chunk b/2 for even
@@ -665,6 +701,65 @@ hipError_t launch_trsm(const void* X, bool f32, int64_t m, int n, int64_t ldx, c
   }
   return trsm_dispatch<double>(nb, static_cast<const double*>(X), m, n, ldx,
                                static_cast<const double*>(pan), static_cast<double*>(Q), ldq, st);
+}
+
+hipError_t launch_trsm_append(const void* Xv, bool f32, int64_t m, int n, int64_t ldx,
+                              const void* pan, void* Qv, int64_t ldq, int s0, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  const int nb = static_cast<int>(ceil_div(n, 16));
+  if (s0 < 0 || s0 >= nb) return hipErrorInvalidValue;
+  if (!f32) {
+    const unsigned grid = static_cast<unsigned>(ceil_div(m, 64 * RowBlocks<double>::value));
+    const double* X = static_cast<const double*>(Xv);
+    const double* pd = static_cast<const double*>(pan);
+    double* Q = static_cast<double*>(Qv);
+#define RCQ_SD_CASE(NBV)                                                                     \
+  case NBV:                                                                                  \
+    trsm_kernel<double, NBV, true><<<grid, 256, 0, st>>>(X, m, n, ldx, pd, Q, ldq, s0);      \
+    break;
+    switch (nb) {
+      RCQ_SD_CASE(1) RCQ_SD_CASE(2) RCQ_SD_CASE(3) RCQ_SD_CASE(4) RCQ_SD_CASE(5) RCQ_SD_CASE(6)
+      RCQ_SD_CASE(7) RCQ_SD_CASE(8) RCQ_SD_CASE(9) RCQ_SD_CASE(10) RCQ_SD_CASE(11)
+      RCQ_SD_CASE(12) RCQ_SD_CASE(13) RCQ_SD_CASE(14) RCQ_SD_CASE(15) RCQ_SD_CASE(16)
+      default: return hipErrorInvalidValue;
+    }
+#undef RCQ_SD_CASE
+    return hipGetLastError();
+  }
+  const float* X = static_cast<const float*>(Xv);
+  float* Q = static_cast<float*>(Qv);
+  // As launch_trsm's FP32 branch; the whole-tile instance also stages the
+  // solved subpanels from Q by 16-byte direct loads.
+  const int64_t tiles = ceil_div(m, 16 * kTallWaves);
+  const bool aligned = (ldx % 4) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+                       (ldq % 4) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+  const int64_t nfull = (n % 16 == 0 && nb >= 4 && aligned) ? m / (16 * kTallWaves) : 0;
+  const int64_t gfull = (nb % 4 == 0) ? std::min<int64_t>(nfull, device_cus()) : nfull;
+  const unsigned char* p3 = static_cast<const unsigned char*>(pan);
+#define RCQ_SA_RF(NBV, RFV)                                                                  \
+  do {                                                                                       \
+    if (nfull > 0)                                                                           \
+      trsm_bf3_kernel<NBV, true, RFV, true><<<static_cast<unsigned>(gfull), 64 * kTallWaves, \
+                                              0, st>>>(X, m, n, ldx, p3, Q, ldq, 0, s0);     \
+    if (tiles > nfull)                                                                       \
+      trsm_bf3_kernel<NBV, false, RFV, true><<<static_cast<unsigned>(tiles - nfull),         \
+                                               64 * kTallWaves, 0, st>>>(X, m, n, ldx, p3,   \
+                                                                         Q, ldq, nfull, s0); \
+  } while (0)
+#define RCQ_SA_CASE(NBV)   \
+  case NBV:                \
+    RCQ_SA_RF(NBV, false); \
+    RCQ_SA_RF(NBV, true);  \
+    break;
+  switch (nb) {
+    RCQ_SA_CASE(1) RCQ_SA_CASE(2) RCQ_SA_CASE(3) RCQ_SA_CASE(4) RCQ_SA_CASE(5) RCQ_SA_CASE(6)
+    RCQ_SA_CASE(7) RCQ_SA_CASE(8) RCQ_SA_CASE(9) RCQ_SA_CASE(10) RCQ_SA_CASE(11)
+    RCQ_SA_CASE(12) RCQ_SA_CASE(13) RCQ_SA_CASE(14) RCQ_SA_CASE(15) RCQ_SA_CASE(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef RCQ_SA_CASE
+#undef RCQ_SA_RF
+  return hipGetLastError();
 }
 
 template <typename T, bool FULL>

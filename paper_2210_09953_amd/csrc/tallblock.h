@@ -42,10 +42,15 @@ struct TrsmLds {
 // Rows 64 RB blk .. 64 RB blk + 64 RB - 1 of Q = X R^{-1} (trsm_kernel's
 // work for workgroup blk); all 256 threads of the calling workgroup take
 // part, and its LDS is `sh`.
-template <typename T, int NB>
+//
+// SK (the column-oriented update): panels 0..s0-1 are already solved and sit
+// in Q.  They are loaded from there straight into the operand layout of the
+// later updates and neither solved again nor stored; X then holds columns
+// 16 s0 .. n-1.  Without SK, s0 is ignored.
+template <typename T, int NB, bool SK = false>
 __device__ __forceinline__ void trsm_block(const T* X, int64_t m, int n, int64_t ldx,
                                            const T* __restrict__ pan, T* Q, int64_t ldq,
-                                           int64_t blk, TrsmLds<T, NB>& sh) {
+                                           int64_t blk, TrsmLds<T, NB>& sh, int s0 = 0) {
   typedef typename Acc4<T>::type A4;
   constexpr int RB = RowBlocks<T>::value;
   auto& tq = sh.tq;
@@ -64,18 +69,36 @@ __device__ __forceinline__ void trsm_block(const T* X, int64_t m, int n, int64_t
   const bool full = blk * 64 * RB + 64 * RB <= m && n == 16 * NB;
   T xn[RB][4];
   auto load_x = [&](int b) {
+    if constexpr (SK) {
+      if (b < s0) {
+        // a solved panel: lane group lg takes columns 4 v + lg (the operand
+        // layout qa[4 b + v])
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int64_t row = row0 + 16 * rb;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * b + 4 * v + lg;
+            xn[rb][v] = (full || row < m) ? Q[row + static_cast<int64_t>(col) * ldq] : T(0);
+          }
+        }
+        return;
+      }
+    }
+    const int cb = 16 * (SK ? b - s0 : b);  // panel b's first column in X
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int64_t row = row0 + 16 * rb;
       if (full) {
         const T* xb = X + row + static_cast<int64_t>(4 * lg) * ldx;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) xn[rb][v] = xb[static_cast<int64_t>(16 * b + v) * ldx];
+        for (int v = 0; v < 4; ++v) xn[rb][v] = xb[static_cast<int64_t>(cb + v) * ldx];
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int col = 16 * b + 4 * lg + v;
-          xn[rb][v] = (row < m && col < n) ? X[row + static_cast<int64_t>(col) * ldx] : T(0);
+          xn[rb][v] = (row < m && col < n)
+                          ? X[row + static_cast<int64_t>(cb + 4 * lg + v) * ldx] : T(0);
         }
       }
     }
@@ -87,6 +110,20 @@ __device__ __forceinline__ void trsm_block(const T* X, int64_t m, int n, int64_t
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const T* pb = pbuf[b & 1];
+    if (SK && b < s0) {
+      // already solved: into the operand registers as loaded
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qa[rb][4 * b + v] = xn[rb][v];
+      if (b + 1 < NB) {
+        panel_fetch<T, NB>(pan, b + 1, stg);
+        load_x(b + 1);
+        panel_store<T, NB>(pbuf[(b + 1) & 1], b + 1, stg);
+        __syncthreads();
+      }
+      continue;
+    }
     A4 D[RB], E[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)

@@ -33,7 +33,8 @@ def _np(t):
 
 
 @pytest.mark.parametrize("widths,kind", [((64, 64, 64, 64), 0), ((20, 7, 33, 1), 1),
-                                         ((1,) * 12, 0), ((100, 100), 3), ((50,), 2)])
+                                         ((1,) * 12, 0), ((100, 100), 3), ((50,), 2),
+                                         ((32, 48, 16), 0)])
 def test_col_blocks_f64(rq, orc, widths, kind):
     import torch
     n = sum(widths)
@@ -91,3 +92,41 @@ def test_col_block_in_place_and_errors(rq, orc):
     assert torch.equal(a.Q, b.Q) and torch.equal(a.R, b.R)
     with pytest.raises(ValueError):
         a.append(_gpu(X[:, :1]))
+
+
+@pytest.mark.parametrize("widths", [(240, 16), (96, 32, 128), (20, 7, 33, 68), (64, 64)])
+def test_col_blocks_f32_update_pass(rq, orc, widths):
+    """The FP32 step 5 reads the solved columns in the same pass that solves
+    the new ones: they stay bit for bit as they were, also when j0 is not a
+    multiple of 16 (the shared subpanel is solved in place) and when the
+    row tiles are shared out to persistent workgroups (m past 256 x 128
+    rows), and the result matches the oracle.  The last block is appended a
+    second time from inside Q (X_b already in place) with the same bits."""
+    import torch
+    n = sum(widths)
+    m, k = 70000, 3 * n
+    X32 = synth.make_x(m, n, 1e-3, seed=17, dtype=np.float32)
+    cuts = np.cumsum((0,) + widths)
+    cq = rq.ColumnQR(m, n, k, 4, rq.RADEMACHER, rq.F32)
+    prev = None
+    for i in range(len(widths)):
+        cq.append(_gpu(X32[:, cuts[i]:cuts[i + 1]]))
+        torch.cuda.synchronize()
+        if prev is not None:
+            assert np.array_equal(_np(cq.Q[:, :prev.shape[1]]), prev)
+        prev = _np(cq.Q[:, :cuts[i + 1]]).copy()
+    Q, R = _np(cq.Q).astype(np.float64), _np(cq.R)
+    X = X32.astype(np.float64)
+    ref = orc.col_rcholqr([X[:, a:b] for a, b in zip(cuts[:-1], cuts[1:])], k, 4, orc.RADEMACHER)
+    res = np.max(np.linalg.norm(X - Q @ R, axis=0) / np.linalg.norm(X, axis=0))
+    dR = np.linalg.norm(R - ref["R"]) / np.linalg.norm(ref["R"])
+    print(f"col f32 {widths}: resid {res:.2e} dR {dR:.2e}")
+    assert res <= 1e-5 and dR <= 1e-4
+    assert np.linalg.cond(Q) <= 10
+    # the last block again, with X_b already in Q's columns
+    last = cq.Q.clone()
+    cq.j = int(cuts[-2])
+    cq.Q[:, cuts[-2]:] = torch.from_numpy(X32[:, cuts[-2]:]).to("cuda")
+    cq.append(cq.Q[:, cuts[-2]:])
+    torch.cuda.synchronize()
+    assert torch.equal(cq.Q, last)
