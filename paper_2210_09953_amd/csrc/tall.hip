@@ -981,57 +981,59 @@ __global__ __launch_bounds__(64 * (CROSS ? NBB * NBB : NBB * (NBB + 1) / 2)) voi
 // loses nothing to the later, smaller steps, as it would in an FP32 running
 // sum.  The partial is written once, at the end of the split.
 //
-// One workgroup owns one set of rows and the whole upper triangle, in 64 x 64
-// tiles: two waves per off-diagonal tile (32 rows each), one wave per
-// diagonal tile (only its 10 upper 16 x 16 sub-tiles are formed), so every
-// row of Q is fetched and split exactly once and no wave holds more than 10
-// FP64 sub-tile accumulators (16 waves for n = 256, four per SIMD).  Stages of 32 rows are double buffered in LDS
-// as three bf16 planes laid out as the matrix-core operands: 16-byte chunks
-// (8 rows of one column), chunk-major with a row of chunks per 8 rows; the
-// operand reads (16 consecutive columns per lane group) and the split's
-// writes (16 consecutive columns per 16 lanes) are free of bank conflicts.
-// The next stage's loads are issued before the current stage's products.
+// One workgroup owns one set of rows and the whole upper triangle of 16 x 16
+// sub-tiles.  With NB = n / 16 column blocks, wave w owns the pair of row
+// blocks w and NB - 1 - w: sub-tiles (w, c) for c >= w and (NB - 1 - w, c)
+// for c >= NB - 1 - w, NB + 1 of them for every wave (17 FP64 accumulators,
+// 136 registers, for n = 256 in 8 waves: two waves per SIMD, so nothing
+// spills), every column block read once per wave for both rows.  Each row of
+// Q is fetched and split exactly once.  Stages of 32 rows are double
+// buffered in LDS as three bf16 planes laid out as the matrix-core operands:
+// 16-byte chunks (8 rows of one column), chunk-major with a row of chunks per
+// 8 rows; the operand reads (16 consecutive columns per lane group) and the
+// split's writes (16 consecutive columns per 16 lanes) are free of bank
+// conflicts.  The next stage's loads are issued before the current stage's
+// products.
 template <int NB64>
-struct TriGram {
-  static constexpr int kOff = NB64 * (NB64 - 1) / 2;  // off-diagonal 64 x 64 tiles
-  // Two waves per off-diagonal tile (row blocks 0-1 and 2-3: 8 sub-tiles
-  // each), one per diagonal tile (its 10 upper sub-tiles): at most 10 FP64
-  // sub-tile accumulators (80 registers) per wave, 16 waves for n = 256.
-  static constexpr int kWaves = 2 * kOff + NB64;
-  static constexpr int kAcc = 10;
+struct PairGram {
+  static constexpr int kNB = 4 * NB64;            // 16-column blocks
+  static constexpr int kWaves = kNB / 2;          // one pair of row blocks each
+  static constexpr int kAcc = kNB + 1;            // sub-tiles per wave
   static constexpr int kCols = 64 * NB64;
   // Chunk row stride (16-byte units): a multiple of 16 chunks, so that an
   // operand read (16 consecutive chunks per lane group, the four groups a
   // stride apart) is free of bank conflicts on gfx950 (a stride of 2 mod 16
   // costs 4 extra cycles per read, measured).
   static constexpr int kStr = kCols;
-  static constexpr int kBuf = 3 * 4 * kStr;            // chunks per stage buffer
-  static constexpr int kTasks = 4 * kCols;             // 8-row pieces per stage
-  static constexpr int kPer = (kTasks + 64 * kWaves - 1) / (64 * kWaves);
+  static constexpr int kBuf = 3 * 4 * kStr;       // chunks per stage buffer
+  static constexpr int kTasks = 4 * kCols;        // 8-row pieces per stage
+  static constexpr int kPer = kTasks / (64 * kWaves);
+  static_assert(kPer * 64 * kWaves == kTasks, "whole tasks per thread");
   static constexpr size_t kLds = 2 * kBuf * 16;
 };
 
+// Sub-tile t of the wave that owns row blocks W and NB - 1 - W: the row block
+// and the column block.
+template <int NB, int W>
+__device__ __forceinline__ constexpr int pg_row(int t) {
+  return t < NB - W ? W : NB - 1 - W;
+}
+template <int NB, int W>
+__device__ __forceinline__ constexpr int pg_col(int t) {
+  return t < NB - W ? W + t : (NB - 1 - W) + (t - (NB - W));
+}
+
 template <int NB64>
-__global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
+__global__ __launch_bounds__(64 * PairGram<NB64>::kWaves) void gram_bf3_kernel(
     const float* __restrict__ Q, int64_t m, int n, int64_t ldq, int64_t rows_per_split, int npg,
     double* __restrict__ gpart) {
-  typedef TriGram<NB64> G;
+  typedef PairGram<NB64> G;
+  constexpr int NB = G::kNB;
   extern __shared__ __align__(16) u4v_t qs3[];
   const int s = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const bool offd = wave < 2 * G::kOff;
-  // Off-diagonal wave: tile (ti, tj), ti < tj, row blocks 2 half, 2 half + 1.
-  // Diagonal wave: tile td.
-  int ti = 0, tj = 0;
-  for (int j = 1, c = 0; j < NB64; ++j)
-    for (int i = 0; i < j; ++i, ++c)
-      if (c == (wave >> 1)) {
-        ti = i;
-        tj = j;
-      }
-  const int half = wave & 1;
-  const int td = wave - 2 * G::kOff;
   // Workgroup s takes the 32-row stages s, s + G, s + 2G, ... (G = the
   // grid): at any time the workgroups read one contiguous band of rows.  Its
   // partial sums these stages in that order.
@@ -1041,92 +1043,85 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
   const int64_t r_end = m;
   double* dst = gpart + static_cast<int64_t>(s) * npg * npg;
 
-  // FP64 accumulators.  Off-diagonal wave: sub-tile (2 half + aa, b) at
-  // 4 aa + b.  Diagonal wave: sub-tile (a <= b) at its rank in row order.
   d4 acc[G::kAcc];
 #pragma unroll
   for (int i = 0; i < G::kAcc; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  // The empty asm pins each sum to its place in the instruction stream:
+  // otherwise the FP64 adds of a stage sink below all of its products, and
+  // every chain's FP32 result stays live until then.
   auto add_step = [](d4& a, const f4& c) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) a[v] += static_cast<double>(c[v]);
-  };
-  auto flush = [&]() {
-    if (offd) {
-      int64_t lo = (64 * ti + 32 * half + drow<float>(lg, 0)) +
-                   static_cast<int64_t>(64 * tj + l16) * npg;
-      asm volatile("" : "+v"(lo));
-      double* base = dst + lo;
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            double* p = base + (16 * aa + (drow<float>(lg, v) - drow<float>(lg, 0))) +
-                        static_cast<int64_t>(16 * b) * npg;
-            *p = acc[4 * aa + b][v];
-          }
-    } else {
-      int64_t lo = (64 * td + drow<float>(lg, 0)) + static_cast<int64_t>(64 * td + l16) * npg;
-      asm volatile("" : "+v"(lo));
-      double* base = dst + lo;
-      int idx = 0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b, ++idx)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            double* p = base + (16 * a + (drow<float>(lg, v) - drow<float>(lg, 0))) +
-                        static_cast<int64_t>(16 * b) * npg;
-            *p = acc[idx][v];
-          }
+    for (int v = 0; v < 4; ++v) {
+      double x = a[v] + static_cast<double>(c[v]);
+      asm volatile("" : "+v"(x));
+      a[v] = x;
     }
   };
 
   // Loads: task t = (column 16 (t / 64) + t % 16, rows 8 ((t / 16) % 4) ..),
   // kPer tasks per thread: lane groups of 16 write 16 consecutive chunks.
+  // Columns past n read column n - 1 and are zeroed, so that only the last
+  // stage (rows past m) takes the element-wise path: no divergent branches.
   float pre[G::kPer][8];
   const bool vec = ((ldq & 3) == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
-  auto fetch = [&](int64_t r0) {
+  const float* colp[G::kPer];  // first row of the task's 8 in row 0's stage
+  bool liveq[G::kPer];
 #pragma unroll
-    for (int q = 0; q < G::kPer; ++q) {
-      const int t = threadIdx.x + 64 * G::kWaves * q;
-      const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
-      const int64_t r = r0 + 8 * g;
-      const bool live = t < G::kTasks && c < n;
-      const float* src = Q + static_cast<int64_t>(live ? c : 0) * ldq + r;
-      if (live && vec && r + 8 <= r_end) {
-        const float4 f0 = reinterpret_cast<const float4*>(src)[0];
-        const float4 f1 = reinterpret_cast<const float4*>(src)[1];
+  for (int q = 0; q < G::kPer; ++q) {
+    const int t = threadIdx.x + 64 * G::kWaves * q;
+    const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
+    liveq[q] = c < n;
+    colp[q] = Q + static_cast<int64_t>(c < n ? c : n - 1) * ldq + 8 * g;
+  }
+  auto fetch = [&](int64_t r0) {
+    const int64_t rem = r_end - r0;  // rows left from r0 (>= 1)
+    if (vec && rem >= kG3Rows) {
+#pragma unroll
+      for (int q = 0; q < G::kPer; ++q) {
+        const float4 f0 = reinterpret_cast<const float4*>(colp[q] + r0)[0];
+        const float4 f1 = reinterpret_cast<const float4*>(colp[q] + r0)[1];
         pre[q][0] = f0.x; pre[q][1] = f0.y; pre[q][2] = f0.z; pre[q][3] = f0.w;
         pre[q][4] = f1.x; pre[q][5] = f1.y; pre[q][6] = f1.z; pre[q][7] = f1.w;
-      } else {
+      }
+    } else {
+      // the last stage (or unaligned Q): rows clamped to m - 1, then zeroed
+      const int lim = static_cast<int>(rem < kG3Rows ? rem : kG3Rows);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) pre[q][e] = (live && r + e < r_end) ? src[e] : 0.f;
+      for (int q = 0; q < G::kPer; ++q) {
+        const int t = threadIdx.x + 64 * G::kWaves * q;
+        const int g8 = 8 * ((t >> 4) & 3);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int o = g8 + e < lim ? e : lim - 1 - g8;
+          const float v = colp[q][r0 + o];
+          pre[q][e] = g8 + e < lim ? v : 0.f;
+        }
       }
     }
+#pragma unroll
+    for (int q = 0; q < G::kPer; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (!liveq[q]) pre[q][e] = 0.f;
   };
   auto stage_in = [&](u4v_t* buf) {
 #pragma unroll
     for (int q = 0; q < G::kPer; ++q) {
       const int t = threadIdx.x + 64 * G::kWaves * q;
-      if (t < G::kTasks) {
-        const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
-        uint32_t hp[8], dp[8], lp[8];
+      const int c = 16 * (t >> 6) + (t & 15), g = (t >> 4) & 3;
+      uint32_t hp[8], dp[8], lp[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) split3(pre[q][e], hp[e], dp[e], lp[e]);
-        u4v_t hv, dv, lv;
+      for (int e = 0; e < 8; ++e) split3(pre[q][e], hp[e], dp[e], lp[e]);
+      u4v_t hv, dv, lv;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          hv[w] = __builtin_amdgcn_perm(hp[2 * w + 1], hp[2 * w], 0x07060302u);
-          dv[w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
-          lv[w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
-        }
-        buf[(0 * 4 + g) * G::kStr + c] = hv;
-        buf[(1 * 4 + g) * G::kStr + c] = dv;
-        buf[(2 * 4 + g) * G::kStr + c] = lv;
+      for (int w = 0; w < 4; ++w) {
+        hv[w] = __builtin_amdgcn_perm(hp[2 * w + 1], hp[2 * w], 0x07060302u);
+        dv[w] = __builtin_amdgcn_perm(dp[2 * w + 1], dp[2 * w], 0x07060302u);
+        lv[w] = __builtin_amdgcn_perm(lp[2 * w + 1], lp[2 * w], 0x07060302u);
       }
+      buf[(0 * 4 + g) * G::kStr + c] = hv;
+      buf[(1 * 4 + g) * G::kStr + c] = dv;
+      buf[(2 * 4 + g) * G::kStr + c] = lv;
     }
   };
   // Operands of the 16 columns starting at c0: lane (l16, lg) holds rows
@@ -1144,61 +1139,50 @@ __global__ __launch_bounds__(64 * TriGram<NB64>::kWaves) void gram_bf3_kernel(
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd, c, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
   };
+  // One wave's stages, its pair of row blocks a compile-time fact (the
+  // accumulators stay in registers).
+  auto run = [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    constexpr int R0 = W, R1 = NB - 1 - W;
+    int cur = 0;
+    for (int64_t j = s; j < nstage; j += sstep) {
+      const bool more = j + sstep < nstage;
+      if (more) fetch((j + sstep) * kG3Rows);
+      const u4v_t* buf = qs3 + cur * G::kBuf;
+      const bf8 a0h = opnd(buf, 0, 16 * R0), a0d = opnd(buf, 1, 16 * R0), a0l = opnd(buf, 2, 16 * R0);
+      const bf8 a1h = opnd(buf, 0, 16 * R1), a1d = opnd(buf, 1, 16 * R1), a1l = opnd(buf, 2, 16 * R1);
+      static_for<NB - R0>([&](auto cc) {
+        constexpr int c = R0 + decltype(cc)::value;
+        // one column block in flight (bounds the live operand registers)
+        __builtin_amdgcn_sched_barrier(0);
+        const bf8 bh = c == R0 ? a0h : (c == R1 ? a1h : opnd(buf, 0, 16 * c));
+        const bf8 bd = c == R0 ? a0d : (c == R1 ? a1d : opnd(buf, 1, 16 * c));
+        const bf8 bl = c == R0 ? a0l : (c == R1 ? a1l : opnd(buf, 2, 16 * c));
+        add_step(acc[c - R0], prod6(a0h, a0d, a0l, bh, bd, bl));
+        if constexpr (c >= R1) add_step(acc[(NB - W) + (c - R1)], prod6(a1h, a1d, a1l, bh, bd, bl));
+      });
+      if (more) stage_in(qs3 + (cur ^ 1) * G::kBuf);
+      __syncthreads();
+      cur ^= 1;
+    }
+    // The split's partial: sub-tile t at rows 16 pg_row(t) + 4 lg + v,
+    // column 16 pg_col(t) + l16.
+    static_for<G::kAcc>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      double* base = dst + (16 * pg_row<NB, W>(t) + drow<float>(lg, 0)) +
+                     static_cast<int64_t>(16 * pg_col<NB, W>(t) + l16) * npg;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) base[drow<float>(lg, v) - drow<float>(lg, 0)] = acc[t][v];
+    });
+  };
   if (s < nstage) {
     fetch(static_cast<int64_t>(s) * kG3Rows);
     stage_in(qs3);
   }
   __syncthreads();
-  int cur = 0;
-  for (int64_t j = s; j < nstage; j += sstep) {
-    const bool more = j + sstep < nstage;
-    if (more) fetch((j + sstep) * kG3Rows);
-    const u4v_t* buf = qs3 + cur * G::kBuf;
-    if (offd) {
-      // The wave's two row blocks held, the four column blocks streamed.
-      bf8 ah[2], ad[2], al[2];
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa) {
-        const int c0 = 64 * ti + 32 * half + 16 * aa;
-        ah[aa] = opnd(buf, 0, c0);
-        ad[aa] = opnd(buf, 1, c0);
-        al[aa] = opnd(buf, 2, c0);
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        // one column block in flight (bounds the live operand registers)
-        __builtin_amdgcn_sched_barrier(0);
-        const bf8 bh = opnd(buf, 0, 64 * tj + 16 * b);
-        const bf8 bd = opnd(buf, 1, 64 * tj + 16 * b);
-        const bf8 bl = opnd(buf, 2, 64 * tj + 16 * b);
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa)
-          add_step(acc[4 * aa + b], prod6(ah[aa], ad[aa], al[aa], bh, bd, bl));
-      }
-    } else {
-      // Diagonal tile: sub-tile (a, b), a <= b, one column block b at a time
-      // with its row blocks a streamed from LDS.
-      const int c0 = 64 * td;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const bf8 bh = opnd(buf, 0, c0 + 16 * b);
-        const bf8 bd = opnd(buf, 1, c0 + 16 * b);
-        const bf8 bl = opnd(buf, 2, c0 + 16 * b);
-#pragma unroll
-        for (int a = 0; a <= b; ++a) {
-          const bf8 xh = (a == b) ? bh : opnd(buf, 0, c0 + 16 * a);
-          const bf8 xd = (a == b) ? bd : opnd(buf, 1, c0 + 16 * a);
-          const bf8 xl = (a == b) ? bl : opnd(buf, 2, c0 + 16 * a);
-          // rank of (a, b) in row order
-          add_step(acc[4 * a - a * (a - 1) / 2 + (b - a)], prod6(xh, xd, xl, bh, bd, bl));
-        }
-      }
-    }
-    if (more) stage_in(qs3 + (cur ^ 1) * G::kBuf);
-    __syncthreads();
-    cur ^= 1;
-  }
-  flush();
+  static_for<G::kWaves>([&](auto wc) {
+    if (wave == decltype(wc)::value) run(wc);
+  });
 }
 
 template <typename T, bool CROSS>
@@ -1226,9 +1210,9 @@ hipError_t launch_gram(const void* Q, bool f32, int64_t m, int n, int64_t ldq, c
   case NB: {                                                                                 \
     const hipError_t e = hipFuncSetAttribute(                                                \
         reinterpret_cast<const void*>(&gram_bf3_kernel<NB>),                                 \
-        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(TriGram<NB>::kLds));    \
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PairGram<NB>::kLds));   \
     if (e != hipSuccess) return e;                                                           \
-    gram_bf3_kernel<NB><<<gp.nsplit, 64 * TriGram<NB>::kWaves, TriGram<NB>::kLds, st>>>(    \
+    gram_bf3_kernel<NB><<<gp.nsplit, 64 * PairGram<NB>::kWaves, PairGram<NB>::kLds, st>>>(  \
         Qf, m, n, ldq, gp.rows_per_split, gp.npg, gpart);                                    \
     break;                                                                                   \
   }
