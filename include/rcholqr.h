@@ -66,11 +66,13 @@ enum rcholqr_sketch_kind {
  *   F32:   X, Q FP32; sketch accumulated in FP64; solves and Gram with
  *          FP32 accuracy on bf16 matrix cores (each FP32 operand split
  *          exactly into three bf16 parts, six products kept).
- *   MIXED: X, Q FP32; Rademacher or SRHT sketch computed exactly on int8
+ *   MIXED: X, Q FP32; the Rademacher sketch computed exactly on int8
  *          matrix cores (each column of X rounded to a 24-bit fixed-point
  *          value under a power-of-two scale, three byte planes times the +-1
  *          entries, integer sums folded into FP64); solves and Gram as F32.
  *          Requires RCHOLQR_RADEMACHER or RCHOLQR_SRHT.
+ * The SRHT sketch, in every precision, is formed by blocked fast
+ * Walsh-Hadamard transforms in FP64 (one pass over X).
  * In every precision the small k x n QR, the Cholesky factorisation and
  * the R' R_s product run in FP64 on the GPU (Section 5: minor operations
  * in higher precision). */

@@ -50,6 +50,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int kind, int passes, int pr
     sp.ktiles = 0;
     sp.kpad = static_cast<int>(k);
     sp.rows_per_split = m;
+  } else if (kind == kSRHT) {
+    // blocked fast transform (srht.hip), every precision
+    srht_sketch_plan(m, static_cast<int>(k), static_cast<int>(n), sp);
   } else if (prec == kPrecMixed) {
     // int8 matrix-core sketch (mixed.hip) chooses its own tiles and splits.
     mixed_sketch_plan(m, static_cast<int>(k), static_cast<int>(n), sp);

@@ -56,7 +56,13 @@ hipError_t launch_sketch_partials(const void* X, bool x_is_f32, int64_t m, int n
                                   int k, int kind, uint64_t seed, const SketchPlan& pl,
                                   double* part, uint32_t* keys, hipStream_t st);
 void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp);
-// kind: kRademacher or kSRHT (the +-1 kinds).
+// srht.hip: the SRHT sketch's partials by blocked fast Walsh-Hadamard
+// transforms (X FP32 or FP64), and its plan.
+void srht_sketch_plan(int64_t m, int k, int n, SketchPlan& sp);
+hipError_t launch_sketch_srht_partials(const void* X, bool x_is_f32, int64_t m, int n,
+                                       int64_t ldx, int k, uint64_t seed, const SketchPlan& pl,
+                                       double* part, hipStream_t st);
+// kind: kRademacher (int8 matrix cores) or kSRHT (the blocked fast transform).
 hipError_t launch_sketch_mixed(const float* X, int64_t m, int n, int64_t ldx, int k, uint64_t seed,
                                const SketchPlan& pl, double* part, double* P, int64_t ldp,
                                hipStream_t st, int kind = kRademacher);

@@ -1,5 +1,6 @@
-// mixed.hip -- Rademacher or SRHT sketch P = Theta X for FP32 X on int8 matrix
-// cores (both kinds have +-1 entries).
+// mixed.hip -- Rademacher sketch P = Theta X for FP32 X on int8 matrix cores
+// (the +-1 entries are exact in int8; the SRHT sketch takes the blocked fast
+// transform of srht.hip in every precision).
 //
 // Section 5 asks for the sketch to be computed more accurately than the
 // working precision.  Here the products Theta X are exact integer sums:
@@ -71,11 +72,11 @@ __device__ __forceinline__ float group_max(float v) {
 // rows) per stage.  NSL: quantiser task slots per thread.  FULL: the tasks
 // fill every slot of every thread (no per-slot guards) and the stage's
 // matrix-core steps are interleaved with the next stage's quantisation.
-template <int TT, int CT, int SB, int NSL, bool FULL, bool SRHT>
+template <int TT, int CT, int SB, int NSL, bool FULL>
 __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
     const float* __restrict__ X, int64_t m, int n, int64_t ldx, int k, uint64_t seed, int wt,
     int wc, int ktiles, int nh, int64_t rows_per_split, int kpad, int npad,
-    double* __restrict__ part, int srht_l) {
+    double* __restrict__ part) {
   constexpr int S = kQBlock * SB;  // rows per stage
   constexpr int KS = S / 64;       // matrix-core steps per stage
   // LDS bytes per column of a digit plane: 2 mod 16 chunks of 16 bytes, so
@@ -219,19 +220,13 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
 
   // Philox words of the stage starting at row r0 into buffer buf: draw c is
   // Theta row theta0 + c % Tg, block (r0 >> 7) + c / Tg.  The block size is a
-  // multiple of Tg, so a thread always draws row theta0 + tid % Tg: its SRHT
-  // sample (srht_l >= 0; -1 means Rademacher) is taken once.
-  constexpr bool srht = SRHT;
-  const uint64_t srow =
-      (srht && theta0 + tid % Tg < k) ? srht_row(seed, theta0 + tid % Tg, srht_l) : 0;
+  // multiple of Tg, so a thread always draws row theta0 + tid % Tg.
   auto draw = [&](int64_t r0, int buf) {
     for (int c = tid; c < Tg * SB; c += nthr) {
       const int r = c % Tg, sb = c / Tg;
       const int i = theta0 + r;
       Words w{0u, 0u, 0u, 0u};
-      if (i < k)
-        w = srht ? srht_words(seed, srow, srht_walsh(srow), (r0 >> 7) + sb)
-                 : radem_words(seed, i, (r0 >> 7) + sb);
+      if (i < k) w = radem_words(seed, i, (r0 >> 7) + sb);
       uint32_t* z = zb + buf * zb_sz + (sb * Tg + r) * kQZs;
       z[0] = w.w0;
       z[1] = w.w1;
@@ -352,10 +347,6 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
       float fq = 0.f;
       const int pr = tid % Tg, psb = tid / Tg;  // this thread's Philox draw
       PhiloxState ph;
-      // SRHT sample packed in one register: s >> 7 in bits 0..24, s & 127 in
-      // 25..31 (s < 2^32 here: the launch checks m' <= 2^32)
-      const uint32_t spk = static_cast<uint32_t>(srow >> 7) |
-                           (static_cast<uint32_t>(srow & 127u) << 25);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -373,12 +364,10 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
           } else if (ks == NSL) {
             if (j == 0) {
               const uint64_t blk = static_cast<uint64_t>((r0 + sstride) >> 7) + psb;
-              // Rademacher: words (blk, row, RADE); SRHT: the signs (blk, 0, SRHD),
-              // then the row's Walsh pattern and parity term (srht_words)
+              // words (blk, row, RADE)
               ph = PhiloxState{static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
-                               srht ? 0u : static_cast<uint32_t>(theta0 + pr),
-                               srht ? kTagSrhtD : kTagRadem, static_cast<uint32_t>(seed),
-                               static_cast<uint32_t>(seed >> 32)};
+                               static_cast<uint32_t>(theta0 + pr), kTagRadem,
+                               static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
             }
             if (j < 5) {
               philox_round(ph);
@@ -386,20 +375,10 @@ __global__ __launch_bounds__(512, 1) void sketch_i8_kernel(
             }
             if (j == 5) {
               uint32_t* z = zb + (cur ^ 1) * zb_sz + (psb * Tg + pr) * kQZs;
-              if (srht) {
-                const uint32_t blk32 = static_cast<uint32_t>(((r0 + sstride) >> 7) + psb);
-                const uint32_t shi = (__builtin_popcount(spk & 0x1FFFFFFu & blk32) & 1) ? ~0u : 0u;
-                const Words wl = srht_walsh(spk >> 25);
-                z[0] = ph.c0 ^ wl.w0 ^ shi;
-                z[1] = ph.c1 ^ wl.w1 ^ shi;
-                z[2] = ph.c2 ^ wl.w2 ^ shi;
-                z[3] = ph.c3 ^ wl.w3 ^ shi;
-              } else {
-                z[0] = ph.c0;
-                z[1] = ph.c1;
-                z[2] = ph.c2;
-                z[3] = ph.c3;
-              }
+              z[0] = ph.c0;
+              z[1] = ph.c1;
+              z[2] = ph.c2;
+              z[3] = ph.c3;
             }
           }
           if (ks + 1 < KS && j >= NG - TT) {
@@ -524,14 +503,12 @@ void mixed_sketch_plan(int64_t m, int k, int n, SketchPlan& sp) {
 hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_t ldx, int k,
                                         uint64_t seed, const SketchPlan& pl, double* part,
                                         hipStream_t st, int kind) {
+  if (kind == kSRHT) return launch_sketch_srht_partials(X, true, m, n, ldx, k, seed, pl, part, st);
+  if (kind != kRademacher) return hipErrorInvalidValue;
   const I8Plan p = i8_plan(k, n);
-  if (kind != kRademacher && kind != kSRHT) return hipErrorInvalidValue;
-  const int srht_l = (kind == kSRHT) ? srht_log2(m) : -1;
   // every thread draws one Theta row: the block is a multiple of Tg
   const int tt = p.full ? kQMainTT : 4;
   if ((64 * p.wt * p.wc) % (16 * tt * p.wt) != 0) return hipErrorInvalidValue;
-  const bool sr = kind == kSRHT;
-  if (sr && p.full && srht_l > 32) return hipErrorInvalidValue;  // X would exceed 500 GB
   if (p.ktiles != pl.ktiles || p.kpad != pl.kpad || p.npad != pl.npad ||
       (pl.rows_per_split % (kQBlock * p.sb)) != 0 || (pl.nsplit % 8) != 0 ||
       pl.rows_per_split > (int64_t{1} << 23))
@@ -539,29 +516,22 @@ hipError_t launch_sketch_mixed_partials(const float* X, int64_t m, int n, int64_
   const size_t shm = i8_lds_bytes(p);
   const dim3 grid(pl.nsplit * p.ktiles * p.nh), block(64 * p.wt * p.wc);
   hipError_t e = hipSuccess;
-#define RCQ_I8(TTV, CTV, SBV, NSLV, FV, SRV)                                                   \
+#define RCQ_I8(TTV, CTV, SBV, NSLV, FV)                                                        \
   do {                                                                                         \
-    const void* fn =                                                                           \
-        reinterpret_cast<const void*>(&sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV, SRV>);       \
+    const void* fn = reinterpret_cast<const void*>(&sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV>); \
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,                    \
                             static_cast<int>(shm));                                            \
     if (e != hipSuccess) return e;                                                             \
-    sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV, SRV><<<grid, block, shm, st>>>(                  \
+    sketch_i8_kernel<TTV, CTV, SBV, NSLV, FV><<<grid, block, shm, st>>>(                       \
         X, m, n, ldx, k, seed, p.wt, p.wc, p.ktiles, p.nh, pl.rows_per_split, pl.kpad, pl.npad, \
-        part, srht_l);                                                                         \
+        part);                                                                                 \
   } while (0)
-  if (p.full && sr)
-    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true, true);
-  else if (p.full)
-    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true, false);
-  else if (p.ct == 2 && sr)
-    RCQ_I8(4, 2, 1, 2, false, true);
+  if (p.full)
+    RCQ_I8(kQMainTT, kQMainCT, 2, 2, true);
   else if (p.ct == 2)
-    RCQ_I8(4, 2, 1, 2, false, false);
-  else if (sr)
-    RCQ_I8(4, 1, 1, 2, false, true);
+    RCQ_I8(4, 2, 1, 2, false);
   else
-    RCQ_I8(4, 1, 1, 2, false, false);
+    RCQ_I8(4, 1, 1, 2, false);
 #undef RCQ_I8
   return hipGetLastError();
 }

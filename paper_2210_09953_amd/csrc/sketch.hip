@@ -82,11 +82,8 @@ __global__ __launch_bounds__(256, 2) void sketch_dense_kernel(const TX* __restri
   d4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
-  Words rw{0u, 0u, 0u, 0u};  // Rademacher or SRHT words of this lane's Theta row
+  Words rw{0u, 0u, 0u, 0u};  // Rademacher words of this lane's Theta row
   int64_t rblk = -1;
-  const bool srht = kind == kSRHT;
-  const uint64_t srow = srht ? srht_row(seed, ibase + l16, srht_log2(m)) : 0;
-  const Words swal = srht_walsh(srow);
 
   // X prefetch: element e of thread t is row t % 16, column t / 16 + 16 e.
   const int pjj = threadIdx.x & 15, pc0 = threadIdx.x >> 4;
@@ -123,7 +120,7 @@ __global__ __launch_bounds__(256, 2) void sketch_dense_kernel(const TX* __restri
       const int ii = lane & 15, jj0 = 4 * (lane >> 4);
       const int64_t blk = r0 >> 7;
       if (blk != rblk) {
-        rw = srht ? srht_words(seed, srow, swal, blk) : radem_words(seed, ibase + ii, blk);
+        rw = radem_words(seed, ibase + ii, blk);
         rblk = blk;
       }
       const int o = static_cast<int>(r0 & 127) + jj0;
@@ -299,6 +296,7 @@ hipError_t launch_sketch_partials(const void* X, bool x_is_f32, int64_t m, int n
                                   int k, int kind, uint64_t seed, const SketchPlan& pl,
                                   double* part, uint32_t* keys, hipStream_t st) {
   hipError_t e;
+  if (kind == kSRHT) return launch_sketch_srht_partials(X, x_is_f32, m, n, ldx, k, seed, pl, part, st);
   if (kind == kCountSketch) {
     const int64_t ntile = ceil_div(m, kCsTile);
     count_prep_kernel<<<static_cast<unsigned>(ntile), kCsTile, 0, st>>>(m, k, seed, keys);

@@ -1,9 +1,11 @@
 """GPU parity of the SRHT sketch (Section 2's subsampled randomized Hadamard
-transform) against the oracle, whose sketch takes the fast Walsh-Hadamard
-route while the kernels form the entries d_j (-1)^popcount(s_i & j) on the
-fly: two computations of the same Theta.  Tolerances as for the other dense
-kinds (test_gpu_parity.py): Theta bit for bit, P within 4 m u |Theta||X|,
-the int8 path within its fixed-point rounding bound."""
+transform) against the oracle.  The oracle transforms whole columns of
+length m' with the fast Walsh-Hadamard transform; the library transforms
+256-row blocks and adds +-Y[s2] over blocks (srht.hip), and its debug export
+forms the entries d_j (-1)^popcount(s_i & j) one by one: three computations
+of the same Theta.  Tolerances: Theta bit for bit; P within the FP64 error of
+the blocked transform, (16 + blocks + 64) u |Theta||X| (8 butterfly levels,
+the sum over a range's blocks, the sum over ranges), for every precision."""
 import math
 
 import numpy as np
@@ -61,8 +63,8 @@ def test_srht_sketch_parity_f64_and_f32(rq, orc, m, n, k):
 
 @pytest.mark.parametrize("m,n,k", [(5000, 64, 192), (20000, 256, 768), (4099, 1, 3)])
 def test_srht_mixed_sketch_parity(rq, orc, m, n, k):
-    """int8 matrix cores: exact sums of the quantised X, so per column
-    ||dP_j|| <= 2 sqrt(m) 2^-21 max|X_j| (the bound of the Rademacher path)."""
+    """Mixed precision (FP32 X): at least as accurate as the Rademacher int8
+    path's bound, per column ||dP_j|| <= 2 sqrt(m) 2^-21 max|X_j|."""
     X32 = synth.make_x(m, n, 1e-5, seed=9, dtype=np.float32)
     X32 = np.asfortranarray((X32 * np.float32(10.0) ** np.linspace(-3, 3, n, dtype=np.float32))
                             .astype(np.float32))
@@ -116,11 +118,44 @@ def test_srht_rank_revealing(rq, orc):
 
 
 def test_srht_mixed_sketch_at_the_largest_k(rq, orc):
-    """k = 1024 (the library's largest) with n = 256 runs the main int8 tiles
-    with the most Theta row tiles."""
+    """k = 1024 (the library's largest) with n = 256: the most samples per
+    thread and every column group."""
     m, n, k = 6000, 256, 1024
     X32 = synth.make_x(m, n, 1e-3, seed=5, dtype=np.float32)
     P = _np(rq.sketch(_gpu(X32), k, 8, kind=rq.SRHT, precision=rq.MIXED))
     X = X32.astype(np.float64)
     err = np.linalg.norm(P - orc.sketch(orc.SRHT, X, k, 8), axis=0)
     assert np.all(err <= 2.0 * math.sqrt(m) * 2.0 ** -21 * np.abs(X).max(axis=0))
+
+
+def _blocked_bound(m, k, Xd):
+    """(16 + blocks + 64) u |Theta||X|: every |Theta| entry is 1/sqrt(k)."""
+    nb = -(-m // 256)
+    return (16 + nb + 64) * U64 * (np.abs(Xd).sum(axis=0) / math.sqrt(k))[None, :]
+
+
+@pytest.mark.parametrize("m,n,k,ld_extra", [
+    (1, 1, 3, 0),                # one row: m' = 1
+    (255, 5, 16, 0),             # one ragged block
+    (1000, 40, 100, 1),          # odd ld: element loads; three column groups
+    (70_000, 17, 300, 0),        # 17 columns, 32 samples per thread
+    (300_001, 33, 700, 0),       # 48 samples per thread, ragged last block
+    (65_536, 16, 1000, 3),       # 64 samples per thread
+    (1_048_653, 16, 768, 0),     # m' = 2^21, many row ranges
+])
+def test_srht_fast_transform_parity(rq, orc, m, n, k, ld_extra):
+    """Every precision against the oracle's FP64 full-length transform,
+    within the blocked transform's FP64 bound (far inside 4 m u)."""
+    import torch
+    X = synth.make_x(m, n, 1e-4, seed=12) if m >= n else np.ones((m, n))
+    refs = {np.float64: orc.sketch(orc.SRHT, X, k, 13),
+            np.float32: orc.sketch(orc.SRHT, X.astype(np.float32).astype(np.float64), k, 13)}
+    for dt, prec in ((np.float64, rq.F64), (np.float32, rq.F32), (np.float32, rq.MIXED)):
+        Xh = X.astype(dt)
+        buf = torch.zeros((n, m + ld_extra), dtype=torch.float64 if dt == np.float64
+                          else torch.float32, device="cuda")
+        buf[:, :m] = torch.from_numpy(np.ascontiguousarray(Xh.T)).to("cuda")
+        Xg = buf.t()[:m, :]  # column-major, ld = m + ld_extra
+        P = _np(rq.sketch(Xg, k, 13, kind=rq.SRHT, precision=prec))
+        Xd = Xh.astype(np.float64)
+        assert np.all(np.abs(P - refs[dt]) <= _blocked_bound(m, k, Xd) + 1e-300), (dt, prec)
