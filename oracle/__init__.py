@@ -411,6 +411,17 @@ def strong_rrqr(R, k, f=1.5, max_swaps=None):
     return R, perm, swaps
 
 
+def colnorms(X):
+    """Column 2-norms ||X_j||, the D of Algorithm 7.  Each column is divided
+    by its largest magnitude before squaring, so that no square overflows or
+    underflows (a plain sum of squares is Inf for entries near 1e170 and 0
+    near 1e-170); a zero column has norm 0."""
+    X = _f64(X)
+    a = np.abs(X).max(axis=0) if X.shape[0] else np.zeros(X.shape[1])
+    s = np.where(a > 0, a, 1.0)
+    return s * np.sqrt(((X / s[None, :]) ** 2).sum(axis=0))
+
+
 def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12, f=1.5):
     """Algorithm 7 on the column-normalised X (Section 4): D = column norms,
     P = (Theta X) D^{-1}, [R, Pi] = RRQR(P), rank r, Q = (X Pi_{1:r})
@@ -421,7 +432,7 @@ def rr_rcholqr(X, k, seed, kind=GAUSSIAN, tau=1e-12, f=1.5):
     (Rn: the R of the normalised sketch)."""
     X = _f64(X)
     m, n = X.shape
-    d = np.linalg.norm(X, axis=0)
+    d = colnorms(X)
     P = sketch(kind, X, k, seed) / np.where(d > 0, d, 1.0)  # a zero column stays zero
     Rn, piv = qrcp(P)
     r = rr_rank(Rn, tau)

@@ -563,6 +563,39 @@ def test_rr_rcholqr_finds_exact_rank(orc, kind):
     assert err.max() <= 1e-9
 
 
+def test_colnorms_closed_forms(orc):
+    """D of Algorithm 7: the 2-norm of each column, also where a plain sum of
+    squares overflows or underflows -- a column of two equal entries v has
+    norm sqrt(2)|v| for v = 1e200 and 1e-200, a zero column 0, and the norm
+    is homogeneous, ||c x|| = |c| ||x||, for c = 1e170, 1e-170, -3."""
+    X = np.array([[1e200, 1e-200, 0.0, 3.0], [1e200, -1e-200, 0.0, 4.0]])
+    d = orc.colnorms(X)
+    assert d[0] == pytest.approx(math.sqrt(2) * 1e200, rel=1e-15)
+    assert d[1] == pytest.approx(math.sqrt(2) * 1e-200, rel=1e-15)
+    assert d[2] == 0.0 and d[3] == pytest.approx(5.0, rel=1e-15)
+    rng = np.random.default_rng(3)
+    X0 = rng.standard_normal((1000, 6))
+    for c in (1e170, 1e-170, -3.0):
+        assert np.allclose(orc.colnorms(X0 * c), abs(c) * np.linalg.norm(X0, axis=0),
+                           rtol=2e-15, atol=0.0)
+    assert orc.colnorms(np.zeros((0, 3))).tolist() == [0.0, 0.0, 0.0]
+
+
+def test_rr_rcholqr_is_column_scale_invariant(orc):
+    """Algorithm 7 normalises X by D, so scaling columns by 1e170 and 1e-170
+    leaves the rank, the pivots and Q as they were (to rounding)."""
+    rng = np.random.default_rng(9)
+    m, n, rho, k = 4000, 16, 7, 48
+    X = np.asfortranarray(rng.standard_normal((m, rho)) @ rng.standard_normal((rho, n)))
+    sc = np.ones(n)
+    sc[0::3], sc[1::3] = 1e170, 1e-170
+    a = orc.rr_rcholqr(X, k, 3, RD, tau=1e-10)
+    b = orc.rr_rcholqr(np.asfortranarray(X * sc[None, :]), k, 3, RD, tau=1e-10)
+    assert a["rank"] == b["rank"] == rho
+    assert np.array_equal(a["piv"][:rho], b["piv"][:rho])
+    assert np.linalg.norm(a["Q"] - b["Q"]) <= 1e-12 * np.linalg.norm(a["Q"])
+
+
 def test_rr_rcholqr_full_rank_is_stable_beyond_cholesky(orc):
     """kappa = 1e14 (beyond what the Cholesky-based passes take): with a tiny
     tau every column is kept or the trailing part is below tau; Q stays
