@@ -1,6 +1,8 @@
 // rr.hip -- the steps of rank-revealing RCholeskyQR (Algorithm 7, Section 4)
 // around the shared sketch, Householder and tall-solve kernels:
-//   * column norms D of X (split partials in FP64, reduced in split order),
+//   * column norms D of X (split partials of power-of-two scaled sums of
+//     squares, so that no column overflows or underflows; reduced in split
+//     order),
 //   * the normalised sketch P D^{-1},
 //   * the rank-revealing QR of that sketch: Householder with column pivoting
 //     (largest remaining column norm, first on ties) applied to the n x n R
@@ -19,49 +21,110 @@ namespace rcq {
 
 constexpr int kRrSplits = 256;  // row splits of the column norms
 
-// part[s * n + c] = sum of X(r, c)^2 over rows r of split s (FP64); one wave
-// per column, 4 columns per workgroup.
+// Column norms without overflow or underflow: a sum of squares is kept as a
+// pair (ssq, e) meaning ssq * 4^(e - 1023), e a biased FP64 exponent.  FP64
+// entries are scaled by the power of two of the largest exponent seen so far
+// (as the scaled sums of LAPACK's norm routines, with powers of two so that
+// scaling is exact); FP32 entries square into the FP64 range unscaled
+// (e = 1023).  kEmpty marks a sum with no non-zero term.
+constexpr int kEmpty = -4096;
+
+struct Ssq {
+  double s;
+  int e;
+};
+
+__device__ __forceinline__ void ssq_add(Ssq& a, double x) {
+  const int ex = static_cast<int>((__double_as_longlong(x) >> 52) & 0x7ff);
+  if (x != 0.0) {
+    if (ex > a.e) {
+      a.s = (a.e == kEmpty) ? 0.0 : ldexp(a.s, 2 * (a.e - ex));
+      a.e = ex;
+    }
+    const double y = ldexp(x, 1023 - a.e);
+    a.s += y * y;
+  }
+}
+
+// a.s * 4^(a.e - e) for e >= a.e.
+__device__ __forceinline__ double ssq_at(const Ssq& a, int e) {
+  return (a.e == kEmpty) ? 0.0 : ldexp(a.s, 2 * (a.e - e));
+}
+
+// part[s * n + c] = the scaled sum of squares of X(r, c) over the rows r of
+// split s and epart[s * n + c] its exponent; one wave per column, 4 columns
+// per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void colnorm_partial_kernel(const T* __restrict__ X, int64_t m,
                                                               int n, int64_t ldx,
                                                               int64_t rows_per_split,
-                                                              double* __restrict__ part) {
+                                                              double* __restrict__ part,
+                                                              int* __restrict__ epart) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = blockIdx.x * 4 + wave, s = blockIdx.y;
   if (c >= n) return;
   const int64_t r0 = static_cast<int64_t>(s) * rows_per_split;
   const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
   const T* col = X + static_cast<int64_t>(c) * ldx;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  Ssq acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = Ssq{0.0, sizeof(T) == 8 ? kEmpty : 1023};
+  auto add = [&](Ssq& a, T v) {
+    if constexpr (sizeof(T) == 8) {
+      ssq_add(a, v);
+    } else {
+      const double x = static_cast<double>(v);
+      a.s += x * x;
+    }
+  };
   int64_t r = r0 + lane;
   for (; r + 192 < r1; r += 256) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double x = static_cast<double>(col[r + 64 * u]);
-      acc[u] += x * x;
-    }
+    for (int u = 0; u < 4; ++u) add(acc[u], col[r + 64 * u]);
   }
-  for (; r < r1; r += 64) {
-    const double x = static_cast<double>(col[r]);
-    acc[0] += x * x;
+  for (; r < r1; r += 64) add(acc[0], col[r]);
+  // the lane's pairs at its largest exponent, then the wave's
+  int e = acc[0].e;
+#pragma unroll
+  for (int u = 1; u < 4; ++u) e = max(e, acc[u].e);
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) t += ssq_at(acc[u], e);
+  int ew = e;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) ew = max(ew, __shfl_xor(ew, off));
+  const double tw = wave_sum(ssq_at(Ssq{t, e}, ew));
+  if (lane == 0) {
+    part[static_cast<int64_t>(s) * n + c] = tw;
+    epart[static_cast<int64_t>(s) * n + c] = ew;
   }
-  const double t = wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
-  if (lane == 0) part[static_cast<int64_t>(s) * n + c] = t;
 }
 
-// d[c] = sqrt(sum of the split partials, a fixed-order block reduction);
-// P(:, c) /= d[c] (a zero column stays zero).  One workgroup per column.
+// d[c] = the norm from the split pairs (their largest exponent, then a
+// fixed-order block reduction); P(:, c) /= d[c] (a zero column stays zero).
+// One workgroup per column.
 __global__ __launch_bounds__(256) void colnorm_scale_kernel(const double* __restrict__ part,
+                                                            const int* __restrict__ epart,
                                                             int nsplit, int n,
                                                             double* __restrict__ d,
                                                             double* __restrict__ P, int k,
                                                             int64_t ldp) {
   __shared__ double red[4];
+  __shared__ int emax[4];
   const int c = blockIdx.x, t = threadIdx.x;
+  int e = kEmpty;
+  for (int i = t; i < nsplit; i += 256) e = max(e, epart[static_cast<int64_t>(i) * n + c]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) e = max(e, __shfl_xor(e, off));
+  if ((t & 63) == 0) emax[t >> 6] = e;
+  __syncthreads();
+  e = max(max(emax[0], emax[1]), max(emax[2], emax[3]));
   double s = 0.0;
-  for (int i = t; i < nsplit; i += 256) s += part[static_cast<int64_t>(i) * n + c];
+  for (int i = t; i < nsplit; i += 256)
+    s += ssq_at(Ssq{part[static_cast<int64_t>(i) * n + c], epart[static_cast<int64_t>(i) * n + c]},
+                e);
   s = block_sum(s, red);
-  const double dc = sqrt(s);
+  const double dc = (e == kEmpty) ? 0.0 : ldexp(sqrt(s), e - 1023);
   if (t == 0) d[c] = dc;
   const double inv = (dc > 0.0) ? 1.0 / dc : 0.0;
   double* pc = P + static_cast<int64_t>(c) * ldp;
@@ -583,6 +646,7 @@ hipError_t launch_left_upper(const double* U, int64_t ldu, int r, double* R, int
 size_t rr_extra_bytes(int n) {
   const size_t nn = static_cast<size_t>(n) * n * sizeof(double);
   return static_cast<size_t>(kRrSplits) * n * sizeof(double)  // norm partials
+         + static_cast<size_t>(kRrSplits) * n * sizeof(double)  // their exponents (int)
          + n * sizeof(double)                                 // d
          + 5 * nn                                             // W, Rt, Rs, Rw, Ri
          + 256                                                // ||R||_2
@@ -594,7 +658,8 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
                            double* R, int64_t ldr, int* piv_out, int* rank_out, int* status,
                            double** Rs_out, hipStream_t st, int stage) {
   double* part = reinterpret_cast<double*>(extra);
-  double* d = part + static_cast<size_t>(kRrSplits) * n;
+  int* epart = reinterpret_cast<int*>(part + static_cast<size_t>(kRrSplits) * n);
+  double* d = part + 2 * static_cast<size_t>(kRrSplits) * n;
   double* W = d + n;
   double* Rt = W + static_cast<size_t>(n) * n;
   double* Rs = Rt + static_cast<size_t>(n) * n;
@@ -608,11 +673,11 @@ hipError_t launch_rr_steps(const void* X, bool f32, int64_t m, int n, int64_t ld
     const dim3 grid(static_cast<unsigned>(ceil_div(n, 4)), kRrSplits);
     if (f32)
       colnorm_partial_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(X), m, n, ldx,
-                                                           rows, part);
+                                                           rows, part, epart);
     else
       colnorm_partial_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(X), m, n,
-                                                            ldx, rows, part);
-    colnorm_scale_kernel<<<n, 256, 0, st>>>(part, kRrSplits, n, d, P, k, k);
+                                                            ldx, rows, part, epart);
+    colnorm_scale_kernel<<<n, 256, 0, st>>>(part, epart, kRrSplits, n, d, P, k, k);
     return hipGetLastError();
   }
   qrcp_kernel<<<1, kQcpThreads, 0, st>>>(Rp, n, W, Rt, Rw, piv_out);

@@ -71,6 +71,32 @@ def test_rr_low_rank_f64(rq, orc, kind, n, rho):
     assert np.linalg.cond(Q) <= 10
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_rr_extreme_column_scales_f64(rq, orc, kind):
+    """Columns scaled by 1e170 and 1e-170 (their squares overflow and
+    underflow FP64): the column norms take scaled sums, so the result is the
+    oracle's (whose norms are scaled too) and, Algorithm 7 normalising by
+    D, the same rank and pivots as for the unscaled matrix."""
+    m, n, rho, k = 20000, 64, 20, 192
+    X0 = _low_rank(m, n, rho, 11)
+    sc = np.ones(n)
+    sc[0::3], sc[1::3] = 1e170, 1e-170
+    X = np.asfortranarray(X0 * sc[None, :])
+    Q, R, piv, r = rq.rr(_gpu(X), k, 5, kind, tau=1e-10)
+    ref = orc.rr_rcholqr(X, k, 5, kind, tau=1e-10)
+    _, _, piv0, r0 = rq.rr(_gpu(X0), k, 5, kind, tau=1e-10)
+    assert r == ref["rank"] == int(r0) == rho
+    piv = _np(piv)
+    assert np.array_equal(piv[:r], ref["piv"][:r])
+    assert np.array_equal(piv[:r], _np(piv0)[:r])
+    Q, R = _np(Q), _np(R)
+    assert np.all(np.isfinite(Q)) and np.all(np.isfinite(R))
+    assert np.linalg.norm(Q - ref["Q"]) <= 1e-9 * np.linalg.norm(ref["Q"])
+    Rx, Rx_ref = _back_to_x_order(R, piv), _back_to_x_order(ref["R"], ref["piv"])
+    cerr = orc.colnorms(Rx - Rx_ref) / orc.colnorms(Rx_ref)  # scaled norms: no Inf
+    assert cerr.max() <= 1e-9
+
+
 def test_rr_full_rank_ill_conditioned_f64(rq, orc):
     """kappa = 1e14: Q stays well-conditioned (the unconditional stability of
     Algorithm 7) and X Pi = Q R to working accuracy on the kept columns."""
