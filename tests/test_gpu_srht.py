@@ -159,3 +159,19 @@ def test_srht_fast_transform_parity(rq, orc, m, n, k, ld_extra):
         P = _np(rq.sketch(Xg, k, 13, kind=rq.SRHT, precision=prec))
         Xd = Xh.astype(np.float64)
         assert np.all(np.abs(P - refs[dt]) <= _blocked_bound(m, k, Xd) + 1e-300), (dt, prec)
+
+
+def test_srht_full_size_sampled_columns(rq, orc):
+    """The benchmarked launch (m = 4e6, n = 256, k = 768, FP32 X, mixed
+    precision: 16 column groups, every row range): four columns of P against
+    the oracle's full-length transform of those columns alone (the sketch
+    acts on each column separately), within the blocked FP64 bound."""
+    import torch
+    m, n, k = 4_000_000, 256, 768
+    X = synth.make_x_torch(m, n, 1e-5, seed=1, dtype=torch.float32)
+    P = _np(rq.sketch(X, k, 7, kind=rq.SRHT, precision=rq.MIXED))
+    cols = [0, 17, 128, 255]
+    Xc = np.asfortranarray(X[:, cols].double().cpu().numpy())
+    del X
+    Pr = orc.sketch(orc.SRHT, Xc, k, 7)
+    assert np.all(np.abs(P[:, cols] - Pr) <= _blocked_bound(m, k, Xc) + 1e-300)
