@@ -30,13 +30,15 @@ constexpr int kFwYLd = 257;    // doubles per column of the transformed block
 constexpr int kFwDChunk = 32;  // blocks per table of d words
 
 // LDS of one workgroup.  Both block buffers are padded so that their
-// accesses are affine (immediate offsets) and free of bank conflicts: row r
-// of a column of z sits at 17 (r >> 4) + (r & 15), so 16 consecutive rows
-// (written by one lane) and rows 16 apart (read by 16 lanes) both spread
-// over the banks; y is column-major with an odd stride, so that the 16
-// columns of one sample's row, read by 16 lanes, fall in distinct banks
-// (17-double rows, conflict-free for the writes, measured 0.43 ms slower:
-// two samples of a half-wave then collide far more often).
+// accesses are affine (immediate offsets).  Row r of a column of z sits at
+// 17 (r >> 4) + (r & 15), so 16 consecutive rows (written by one lane) and
+// rows 16 apart (read by 16 lanes) both spread over the banks without
+// conflicts.  y is column-major with an odd stride, so that the 16 columns
+// of one sample's row, read by 16 lanes, fall in distinct banks; the two
+// samples of a half-wave can still share banks, and its writes pair two
+// columns on one bank group.  (17-double rows, conflict-free for the
+// writes, measured 0.43 ms slower: two samples of a half-wave then collide
+// far more often.)
 struct FwhtLds {
   double z[kFwC][kFwZLd];        // first-stage results
   double y[kFwC][kFwYLd];        // transformed block
