@@ -23,20 +23,28 @@ namespace rcq {
 // One wave per panel column, its rows (lane + 64 q) in registers.  Step j:
 // the waves right of j apply reflector j (read from LDS) to their column,
 // and wave j + 1 then forms reflector j + 1 from its updated column and
-// publishes it in LDS: one barrier per reflector.
+// publishes it in LDS: one barrier per reflector.  The wave that forms the
+// next reflector raises its issue priority for the step and the others wait
+// briefly before reading the reflector, as their updates are off the
+// critical path.  Reflector j sits at vsh[j Ls + r] for
+// all 64 RPL rows (zero from row L on, so no reads are guarded), with the
+// stride Ls = 4 (mod 32) doubles so that the 16 reflectors' entries of one
+// row fall in distinct banks for the V^T V step.
 // RPL = rows per lane (L <= 64 RPL).
+__host__ __device__ constexpr int hh_panel_ld(int rpl) { return 64 * rpl + 4; }
 template <int RPL>
 __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, int k, int n,
                                                         int p0, double* __restrict__ v0g,
                                                         double* __restrict__ betag,
                                                         double* __restrict__ Tp) {
-  extern __shared__ double vsh[];  // [16][L]: reflector j = vsh[j L + r] (0 above row j)
+  extern __shared__ double vsh[];  // [16][Ls]: reflector j = vsh[j Ls + r] (0 above row j)
   __shared__ double sc[kHhPanel][3];
   __shared__ double y[kHhPanel][kHhPanel];
   __shared__ double ypart[8][kHhPanel][kHhPanel + 1];
   const int L = k - p0;
+  constexpr int Ls = hh_panel_ld(RPL);
   const int nbp = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = wave_index(), lane = tid & 63;
   const bool own = wave < nbp;
   double xr[RPL];
 #pragma unroll
@@ -46,12 +54,10 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   }
   // Wave j: reflector from its column (rows >= j), diagonal becomes alpha.
   auto reflect = [&](int j) {
-    double tq[4] = {0.0, 0.0, 0.0, 0.0};
+    // rows >= L hold zeros; rows above j are all in q = 0 (j < 16)
+    double tq[4] = {lane > j ? xr[0] * xr[0] : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const int r = lane + 64 * q;
-      if (r > j && r < L) tq[q & 3] += xr[q] * xr[q];
-    }
+    for (int q = 1; q < RPL; ++q) tq[q & 3] += xr[q] * xr[q];
     const double t = wave_sum((tq[0] + tq[1]) + (tq[2] + tq[3]));
     const double x0 = read_lane(xr[0], j);  // j < 16: row j is lane j, q = 0
     const double nrm = sqrt(x0 * x0 + t);
@@ -59,11 +65,9 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
     const double v0 = x0 - alpha;
     const double vtv = v0 * v0 + t;
     const double beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+    vsh[j * Ls + lane] = (lane < j) ? 0.0 : ((lane == j) ? v0 : xr[0]);
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const int r = lane + 64 * q;
-      if (r < L) vsh[j * L + r] = (r < j) ? 0.0 : ((r == j) ? v0 : xr[q]);
-    }
+    for (int q = 1; q < RPL; ++q) vsh[j * Ls + lane + 64 * q] = xr[q];
     if (lane == j) xr[0] = alpha;
     if (lane == 0) {
       sc[j][0] = alpha;
@@ -75,20 +79,27 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   __syncthreads();
   for (int j = 0; j < nbp; ++j) {
     if (wave > j && own) {
-      const double* vj = vsh + j * L;
+      const bool next = wave == j + 1;
+      if (next)
+        __builtin_amdgcn_s_setprio(2);
+      else
+        __builtin_amdgcn_s_sleep(2);  // its reads of reflector j go first
+      const double* vj = vsh + j * Ls;
       double wq[4] = {0.0, 0.0, 0.0, 0.0};
       double vr[RPL];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        const int r = lane + 64 * q;
-        vr[q] = (r < L) ? vj[r] : 0.0;
+        vr[q] = vj[lane + 64 * q];
         wq[q & 3] += vr[q] * xr[q];
       }
       const double w = wave_sum((wq[0] + wq[1]) + (wq[2] + wq[3]));
       const double f = sc[j][2] * w;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) xr[q] -= f * vr[q];
-      if (wave == j + 1) reflect(j + 1);
+      if (next) {
+        reflect(j + 1);
+        __builtin_amdgcn_s_setprio(0);
+      }
     }
     __syncthreads();
   }
@@ -102,7 +113,7 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
     d4 yp = d4{0.0, 0.0, 0.0, 0.0};
     for (int r0 = rb; r0 < rb + chunk; r0 += 4) {
       const int r = r0 + lg;
-      const double av = (r < L && l16 < nbp) ? vsh[l16 * L + r] : 0.0;
+      const double av = (r < L && l16 < nbp) ? vsh[l16 * Ls + r] : 0.0;
       yp = mfma16x16x4(av, av, yp);
     }
     // waves 8..15 hand their partials to waves 0..7 (LDS for 8 partials)
@@ -160,84 +171,123 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
 
 // M(p0:k, c_begin + 16 blockIdx.x + 0..15) <- (I - V T' V^T) M(...) with
 // T' = T^T (trans = 1, factorisation) or T (trans = 0, forming S).  One
-// workgroup of 16 waves per 16-column block, wave c for column c: it loads
-// its column's rows (lane + 64 q) and reflector column c's rows into
-// registers up front, the reflectors V (L x 16, L = k - p0) go to LDS (rows
-// of 16, padded to 18), W = V^T M is summed per lane and across the wave,
-// Y = T' W is formed redundantly by the lanes, and M -= V Y is applied in
-// registers and stored.
-constexpr int kHuLd = 18;  // LDS row stride of V (doubles)
-
-template <int RPL>
+// workgroup of 16 waves per 16-column block; the L = k - p0 rows go in tiles
+// of 16, tile g to wave g % 16 (TPW tiles per wave, L <= 256 TPW).  All on
+// FP64 matrix cores: each wave sums W_w = V(rows_w, :)^T M(rows_w, :) over
+// its tiles, the 16 partials are added in LDS in wave order, every wave forms
+// Y = T' W and then M(rows_w, :) - V(rows_w, :) Y, with the M values it read
+// for the first product kept in registers as the accumulator.  V is read
+// from A (its tail below the diagonal) and v0[] (its leading entries).
+// A wave reads and writes its 16 x 16 tiles of M and V four columns per
+// instruction, each column's 16 rows a full 128-byte line (the operand
+// layouts would touch 16 lines per instruction), and turns them into
+// operands and back through its own LDS buffer.
+constexpr int kHuLd = kHhPanel + 1;  // LDS row stride (doubles) of tiles and partials
+template <int TPW>
 __global__ __launch_bounds__(1024) void hh_update_kernel(const double* __restrict__ A, int k,
                                                          int n, int p0, const double* __restrict__ v0g,
                                                          const double* __restrict__ Tp, int trans,
                                                          double* __restrict__ M, int64_t ldm,
                                                          int c_begin, int c_end) {
-  extern __shared__ double vs[];  // [L][kHuLd]
-  __shared__ double ts[kHhPanel * kHhPanel];  // T' (row i, column l) at ts[16 i + l]
+  __shared__ double wp[16][kHhPanel][kHuLd];
+  __shared__ double wsum[kHhPanel][kHuLd];
+  __shared__ double tiles[16][2][kHhPanel][kHuLd];  // per wave: M, V tile as [column][row]
   const int L = k - p0;
-  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nref = (n - p0 < kHhPanel) ? n - p0 : kHhPanel;  // reflectors of the panel
+  const int wave = wave_index(), lane = threadIdx.x & 63, l16 = lane & 15, lg = lane >> 4;
+  const int cb = c_begin + kHhPanel * blockIdx.x;
+  // Tile loads: load q reads column 4 q + lc, row lr.  Every address is
+  // clamped into range and issued unconditionally, so that a wave's loads
+  // are in flight together (a select on a loaded value becomes an
+  // exec-masked branch holding the load, and a wait for it); V's structure
+  // (zero above row i, v0[i] on it, the stored tail below) is applied by 0/1
+  // factors (inputs are finite; a non-finite one is reported by the status
+  // word).  M's clamped rows and columns need no mask: V is zero on those
+  // rows and such outputs are never stored.
+  const int lr = lane & 15, lc = lane >> 4;
+  int64_t mcol[4], vcol[4];
+  double v0q[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = 4 * q + lc, mc = cb + c, ic = c < nref ? c : nref - 1;
+    mcol[q] = static_cast<int64_t>(mc < c_end ? mc : c_end - 1) * ldm;
+    vcol[q] = static_cast<int64_t>(p0 + ic) * k;
+    v0q[q] = v0g[p0 + ic];
+  }
+  auto load_tile = [&](int t, double* mld, double* vld) {
+    const int r = 16 * (wave + 16 * t) + lr, rc = p0 + (r < L ? r : L - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * q + lc;
+      const bool ok = r < L && c < nref;
+      mld[q] = M[rc + mcol[q]];
+      vld[q] = A[rc + vcol[q]] * ((ok && r > c) ? 1.0 : 0.0) + v0q[q] * ((ok && r == c) ? 1.0 : 0.0);
+    }
+  };
+  double (*mt)[kHuLd] = tiles[wave][0];
+  double (*vt)[kHuLd] = tiles[wave][1];
+  double mreg[TPW][4], va[TPW][4];
+  d4 w = d4{0.0, 0.0, 0.0, 0.0};
+  double mld[4], vld[4];
+  load_tile(0, mld, vld);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      mt[4 * q + lc][lr] = mld[q];
+      vt[4 * q + lc][lr] = vld[q];
+    }
+    if (t + 1 < TPW) load_tile(t + 1, mld, vld);
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      // A(i, kk) = V(r0 + kk, i), B(kk, j) = M(r0 + kk, j), r0 = 16 g + 4 s;
+      // and the second product's A(rr, kk) = -V(16 g + rr, 4 s + kk)
+      mreg[t][s] = mt[l16][4 * s + lg];
+      w = mfma16x16x4(vt[l16][4 * s + lg], mreg[t][s], w);
+      va[t][s] = -vt[4 * s + lg][l16];
+    }
+    wave_sync();
+  }
+  double ta[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int l = 4 * s + lg;
+    ta[s] = trans ? Tp[l + kHhPanel * l16] : Tp[l16 + kHhPanel * l];  // T'(l16, l)
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) wp[wave][drow<double>(lg, v)][l16] = w[v];
+  __syncthreads();
   if (threadIdx.x < kHhPanel * kHhPanel) {
-    const int i = threadIdx.x >> 4, l = threadIdx.x & 15;
-    ts[threadIdx.x] = trans ? Tp[l + kHhPanel * i] : Tp[i + kHhPanel * l];
-  }
-  const int col = c_begin + kHhPanel * blockIdx.x + c;
-  const bool live = col < c_end;
-  const bool vlive = p0 + c < n;
-  const double v0c = vlive ? v0g[p0 + c] : 0.0;
-  double mq[RPL], vq[RPL];
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int r = lane + 64 * q;
-    mq[q] = (r < L && live) ? M[(p0 + r) + static_cast<int64_t>(col) * ldm] : 0.0;
-    vq[q] = (r < L && vlive && r > c) ? A[(p0 + r) + static_cast<int64_t>(p0 + c) * k] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int r = lane + 64 * q;
-    if (r < L) vs[r * kHuLd + c] = (r == c) ? v0c : vq[q];
+    const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+    double sum = 0.0;
+    for (int ww = 0; ww < 16; ++ww) sum += wp[ww][i][j];
+    wsum[i][j] = sum;
   }
   __syncthreads();
-  double w[kHhPanel];
+  // Y = T' W; element v of y holds Y(lg + 4 v, l16), which is the B operand
+  // of step v of the second product.
+  d4 y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < kHhPanel; ++i) w[i] = 0.0;
+  for (int s = 0; s < 4; ++s) y = mfma16x16x4(ta[s], wsum[4 * s + lg][l16], y);
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int r = lane + 64 * q;
-    if (r < L) {
-      const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
+  for (int t = 0; t < TPW; ++t) {
+    // C(rr, j) = M(16 g + rr, j): element v (row lg + 4 v) was read in step v
+    d4 acc = d4{mreg[t][0], mreg[t][1], mreg[t][2], mreg[t][3]};
 #pragma unroll
-      for (int j = 0; j < kHhPanel / 2; ++j) {
-        const double2 v = vr[j];
-        w[2 * j] += v.x * mq[q];
-        w[2 * j + 1] += v.y * mq[q];
-      }
+    for (int s = 0; s < 4; ++s) acc = mfma16x16x4(va[t][s], y[s], acc);
+    // back to the load layout through the wave's tile buffer: full-line stores
+#pragma unroll
+    for (int v = 0; v < 4; ++v) mt[l16][drow<double>(lg, v)] = acc[v];
+    wave_sync();
+    const int r = 16 * (wave + 16 * t) + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = cb + 4 * q + lc;
+      const double val = mt[4 * q + lc][lr];
+      if (r < L && col < c_end) M[(p0 + r) + static_cast<int64_t>(col) * ldm] = val;
     }
-  }
-#pragma unroll
-  for (int i = 0; i < kHhPanel; ++i) w[i] = wave_sum(w[i]);
-  double y[kHhPanel];
-#pragma unroll
-  for (int i = 0; i < kHhPanel; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int l = 0; l < kHhPanel; ++l) t += ts[kHhPanel * i + l] * w[l];
-    y[i] = t;
-  }
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int r = lane + 64 * q;
-    if (r < L && live) {
-      const double2* vr = reinterpret_cast<const double2*>(vs + r * kHuLd);
-      double t = 0.0;
-#pragma unroll
-      for (int j = 0; j < kHhPanel / 2; ++j) {
-        const double2 v = vr[j];
-        t += v.x * y[2 * j] + v.y * y[2 * j + 1];
-      }
-      M[(p0 + r) + static_cast<int64_t>(col) * ldm] = mq[q] - t;
-    }
+    wave_sync();
   }
 }
 
@@ -333,23 +383,15 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
                               double* S, int64_t lds, double* Rs, double* R, int64_t ldr,
                               int* status, hipStream_t st) {
   hipError_t e;
-  const size_t shm = static_cast<size_t>(kHhPanel) * k * sizeof(double);
   static bool attr_done = false;
   if (!attr_done) {
     const void* pk[] = {reinterpret_cast<const void*>(hh_panel_kernel<4>),
                         reinterpret_cast<const void*>(hh_panel_kernel<8>),
                         reinterpret_cast<const void*>(hh_panel_kernel<12>),
                         reinterpret_cast<const void*>(hh_panel_kernel<16>)};
-    const void* uk[] = {reinterpret_cast<const void*>(hh_update_kernel<4>),
-                        reinterpret_cast<const void*>(hh_update_kernel<8>),
-                        reinterpret_cast<const void*>(hh_update_kernel<12>),
-                        reinterpret_cast<const void*>(hh_update_kernel<16>)};
     for (int i = 0; i < 4; ++i) {
       e = hipFuncSetAttribute(pk[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(kHhPanel * kMaxK * sizeof(double)));
-      if (e != hipSuccess) return e;
-      e = hipFuncSetAttribute(uk[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(kHuLd * kMaxK * sizeof(double)));
+                              static_cast<int>(kHhPanel * hh_panel_ld(16) * sizeof(double)));
       if (e != hipSuccess) return e;
     }
     attr_done = true;
@@ -381,13 +423,13 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
   } while (0)
   for (int p = 0; p < npan; ++p) {
     const int p0 = p * kHhPanel;
-    RCQ_HH_RPL(k - p0, (hh_panel_kernel<RPL><<<1, 1024, shm, st>>>(
+    RCQ_HH_RPL(k - p0, (hh_panel_kernel<RPL><<<1, 1024, kHhPanel * hh_panel_ld(RPL) * sizeof(double), st>>>(
                            A, k, n, p0, V0, beta, T + p * kHhPanel * kHhPanel)));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int cstart = p0 + kHhPanel;
     if (cstart < n) {
       const int nblk = static_cast<int>(ceil_div(n - cstart, kHhPanel));
-      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL><<<nblk, 1024, kHuLd * (k - p0) * sizeof(double), st>>>(
+      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL / 4><<<nblk, 1024, 0, st>>>(
                              A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 1, A, k, cstart, n)));
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -399,7 +441,7 @@ hipError_t launch_householder(double* A, int k, int n, double* V0, double* beta,
     for (int p = npan - 1; p >= 0; --p) {
       const int p0 = p * kHhPanel;
       const int nblk = static_cast<int>(ceil_div(n - p0, kHhPanel));
-      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL><<<nblk, 1024, kHuLd * (k - p0) * sizeof(double), st>>>(
+      RCQ_HH_RPL(k - p0, (hh_update_kernel<RPL / 4><<<nblk, 1024, 0, st>>>(
                              A, k, n, p0, V0, T + p * kHhPanel * kHhPanel, 0, S, lds, p0, n)));
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
