@@ -476,8 +476,9 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
   __shared__ double dgb[16][17];        // diagonal tile being factored
   __shared__ double wl[16][17];         // W^T, W = R_PP^{-1}
   __shared__ double rp[16][kMaxN + 1];  // row panel R_P,: (16 x n)
+  __shared__ double xt[kChWaves][16][17];  // per wave: a tile on its way to or from G
   __shared__ int fail;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = wave_index(), lane = tid & 63;
   const int l16 = lane & 15, lg = lane >> 4;
   const int nt = (n + 15) / 16;
   const int ntile = nt * (nt + 1) / 2;
@@ -501,24 +502,39 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
     tj = (code >> 8) & 255;
     return (code >> 16) == 0;
   };
+  // Tiles move between G and the accumulators through the wave's LDS tile
+  // xt[column][row]: a load or store covers four columns of 16 rows (full
+  // 128-byte lines), where the accumulator layout would touch 16 lines.
+  // Loads come from clamped addresses in the upper triangle (an element
+  // below the diagonal reads its mirror image), unconditionally and with the
+  // mask applied by 0/1 factors, so that they are all in flight together (a
+  // select on a loaded value is compiled into a branch and a wait per load).
+  // Padding beyond n is the identity.
+  double (*xw)[17] = xt[wave];
+  auto load_tile = [&](int u, double* x) {
+    int ti, tj;
+    const bool live = decode(u, ti, tj);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * ti + l16, c = 16 * tj + 4 * q + lg;
+      const int rc = r < n ? r : n - 1, cc = c < n ? c : n - 1;
+      const bool inb = r < n && c < n;
+      const double g = G[(rc < cc ? rc : cc) + static_cast<int64_t>(rc < cc ? cc : rc) * ldg];
+      x[q] = g * ((live && inb && r <= c) ? 1.0 : 0.0) + ((live && !inb && r == c) ? 1.0 : 0.0);
+    }
+  };
   d4 acc[kChPerWave];
+  double xl[4];
+  load_tile(0, xl);
 #pragma unroll
   for (int u = 0; u < kChPerWave; ++u) {
-    const int t = wave + kChWaves * u;
-    int ti, tj;
-    decode(u, ti, tj);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
-      double x = 0.0;
-      if (t < ntile) {
-        if (r < n && c < n)
-          x = (r <= c) ? G[r + static_cast<int64_t>(c) * ldg] : 0.0;
-        else
-          x = (r == c) ? 1.0 : 0.0;
-      }
-      acc[u][v] = x;
-    }
+    for (int q = 0; q < 4; ++q) xw[4 * q + lg][l16] = xl[q];
+    if (u + 1 < kChPerWave) load_tile(u + 1, xl);
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = xw[l16][drow<double>(lg, v)];
+    wave_sync();
   }
   for (int P = 0; P < nt; ++P) {
     // 1. the diagonal tile to LDS (its owner), then wave 0 factors it.
@@ -545,29 +561,23 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
         const double d = read_lane(col[j], j);
         const bool ok = (d > 0.0) && isfinite(d);
         // 1 / sqrt(d) from the hardware estimate and two Newton steps
-        // (y <- y (3/2 - d y^2 / 2), each squaring the relative error), then
-        // sqrt(d) = d / sqrt(d): a few dependent FMAs instead of a correctly
-        // rounded square root and division on this serial chain.
+        // (y <- y (3/2 - d y^2 / 2), each squaring the relative error): a
+        // few dependent FMAs instead of a correctly rounded square root and
+        // division on this serial chain.
         const double dd = ok ? d : 1.0;
         const double hd = 0.5 * dd;
         double ri = __builtin_amdgcn_rsq(dd);
         ri *= __builtin_fma(-hd, ri * ri, 1.5);
         ri *= __builtin_fma(-hd, ri * ri, 1.5);
-        const double r = dd * ri;
         if (!ok && lane == 0 && fail == 0 && 16 * P + j < n) fail = 16 * P + j + 1;
-        // row j: R(j, c) = A(j, c) / r for c > j; the identity part is scaled whole
-        if (apart) {
-          if (c == j) col[j] = r;
-          else if (c > j) col[j] *= ri;
-        } else {
-          col[j] *= ri;
-        }
-        // rows i > j: A(i, c) -= R(j, i) R(j, c) (c >= i in the tile part)
+        // row j: R(j, c) = A(j, c) / sqrt(d), lane j's own entry giving
+        // d / sqrt(d) = sqrt(d); the identity part is scaled whole.  Rows i > j:
+        // A(i, c) -= R(j, i) R(j, c).  Only entries on or above the diagonal
+        // are ever read (pivots and R(j, i) with j < i), so the tile part's
+        // lanes update below the diagonal too instead of masking.
+        col[j] *= ri;
 #pragma unroll
-        for (int i = j + 1; i < 16; ++i) {
-          const double rji = read_lane(col[j], i);  // R(j, i) sits in lane i
-          if (!apart || i <= c) col[i] -= rji * col[j];
-        }
+        for (int i = j + 1; i < 16; ++i) col[i] -= read_lane(col[j], i) * col[j];
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -622,10 +632,15 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
       int ti, tj;
       if (!decode(u, ti, tj)) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * ti + drow<double>(lg, v), c = 16 * tj + l16;
-        if (r < n && c < n && r <= c) G[r + static_cast<int64_t>(c) * ldg] = acc[u][v];
+      for (int v = 0; v < 4; ++v) xw[l16][drow<double>(lg, v)] = acc[u][v];
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + l16, c = 16 * tj + 4 * q + lg;
+        const double x = xw[4 * q + lg][l16];
+        if (r < n && c < n && r <= c) G[r + static_cast<int64_t>(c) * ldg] = x;
       }
+      wave_sync();
     }
   }
   if (tid == 0 && fail) atomicCAS(status, 0, 1000 + fail - 1);
