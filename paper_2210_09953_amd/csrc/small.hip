@@ -556,9 +556,10 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
       double col[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) col[i] = apart ? dgb[i][c] : ((i == c) ? 1.0 : 0.0);
+      double dn = read_lane(col[0], 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double d = read_lane(col[j], j);
+        const double d = dn;
         const bool ok = (d > 0.0) && isfinite(d);
         // 1 / sqrt(d) from the hardware estimate and two Newton steps
         // (y <- y (3/2 - d y^2 / 2), each squaring the relative error): a
@@ -576,8 +577,9 @@ __global__ __launch_bounds__(64 * kChWaves) void chol_kernel(double* __restrict_
         // are ever read (pivots and R(j, i) with j < i), so the tile part's
         // lanes update below the diagonal too instead of masking.
         col[j] *= ri;
+        if (j + 1 < 16) dn = read_lane(__builtin_fma(-col[j], col[j], col[j + 1]), j + 1);
 #pragma unroll
-        for (int i = j + 1; i < 16; ++i) col[i] -= read_lane(col[j], i) * col[j];
+        for (int i = j + 1; i < 16; ++i) col[i] = __builtin_fma(-read_lane(col[j], i), col[j], col[i]);
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -758,11 +760,27 @@ __global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* 
                                                                   int64_t ldr, int n,
                                                                   unsigned char* __restrict__ pan3,
                                                                   int* __restrict__ flags) {
+  __shared__ double rb[16][17];  // the diagonal block (identity past n)
   __shared__ double tb[16][17];
   __shared__ double amp[16];
   const int b = blockIdx.x, lane = threadIdx.x;
   const int l16 = lane & 15, lg = lane >> 4;
   const int c0 = 16 * b;
+  // Every global load is issued unconditionally from a clamped in-range
+  // address with its mask applied afterwards by 0/1 factors, so that a
+  // lane's loads are in flight together (a select on a loaded value is
+  // compiled into a branch and a wait per load); the serial steps below
+  // then read the block from LDS.
+  auto rat = [&](int r, int c) -> double {
+    return R[(r < n ? r : n - 1) + static_cast<int64_t>(c < n ? c : n - 1) * ldr];
+  };
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * lg + e, j = l16;
+    const bool in = c0 + j < n && i <= j;
+    rb[i][j] = rat(c0 + i, c0 + j) * (in ? 1.0 : 0.0) + ((c0 + j >= n && i == j) ? 1.0 : 0.0);
+  }
+  __syncthreads();
   if (lane < 16) {
     // column j = lane of Tb by back substitution (upper triangular)
     const int j = lane;
@@ -770,11 +788,11 @@ __global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* 
       double t = 0.0;
       if (i <= j && c0 + j < n) {
         if (i == j) {
-          t = 1.0 / R[(c0 + j) + static_cast<int64_t>(c0 + j) * ldr];
+          t = 1.0 / rb[j][j];
         } else {
           double s = 0.0;
-          for (int l = i + 1; l <= j; ++l) s += R[(c0 + i) + static_cast<int64_t>(c0 + l) * ldr] * tb[l][j];
-          t = -s / R[(c0 + i) + static_cast<int64_t>(c0 + i) * ldr];
+          for (int l = i + 1; l <= j; ++l) s += rb[i][l] * tb[l][j];
+          t = -s / rb[i][i];
         }
       }
       tb[i][j] = t;
@@ -784,13 +802,22 @@ __global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* 
   const int nc = (b + 1) / 2;
   unsigned char* base = pan3 + trsm_bf3_panel_offset(b);
   const int col = c0 + l16;
-  for (int p = 0; p < nc; ++p) {
-    uint32_t hp[8], dp[8], lp[8];
+  constexpr int kMaxChunks = (kMaxN / 16 + 1) / 2;
+  double rv[kMaxChunks][8];
+#pragma unroll
+  for (int p = 0; p < kMaxChunks; ++p)
+#pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 32 * p + (e < 4 ? 4 * lg + e : 16 + 4 * lg + (e - 4));
-      const double v = (k < c0 && col < n) ? -R[k + static_cast<int64_t>(col) * ldr] : 0.0;
-      split3_bits(v, hp[e], dp[e], lp[e]);
+      const bool in = p < nc && k < c0 && col < n;
+      const double x = -rat(in ? k : 0, col);
+      rv[p][e] = in ? x : 0.0;
     }
+#pragma unroll
+  for (int p = 0; p < kMaxChunks; ++p) {
+    if (p >= nc) break;
+    uint32_t hp[8], dp[8], lp[8];
+    for (int e = 0; e < 8; ++e) split3_bits(rv[p][e], hp[e], dp[e], lp[e]);
     unsigned char* dst = base + 3072 * p;
     for (int w = 0; w < 4; ++w) {
       reinterpret_cast<uint32_t*>(dst + 16 * lane)[w] = (hp[2 * w] >> 16) | (hp[2 * w + 1] & 0xFFFF0000u);
@@ -807,7 +834,7 @@ __global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* 
       if (part == 0)
         v = tb[i][l16];
       else
-        v = (i <= l16 && c0 + l16 < n) ? -R[(c0 + i) + static_cast<int64_t>(c0 + l16) * ldr] : 0.0;
+        v = (i <= l16 && c0 + l16 < n) ? -rb[i][l16] : 0.0;
       split3_bits(v, hp[e], dp[e], lp[e]);
     }
     unsigned char* dq = dd + 1536 * part;
@@ -823,10 +850,7 @@ __global__ __launch_bounds__(64) void make_trsm_bf3_panels_kernel(const double* 
     double rs = 0.0;
     for (int j = i; j < 16; ++j) {
       double t = 0.0;
-      for (int l = i; l <= j; ++l) {
-        const double r = (c0 + j < n) ? fabs(R[(c0 + l) + static_cast<int64_t>(c0 + j) * ldr]) : (l == j ? 1.0 : 0.0);
-        t += fabs(tb[i][l]) * r;
-      }
+      for (int l = i; l <= j; ++l) t += fabs(tb[i][l]) * fabs(rb[l][j]);
       rs += t;
     }
     amp[i] = rs;
