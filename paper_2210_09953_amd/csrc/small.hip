@@ -24,9 +24,8 @@ namespace rcq {
 // the waves right of j apply reflector j (read from LDS) to their column,
 // and wave j + 1 then forms reflector j + 1 from its updated column and
 // publishes it in LDS: one barrier per reflector.  The wave that forms the
-// next reflector raises its issue priority for the step and the others wait
-// briefly before reading the reflector, as their updates are off the
-// critical path.  Reflector j sits at vsh[j Ls + r] for
+// next reflector raises its issue priority for the step, as the others'
+// updates are off the critical path.  Reflector j sits at vsh[j Ls + r] for
 // all 64 RPL rows (zero from row L on, so no reads are guarded), with the
 // stride Ls = 4 (mod 32) doubles so that the 16 reflectors' entries of one
 // row fall in distinct banks for the V^T V step.
@@ -80,10 +79,7 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ A, 
   for (int j = 0; j < nbp; ++j) {
     if (wave > j && own) {
       const bool next = wave == j + 1;
-      if (next)
-        __builtin_amdgcn_s_setprio(2);
-      else
-        __builtin_amdgcn_s_sleep(2);  // its reads of reflector j go first
+      if (next) __builtin_amdgcn_s_setprio(2);
       const double* vj = vsh + j * Ls;
       double wq[4] = {0.0, 0.0, 0.0, 0.0};
       double vr[RPL];
