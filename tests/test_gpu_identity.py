@@ -63,3 +63,26 @@ def test_identity_kind_argument_rules(rq):
     assert rq.workspace_bytes(500, 40, 499, rq.IDENTITY_TESTONLY, 1, rq.F64) == 0
     assert rq.workspace_bytes(500, 40, 500, rq.IDENTITY_TESTONLY, 1, rq.MIXED) == 0
     assert rq.workspace_bytes(500, 40, 500, rq.IDENTITY_TESTONLY, 1, rq.F64) > 0
+
+
+@pytest.mark.parametrize("m,n", [(1024, 200), (777, 33), (256, 256)])
+def test_identity_kind_forms_s_as_lapack_q(rq, orc, m, n):
+    """With Theta = I the sketch is X itself, so S = (H_1 ... H_n)[I; 0] D of
+    Algorithm 2's QR of P is LAPACK's thin Q of X with a positive diagonal R.
+    m = 1024 runs the blocked update on four 16-row tiles per wave; n = 200
+    and 33 leave a part-filled last panel."""
+    import torch
+    X = synth.make_x(m, n, 1e-3, seed=3 * m + n)
+    Xg = rq.fortran(torch.from_numpy(np.asfortranarray(X)).cuda())
+    Q, R, ex = rq.factor(Xg, m, 0, rq.IDENTITY_TESTONLY, passes=1, precision=rq.F64,
+                         want_s=True, want_factors=True)
+    torch.cuda.synchronize()
+    assert rq.status(ex["ws"]) == 0
+    S = ex["S"].cpu().numpy()
+    Ql, Rl = _lapack_qr(X)
+    dS = np.linalg.norm(S - Ql) / np.linalg.norm(Ql)
+    orth = np.linalg.norm(S.T @ S - np.eye(n), 2)
+    print(f"identity S m={m} n={n}: |dS|/|S| vs LAPACK {dS:.2e}, ||S^T S - I|| {orth:.2e}")
+    assert S.shape == (m, n)
+    assert dS <= 1e-11            # Q's forward error ~ u kappa sqrt(n), kappa = 1e3
+    assert orth <= 1e-13
